@@ -1,0 +1,148 @@
+/*
+ * sapdd.h - C ABI of the MI355X (gfx950) Schwarz-preconditioned Wilson-clover solver.
+ *
+ * The library implements the domain-decomposition solver summarised in arxiv 1502.04025,
+ * Sec. 3.1: the Wilson-clover Dirac operator M, the multiplicative Schwarz (Schwarz
+ * alternating procedure, SAP) preconditioner over red/black coloured blocks with each
+ * block solved approximately by minimal-residual (MR) iterations on its even-odd reduced
+ * operator, and an outer flexible GMRES (FGMRES) in double precision. The data-layout
+ * (structure of arrays, Sec. 3.2) and half-precision storage (Sec. 3.3) choices of the
+ * paper are re-made for the GPU: a block-tiled even-odd SoA layout in HBM and optional
+ * FP16 storage with one FP32 scale per site.
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ * Lattice dims[4] = {Lx, Ly, Lz, Lt}; sites are ordered x fastest, then y, z, t.
+ * Boundary conditions: periodic in x, y, z; antiperiodic in t when antiperiodic_t != 0.
+ * Dirac basis: DeGrand-Rossi (chiral, gamma_5 = diag(1, 1, -1, -1)).
+ * Operator (kappa normalisation):
+ *   (M psi)(x) = (1 + kappa T(x)) psi(x)
+ *       - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * with the sign -1 on hops across the time boundary (antiperiodic t) and the clover term
+ * T(x) = -c_sw sum_{mu<nu} gamma_mu gamma_nu (x) F_mu,nu(x), F = (Q - Q^+)/8 made traceless,
+ * Q the sum of the four plaquettes in the (mu, nu) plane based at x.
+ *
+ * Canonical host/device arrays (all IEEE double, complex numbers interleaved re, im):
+ *   links   [t][z][y][x][mu][3][3] complex   (mu = 0..3 for x, y, z, t; U[a][b], row a)
+ *   spinor  [rhs][t][z][y][x][4][3] complex  (spin, colour)
+ *   clover  [t][z][y][x][12][12] complex     (T(x), row/column index 3*spin + colour)
+ *
+ * Pointers are host memory unless SAPDD_DEVICE_PTRS is set in `flags`, in which case they
+ * are device memory of the context's device (for instance torch tensor data pointers).
+ * Caller buffers stay owned by the caller. Fields are copied into library-owned device
+ * memory on load and released by sapdd_free_field. Every call is synchronous with respect
+ * to the context's stream: it enqueues its work on that stream and waits for it before
+ * returning.
+ *
+ * Errors: every int-returning call returns SAPDD_OK (0) or a negative status; the message
+ * of the last failure on a context is available from sapdd_last_error. Nothing throws or
+ * aborts across the ABI. One context must not be used from two host threads at once.
+ */
+#ifndef SAPDD_H
+#define SAPDD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sapdd_ctx sapdd_ctx;     /* device, stream, workspaces, last error      */
+typedef struct sapdd_field sapdd_field; /* one resident gauge field and its clover term */
+
+enum {
+    SAPDD_OK = 0,
+    SAPDD_EINVAL = -1,    /* bad argument or unsupported shape                      */
+    SAPDD_ENOMEM = -2,    /* device allocation failed                               */
+    SAPDD_EDEVICE = -3,   /* HIP runtime error                                      */
+    SAPDD_ENOCONV = -4,   /* solver hit max_iter; x and stats hold the best iterate */
+    SAPDD_ESINGULAR = -5, /* a clover block 1 + kappa T is singular (pivot < 1e-12) */
+    SAPDD_ENAN = -6       /* NaN or Inf in a residual                               */
+};
+
+enum { SAPDD_F64 = 0, SAPDD_F32 = 1, SAPDD_F16 = 2 }; /* storage precisions */
+
+enum {
+    SAPDD_DEVICE_PTRS = 1, /* array arguments are device pointers              */
+    SAPDD_USE_X0 = 2,      /* sapdd_solve starts from the x passed in, not 0    */
+    SAPDD_NO_GRAPH = 4     /* sapdd_solve launches the SAP sweep without a graph */
+};
+
+/* Solver parameters (Sec. 3.1 names the pieces; Sec. 3.7 uses 4-5 MR iterations and
+ * 16 Schwarz cycles). block[] must equal the blocking the field was loaded with or be
+ * all zero (use the field's). */
+typedef struct {
+    int block[4];   /* Schwarz block extents Bx, By, Bz, Bt                         */
+    int nmr;        /* MR iterations per block solve (>= 1)                        */
+    int ncy;        /* SAP cycles, each = colour 0 then colour 1 (>= 1)            */
+    int restart;    /* FGMRES restart length m (1..16)                             */
+    int max_iter;   /* cap on outer iterations (preconditioner applications)       */
+    double tol;     /* target true relative residual |b - M x| / |b|               */
+    int sap_prec;   /* storage precision inside SAP: SAPDD_F64, SAPDD_F32, SAPDD_F16 */
+    int flags;      /* SAPDD_DEVICE_PTRS | SAPDD_USE_X0 | SAPDD_NO_GRAPH          */
+} sapdd_params;
+
+/* Per right-hand-side result of sapdd_solve. Times are seconds of device time
+ * (HIP events) spent in each phase, summed over the solve; a batched solve attributes
+ * the whole batch's phase time to every RHS in it. */
+typedef struct {
+    int iters;              /* outer iterations (preconditioner applications)        */
+    int restarts;           /* completed restart cycles                              */
+    int converged;          /* 1 if true_relres <= tol                               */
+    double true_relres;     /* |b - M x| / |b| recomputed in FP64 at the end         */
+    double implicit_relres; /* least-squares residual estimate at the last step      */
+    double t_total;         /* wall time of the call                                 */
+    double t_sap, t_dslash, t_gs, t_host;
+} sapdd_stats;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream). */
+int sapdd_create(int device, void *hip_stream, sapdd_ctx **out);
+void sapdd_destroy(sapdd_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none). Valid until the next call. */
+const char *sapdd_last_error(const sapdd_ctx *ctx);
+
+/* Upload a gauge field (canonical links) and fix its device layout: the lattice is tiled
+ * by Schwarz blocks of extents block[] (each even and >= 2, dividing dims, with an even
+ * number of blocks per direction so the blocks two-colour the lattice, Sec. 3.5 footnote).
+ * Supported block shapes: 2x2x2x2, 4x4x4x4, 8x4x4x4. The clover term starts at zero. */
+int sapdd_load_gauge(sapdd_ctx *ctx, const int dims[4], const int block[4], const double *links,
+                     int antiperiodic_t, int flags, sapdd_field **out);
+/* Build T(x) on the device from the resident links with coefficient c_sw >= 0. */
+int sapdd_compute_clover(sapdd_ctx *ctx, sapdd_field *field, double csw);
+/* Upload T(x) (canonical clover layout). Only the two chiral 6x6 blocks (spins 0-1 and
+ * 2-3) are used; the entries coupling them must be zero in the Dirac basis above. */
+int sapdd_load_clover(sapdd_ctx *ctx, sapdd_field *field, const double *clover, int flags);
+int sapdd_free_field(sapdd_ctx *ctx, sapdd_field *field);
+
+/* out = M in for nrhs canonical spinors, with links, clover and spinors held in storage
+ * precision `prec` (arithmetic in FP64 for SAPDD_F64, FP32 otherwise). in and out may
+ * not overlap. */
+int sapdd_apply_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec, int nrhs,
+                  const double *in, double *out, int flags);
+/* out = M_B in: M with every hop between two different Schwarz blocks removed (the
+ * block-diagonal part of the splitting in Sec. 3.1), same arguments as sapdd_apply_D. */
+int sapdd_apply_block_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec,
+                        int nrhs, const double *in, double *out, int flags);
+/* out = SAP(in): params->ncy cycles of MR block solves over colour 0 then colour 1,
+ * FP64 canonical in and out, internal storage params->sap_prec. */
+int sapdd_sap(sapdd_ctx *ctx, const sapdd_field *field, double kappa, const sapdd_params *params,
+              int nrhs, const double *in, double *out);
+/* Solve M x = b for nrhs right-hand sides with SAP-preconditioned FGMRES(m) in FP64.
+ * kappa[nrhs] may differ per RHS. x holds nrhs canonical spinors (read as the start
+ * vector if SAPDD_USE_X0). stats may be NULL, else it has nrhs entries. Returns
+ * SAPDD_ENOCONV if some RHS missed tol within max_iter. */
+int sapdd_solve(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa,
+                const sapdd_params *params, int nrhs, const double *b, double *x,
+                sapdd_stats *stats);
+
+/* Bytes of device memory a solve of nrhs RHS with these parameters allocates on top of
+ * the resident field (Krylov bases, SAP state, operator copies), for admission control. */
+long long sapdd_solve_footprint(const sapdd_field *field, const sapdd_params *params, int nrhs);
+
+/* Device copy of n bytes (STREAM-type copy kernel, used to measure the attainable HBM
+ * bandwidth); src and dst are device pointers. */
+int sapdd_copy(sapdd_ctx *ctx, const void *src, void *dst, long long n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAPDD_H */

@@ -1,0 +1,200 @@
+// blas.hip - FP64 vector kernels of the outer flexible GMRES: the classical Gram-Schmidt
+// passes (dot products against the Krylov basis and the matching corrections, fused so
+// each pass streams w and the basis once), deterministic reductions of the partial sums,
+// and the solution update x += Z y.
+//
+// Complex entries in the block-tiled layout keep their real and imaginary parts Vbh
+// doubles apart (component 2k and 2k+1 of the site); entry e = r * Vbh + s of a vector
+// has its real part at 2 r Vbh + s and its imaginary part Vbh further on.
+//
+// Reductions are two-level and in a fixed order: every workgroup writes its partial sum,
+// and a second kernel adds the partial sums in workgroup order, so a result never
+// depends on which other right-hand sides share the launch.
+#include "kernels.hpp"
+
+namespace sapdd {
+
+constexpr int BLAS_WG = 256;
+
+// The workgroup count (and so the summation order) depends on the vector length only,
+// never on how many right-hand sides share the launch.
+int blas_partials(int64_t n, int nact) {
+    (void)nact;
+    int64_t want = (n + 4 * BLAS_WG - 1) / (4 * BLAS_WG);  // about four entries per thread
+    const int cap = 1024;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    return (int)want;
+}
+
+template <int NVAL>
+__device__ __forceinline__ void wg_reduce_store(double (&v)[NVAL], double *out) {
+    __shared__ double red[BLAS_WG / 64][NVAL > 0 ? NVAL : 1];
+#pragma unroll
+    for (int k = 0; k < NVAL; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NVAL; ++k) red[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < NVAL) {
+        double t = 0;
+#pragma unroll
+        for (int q = 0; q < BLAS_WG / 64; ++q) t += red[q][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <int MODE, int NV>
+__global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
+    constexpr int NVAL = MODE == 2 ? 1 : 2 * NV;
+    const int slot = blockIdx.y;
+    const int rhs = a.active[slot];
+    const double *v = a.vbase + rhs * a.rstride + (int64_t)a.v0 * a.vstride;
+    const int64_t vs = a.vstride;
+    double *w = a.w + rhs * a.wstride;
+    const int sh = a.vbh_shift;
+    const int64_t vbh = (int64_t)1 << sh;
+    double cr[NV > 0 ? NV : 1], ci[NV > 0 ? NV : 1];
+    if (MODE >= 1) {
+        const double *c = a.coef + (int64_t)rhs * a.cstride;
+        const double *sc = a.vscale + (int64_t)rhs * a.vsstride;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double s = sc[a.v0 + i];
+            cr[i] = c[2 * (a.v0 + i)] * s;
+            ci[i] = c[2 * (a.v0 + i) + 1] * s;
+        }
+    }
+    double acc[NVAL];
+#pragma unroll
+    for (int k = 0; k < NVAL; ++k) acc[k] = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
+    for (int64_t e = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; e < a.n; e += stride) {
+        const int64_t re = e + ((e >> sh) << sh), im = re + vbh;
+        double2 vv[NV > 0 ? NV : 1];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vv[i] = make_double2(v[i * vs + re], v[i * vs + im]);
+        double2 ww = make_double2(w[re], w[im]);
+        if (MODE >= 1 && NV > 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                ww.x -= cr[i] * vv[i].x - ci[i] * vv[i].y;
+                ww.y -= cr[i] * vv[i].y + ci[i] * vv[i].x;
+            }
+            w[re] = ww.x;
+            w[im] = ww.y;
+        }
+        if (MODE <= 1) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {  // conj(v) w
+                acc[2 * i] += vv[i].x * ww.x + vv[i].y * ww.y;
+                acc[2 * i + 1] += vv[i].x * ww.y - vv[i].y * ww.x;
+            }
+        } else {
+            acc[0] += ww.x * ww.x + ww.y * ww.y;
+        }
+    }
+    wg_reduce_store<NVAL>(acc, a.part + ((int64_t)slot * gridDim.x + blockIdx.x) * NVAL);
+}
+
+template <int MODE, int NV>
+static hipError_t cgs_launch(const CgsArgs &a, hipStream_t st) {
+    const int nwg = blas_partials(a.n, a.nact);
+    hipLaunchKernelGGL((cgs_kernel<MODE, NV>), dim3(nwg, a.nact), dim3(BLAS_WG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t cgs_mode(const CgsArgs &a, hipStream_t st) {
+    if (MODE == 2 && a.nv == 0) return cgs_launch<2, 0>(a, st);  // plain |w|^2
+    switch (a.nv) {
+#define C(N) case N: return cgs_launch<MODE, N>(a, st);
+        C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14) C(15) C(16)
+#undef C
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st) {
+    if (a.nact <= 0) return hipSuccess;
+    if (mode == 0) return cgs_mode<0>(a, st);
+    if (mode == 1) return cgs_mode<1>(a, st);
+    if (mode == 2) return cgs_mode<2>(a, st);
+    return hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(BLAS_WG) void reduce_kernel(const double *part, int nwg, int nval, const int *active,
+                                                         double *out, int ostride, const double *mul, int mstride,
+                                                         int v0, double *isq, int istride) {
+    __shared__ double red[BLAS_WG / 64];
+    const int slot = blockIdx.x;
+    const int rhs = active[slot];
+    const double *p = part + (int64_t)slot * nwg * nval;
+    for (int k = 0; k < nval; ++k) {
+        double t = 0;
+        for (int q = threadIdx.x; q < nwg; q += BLAS_WG) t += p[(int64_t)q * nval + k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0;
+            for (int q = 0; q < BLAS_WG / 64; ++q) s += red[q];
+            if (mul) s *= mul[(int64_t)rhs * mstride + v0 + k / 2];
+            out[(int64_t)rhs * ostride + k] = s;
+            if (isq && k == 0) isq[(int64_t)rhs * istride] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
+                         int ostride, const double *mul, int mstride, int v0, double *isq, int istride,
+                         hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(nact), dim3(BLAS_WG), 0, st, part, nwg, nval, active, out, ostride, mul,
+                       mstride, v0, isq, istride);
+    return hipGetLastError();
+}
+
+template <class Z>
+__global__ __launch_bounds__(BLAS_WG) void zupdate_kernel(double *x, int64_t xstride, const Z *z, int64_t zsj,
+                                                          int64_t zsr, const double *y, int ystride, int nz,
+                                                          const int *active, int64_t n, int sh) {
+    const int rhs = active[blockIdx.y];
+    double *xr = x + rhs * xstride;
+    const Z *zr = z + rhs * zsr;
+    const double *yr = y + (int64_t)rhs * ystride;
+    const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
+    for (int64_t e = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; e < n; e += stride) {
+        const int64_t ire = e + ((e >> sh) << sh), iim = ire + ((int64_t)1 << sh);
+        double re = xr[ire], im = xr[iim];
+        for (int j = 0; j < nz; ++j) {
+            const double zr_ = (double)zr[j * zsj + ire], zi_ = (double)zr[j * zsj + iim];
+            re += yr[2 * j] * zr_ - yr[2 * j + 1] * zi_;
+            im += yr[2 * j] * zi_ + yr[2 * j + 1] * zr_;
+        }
+        xr[ire] = re;
+        xr[iim] = im;
+    }
+}
+
+hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, int64_t zstride_j,
+                          int64_t zstride_rhs, const double *y, int ystride, int nz, const int *active, int nact,
+                          int64_t n, int vbh_shift, hipStream_t st) {
+    if (nact <= 0 || nz <= 0) return hipSuccess;
+    const int nwg = blas_partials(n, nact);
+    if (zprec == P64)
+        hipLaunchKernelGGL((zupdate_kernel<double>), dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride,
+                           (const double *)z, zstride_j, zstride_rhs, y, ystride, nz, active, n, vbh_shift);
+    else if (zprec == P32)
+        hipLaunchKernelGGL((zupdate_kernel<float>), dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride,
+                           (const float *)z, zstride_j, zstride_rhs, y, ystride, nz, active, n, vbh_shift);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace sapdd

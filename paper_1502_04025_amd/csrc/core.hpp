@@ -1,0 +1,335 @@
+// core.hpp - device-side building blocks shared by the sapdd kernels.
+//
+// * Block-tiled even-odd structure-of-arrays layout (the GPU re-make of the SoA layout
+//   of Sec. 3.2): for a field with `ncomp` reals per site, real k of the site with
+//   parity p and half-site index s in Schwarz block b lives at
+//       ((b * 2 + p) * ncomp + k) * Vbh + s,      Vbh = (sites per block) / 2.
+//   Lanes map to consecutive s, so every component is one coalesced run per block.
+//   In FP16 storage every site also carries one FP32 scale at (b * 2 + p) * Vbh + s.
+// * Spinor reals: index 2 * (3 * spin + colour) + (0 re, 1 im), 24 per site.
+//   Links: 4 directions x 18 reals, index 18 * mu + 2 * (3 * row + col) + re/im.
+//   Clover (two chiral 6x6 Hermitian blocks): 36 reals per block, first the 6 real
+//   diagonal entries, then the 15 upper off-diagonal entries (i < j, row major) as
+//   complex pairs; block k covers spins 2k, 2k+1 and element index 3 * (spin - 2k) + c.
+// * DeGrand-Rossi gamma matrices: gamma_mu = [[0, G_mu], [G_mu^+, 0]] with
+//   G_x = i sigma_x, G_y = -i sigma_y, G_z = i sigma_z, G_t = 1. Every row of G_mu holds
+//   one entry, a power of i, which the projections below apply as add/sub/swap.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sapdd {
+
+typedef _Float16 half_t;
+
+// ------------------------------------------------------------------ storage traits
+template <class S> struct Storage;
+template <> struct Storage<double> {
+    static constexpr bool scaled = false;
+    static constexpr int bytes = 8;
+};
+template <> struct Storage<float> {
+    static constexpr bool scaled = false;
+    static constexpr int bytes = 4;
+};
+template <> struct Storage<half_t> {
+    static constexpr bool scaled = true;
+    static constexpr int bytes = 2;
+};
+
+// A field in the block-tiled layout: data plus (FP16 only) per-site scales.
+template <class S> struct FieldPtr {
+    S *data;
+    float *scale;
+};
+template <class S> struct CFieldPtr {
+    const S *data;
+    const float *scale;
+};
+
+template <class R, int N, class S>
+__device__ __forceinline__ void load_site(const S *__restrict__ data, const float *__restrict__ scale,
+                                          int64_t bp, int s, int Vbh, R out[N]) {
+    const S *p = data + bp * (int64_t)N * Vbh + s;
+    if constexpr (Storage<S>::scaled) {
+        const R sc = (R)scale[bp * Vbh + s];
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[k] = (R)(float)p[(int64_t)k * Vbh] * sc;
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[k] = (R)p[(int64_t)k * Vbh];
+    }
+}
+
+// Store N reals of one site; FP16 storage divides by the site's max |value| and rounds
+// to nearest even (scale 0 stores zeros).
+template <class R, int N, class S>
+__device__ __forceinline__ void store_site(S *__restrict__ data, float *__restrict__ scale, int64_t bp,
+                                           int s, int Vbh, const R in[N]) {
+    S *p = data + bp * (int64_t)N * Vbh + s;
+    if constexpr (Storage<S>::scaled) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < N; ++k) m = fmaxf(m, fabsf((float)in[k]));
+        scale[bp * Vbh + s] = m;
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+        for (int k = 0; k < N; ++k) p[(int64_t)k * Vbh] = (half_t)((float)in[k] * inv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) p[(int64_t)k * Vbh] = (S)in[k];
+    }
+}
+
+// ------------------------------------------------------------------ gamma structure
+// Multiply (re, im) by i^ph.
+template <int PH, class R> __device__ __forceinline__ void iph(R re, R im, R &ore, R &oim) {
+    if constexpr (PH == 0) { ore = re; oim = im; }
+    else if constexpr (PH == 1) { ore = -im; oim = re; }
+    else if constexpr (PH == 2) { ore = -re; oim = -im; }
+    else { ore = im; oim = -re; }
+}
+
+// Row r of G_mu: column and phase exponent (entry = i^phase).
+template <int MU, int ROW> struct Grow;
+template <> struct Grow<0, 0> { static constexpr int col = 1, ph = 1; };
+template <> struct Grow<0, 1> { static constexpr int col = 0, ph = 1; };
+template <> struct Grow<1, 0> { static constexpr int col = 1, ph = 2; };
+template <> struct Grow<1, 1> { static constexpr int col = 0, ph = 0; };
+template <> struct Grow<2, 0> { static constexpr int col = 0, ph = 1; };
+template <> struct Grow<2, 1> { static constexpr int col = 1, ph = 3; };
+template <> struct Grow<3, 0> { static constexpr int col = 0, ph = 0; };
+template <> struct Grow<3, 1> { static constexpr int col = 1, ph = 0; };
+// Row r of G_mu^+.
+template <int MU, int ROW> struct GDrow;
+template <> struct GDrow<0, 0> { static constexpr int col = 1, ph = 3; };
+template <> struct GDrow<0, 1> { static constexpr int col = 0, ph = 3; };
+template <> struct GDrow<1, 0> { static constexpr int col = 1, ph = 0; };
+template <> struct GDrow<1, 1> { static constexpr int col = 0, ph = 2; };
+template <> struct GDrow<2, 0> { static constexpr int col = 0, ph = 3; };
+template <> struct GDrow<2, 1> { static constexpr int col = 1, ph = 1; };
+template <> struct GDrow<3, 0> { static constexpr int col = 0, ph = 0; };
+template <> struct GDrow<3, 1> { static constexpr int col = 1, ph = 0; };
+
+// Project a spinor with (1 - SIGN*gamma_mu)... expressed through its upper half:
+//   (1 - gamma) psi: h = psi_up - G psi_lo,  lower part = -G^+ h
+//   (1 + gamma) psi: h = psi_up + G psi_lo,  lower part = +G^+ h
+// SIGN = -1 for (1 - gamma_mu), +1 for (1 + gamma_mu). h has 12 reals (2 spins x 3 colours).
+template <int MU, int SIGN, class R>
+__device__ __forceinline__ void project(const R psi[24], R h[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        {
+            constexpr int col = Grow<MU, 0>::col, ph = Grow<MU, 0>::ph;
+            R re, im;
+            iph<ph>(psi[2 * (3 * (2 + col) + c)], psi[2 * (3 * (2 + col) + c) + 1], re, im);
+            h[2 * c] = psi[2 * c] + (R)SIGN * re;
+            h[2 * c + 1] = psi[2 * c + 1] + (R)SIGN * im;
+        }
+        {
+            constexpr int col = Grow<MU, 1>::col, ph = Grow<MU, 1>::ph;
+            R re, im;
+            iph<ph>(psi[2 * (3 * (2 + col) + c)], psi[2 * (3 * (2 + col) + c) + 1], re, im);
+            h[2 * (3 + c)] = psi[2 * (3 + c)] + (R)SIGN * re;
+            h[2 * (3 + c) + 1] = psi[2 * (3 + c) + 1] + (R)SIGN * im;
+        }
+    }
+}
+
+// acc += scale * reconstruct(h) where reconstruct puts h in the upper spins and
+// SIGN * G^+ h in the lower spins.
+template <int MU, int SIGN, class R>
+__device__ __forceinline__ void accum_recon(R acc[24], const R h[12], R scale) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += scale * h[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        {
+            constexpr int col = GDrow<MU, 0>::col, ph = GDrow<MU, 0>::ph;
+            R re, im;
+            iph<ph>(h[2 * (3 * col + c)], h[2 * (3 * col + c) + 1], re, im);
+            acc[2 * (6 + c)] += (R)SIGN * scale * re;
+            acc[2 * (6 + c) + 1] += (R)SIGN * scale * im;
+        }
+        {
+            constexpr int col = GDrow<MU, 1>::col, ph = GDrow<MU, 1>::ph;
+            R re, im;
+            iph<ph>(h[2 * (3 * col + c)], h[2 * (3 * col + c) + 1], re, im);
+            acc[2 * (9 + c)] += (R)SIGN * scale * re;
+            acc[2 * (9 + c) + 1] += (R)SIGN * scale * im;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ SU(3) on half spinors
+// out = U h for both spins; U has 18 reals, row major complex.
+template <class R> __device__ __forceinline__ void su3_mul(const R u[18], const R h[12], R out[12]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const R ur = u[2 * (3 * a + b)], ui = u[2 * (3 * a + b) + 1];
+                const R hr = h[2 * (3 * sp + b)], hi = h[2 * (3 * sp + b) + 1];
+                re += ur * hr - ui * hi;
+                im += ur * hi + ui * hr;
+            }
+            out[2 * (3 * sp + a)] = re;
+            out[2 * (3 * sp + a) + 1] = im;
+        }
+}
+
+// out = U^+ h for both spins.
+template <class R> __device__ __forceinline__ void su3_dag_mul(const R u[18], const R h[12], R out[12]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const R ur = u[2 * (3 * b + a)], ui = u[2 * (3 * b + a) + 1];
+                const R hr = h[2 * (3 * sp + b)], hi = h[2 * (3 * sp + b) + 1];
+                re += ur * hr + ui * hi;
+                im += ur * hi - ui * hr;
+            }
+            out[2 * (3 * sp + a)] = re;
+            out[2 * (3 * sp + a) + 1] = im;
+        }
+}
+
+// ------------------------------------------------------------------ clover
+// out = in + X in, X two packed Hermitian 6x6 blocks (72 reals).
+template <class R> __device__ __forceinline__ void clover_apply(const R x[72], const R in[24], R out[24]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const R *d = x + 36 * k;
+        const R *v = in + 12 * k;
+        R *o = out + 12 * k;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            R re = v[2 * i] + d[i] * v[2 * i];
+            R im = v[2 * i + 1] + d[i] * v[2 * i + 1];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (j == i) continue;
+                const int a = i < j ? i : j, b = i < j ? j : i;
+                const int idx = a * 5 - a * (a - 1) / 2 + (b - a - 1);  // position of (a,b), a<b
+                const R xr = d[6 + 2 * idx];
+                const R xi = (i < j) ? d[6 + 2 * idx + 1] : -d[6 + 2 * idx + 1];
+                re += xr * v[2 * j] - xi * v[2 * j + 1];
+                im += xr * v[2 * j + 1] + xi * v[2 * j];
+            }
+            o[2 * i] = re;
+            o[2 * i + 1] = im;
+        }
+    }
+}
+
+// out = kappa * X in (no identity part).
+template <class R>
+__device__ __forceinline__ void clover_apply_k(const R x[72], const R in[24], R kappa, R out[24]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const R *d = x + 36 * k;
+        const R *v = in + 12 * k;
+        R *o = out + 12 * k;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            R re = d[i] * v[2 * i];
+            R im = d[i] * v[2 * i + 1];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (j == i) continue;
+                const int a = i < j ? i : j, b = i < j ? j : i;
+                const int idx = a * 5 - a * (a - 1) / 2 + (b - a - 1);
+                const R xr = d[6 + 2 * idx];
+                const R xi = (i < j) ? d[6 + 2 * idx + 1] : -d[6 + 2 * idx + 1];
+                re += xr * v[2 * j] - xi * v[2 * j + 1];
+                im += xr * v[2 * j + 1] + xi * v[2 * j];
+            }
+            o[2 * i] = kappa * re;
+            o[2 * i + 1] = kappa * im;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];  // lattice extents x, y, z, t
+    int B[4];  // Schwarz block extents
+    int G[4];  // block grid extents L / B
+    int Vb, Vbh;
+    int64_t Nd, V;
+    int antiperiodic;
+};
+
+// Local coordinates of half-site s with parity p in a block of extents B.
+__host__ __device__ __forceinline__ void local_coords(const int B[4], int p, int s, int l[4]) {
+    const int hx = B[0] >> 1;
+    int r = s / hx;
+    const int xh = s - r * hx;
+    l[1] = r % B[1];
+    r /= B[1];
+    l[2] = r % B[2];
+    l[3] = r / B[2];
+    const int q = (p + l[1] + l[2] + l[3]) & 1;
+    l[0] = 2 * xh + q;
+}
+
+__host__ __device__ __forceinline__ int local_half_index(const int B[4], const int l[4]) {
+    return (l[0] + B[0] * (l[1] + B[1] * (l[2] + B[2] * l[3]))) >> 1;
+}
+
+__host__ __device__ __forceinline__ void block_coords(const int G[4], int64_t b, int g[4]) {
+    g[0] = (int)(b % G[0]);
+    b /= G[0];
+    g[1] = (int)(b % G[1]);
+    b /= G[1];
+    g[2] = (int)(b % G[2]);
+    g[3] = (int)(b / G[2]);
+}
+
+__host__ __device__ __forceinline__ int64_t block_index(const int G[4], const int g[4]) {
+    return ((int64_t)(g[3] * G[2] + g[2]) * G[1] + g[1]) * G[0] + g[0];
+}
+
+// Site address (bp = 2 b + p, s) of global coordinates x[4].
+__host__ __device__ __forceinline__ void site_of(const Geom &geo, const int x[4], int64_t &bp, int &s) {
+    int g[4], l[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        g[mu] = x[mu] / geo.B[mu];
+        l[mu] = x[mu] - g[mu] * geo.B[mu];
+    }
+    const int p = (l[0] + l[1] + l[2] + l[3]) & 1;
+    bp = block_index(geo.G, g) * 2 + p;
+    s = local_half_index(geo.B, l);
+}
+
+// Global coordinates of site (bp, s).
+__host__ __device__ __forceinline__ void coords_of(const Geom &geo, int64_t bp, int s, int x[4]) {
+    int g[4], l[4];
+    block_coords(geo.G, bp >> 1, g);
+    local_coords(geo.B, (int)(bp & 1), s, l);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) x[mu] = g[mu] * geo.B[mu] + l[mu];
+}
+
+// b-th block (in colour order) of colour c: blocks of one colour are enumerated row by
+// row along x; every x row of the (even-sized) block grid holds G_x / 2 of them.
+__host__ __device__ __forceinline__ int64_t colour_block(const int G[4], int c, int64_t k) {
+    const int hg = G[0] >> 1;
+    const int64_t row = k / hg;
+    const int j = (int)(k - row * hg);
+    const int gy = (int)(row % G[1]);
+    const int64_t r2 = row / G[1];
+    const int gz = (int)(r2 % G[2]);
+    const int gt = (int)(r2 / G[2]);
+    const int gx = 2 * j + ((c + gy + gz + gt) & 1);
+    return ((int64_t)(gt * G[2] + gz) * G[1] + gy) * G[0] + gx;
+}
+
+}  // namespace sapdd

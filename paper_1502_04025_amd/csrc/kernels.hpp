@@ -1,0 +1,123 @@
+// kernels.hpp - host-side launchers of the sapdd device kernels (one declaration per
+// kernel family). All launchers enqueue on `stream` and return the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "core.hpp"
+
+namespace sapdd {
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Untyped view of a block-tiled field: data in `prec` plus per-site scales (FP16 only).
+struct Fld {
+    void *data;
+    float *scale;
+    int prec;
+};
+
+// ---- layout (layout.hip)
+// Canonical FP64 array (ncomp = 24 spinor, 72 links) -> block-tiled field, nfield copies
+// (per-field strides V * ncomp / V).
+hipError_t launch_pack(const Geom &geo, int ncomp, int nfield, const double *canon, Fld out, hipStream_t st);
+hipError_t launch_unpack(const Geom &geo, int ncomp, int nfield, Fld in, double *canon, hipStream_t st);
+// Block-tiled FP64 field -> another storage precision (same layout).
+hipError_t launch_convert(const Geom &geo, int ncomp, int nfield, const double *in, Fld out, hipStream_t st);
+// dst[i] = src[i] for n bytes (16-byte vector copies plus a tail).
+hipError_t launch_copy(const void *src, void *dst, int64_t n, hipStream_t st);
+
+// ---- clover (clover.hip)
+// T(x) from the block-tiled FP64 links (periodic closure of every plaquette).
+hipError_t launch_clover_build(const Geom &geo, const double *links, double csw, double *tclov, hipStream_t st);
+// T(x) from the canonical 12x12 complex form.
+hipError_t launch_clover_pack(const Geom &geo, const double *canon, double *tclov, hipStream_t st);
+// X for the SAP kernels: kappa T on even sites, (1 + kappa T)^-1 - 1 on odd sites,
+// written in out.prec. Sets *singular (device int) to 1 if a pivot falls below 1e-12.
+hipError_t launch_sap_clover(const Geom &geo, const double *tclov, double kappa, Fld out, int *singular,
+                             hipStream_t st);
+
+// ---- operators (dslash.hip)
+struct DslashIO {
+    Fld in;            // spinor of rhs r at in + r * in_stride * V * 24 (scales: * V)
+    Fld out;           // idem with out_stride
+    const double *sub; // if set (FP64 out only): out = sub - M in, rhs stride sub_stride
+    double *part;      // if set: per-workgroup partial |out|^2, [nact][dslash_full_partials]
+    const int *active; // if set: rhs index of each of the nact slots
+    int nact;
+    int in_stride, out_stride, sub_stride;  // in units of one spinor field
+    const double *kappa;                    // if set: per-rhs kappa (device), else the scalar
+};
+// Number of partial sums launch_dslash_full writes per RHS slot.
+int dslash_full_partials(const Geom &geo);
+// out = M in over the whole lattice. links/clov in `lprec` (FP64: links + T in FP64).
+hipError_t launch_dslash_full(const Geom &geo, Fld links, Fld tclov, double kappa, const DslashIO &io,
+                              hipStream_t st);
+// out = M_B in (hops between blocks dropped), one workgroup per (block, rhs).
+hipError_t launch_dslash_block(const Geom &geo, Fld links, Fld tclov, double kappa, Fld in, Fld out, int nrhs,
+                               hipStream_t st);
+
+// ---- Schwarz sweep (sap.hip)
+struct SapArgsHost {
+    Fld links;                // storage-precision links
+    const void *const *X;     // per-rhs clover X (device array of nrhs pointers)
+    const float *const *Xsc;  // per-rhs clover scales (FP16) or null
+    const double *kappa;      // per-rhs kappa (device)
+    const double *eta;        // FP64 block-tiled input, stride V * 24 per rhs
+    const double *eta_scale;  // factor applied to eta of rhs r: eta_scale[r * eta_scale_stride], or null
+    int eta_scale_stride;
+    int eta_stride_rhs;       // in units of V * 24 doubles
+    Fld rres;                 // even-site residual, stride V * 12 per rhs (scales V / 2)
+    Fld delta;                // last correction, stride V * 24 per rhs
+    void *psi;                // output, P32 or P64 per psi_prec, stride V * 24 per rhs
+    int psi_prec;
+    int psi_stride_rhs;       // in units of V * 24
+    const int *active;        // slot -> rhs
+    int nact;
+    int nmr;
+};
+// One half-sweep over the blocks of `colour`. mode 0: rho = eta; mode 1: rho = eta +
+// gather; mode 2: rho = stored residual + gather. write_state = 0 skips storing the
+// residual and correction (last half-sweep).
+hipError_t launch_sap_half(const Geom &geo, const SapArgsHost &a, int colour, int mode, int write_state,
+                           hipStream_t st);
+
+// ---- FP64 Krylov kernels (blas.hip)
+// Vectors are complex FP64 in the block-tiled layout, n = 12 V complex entries each. For the
+// rhs of slot q: basis vector i at vbase + rhs * rstride + i * vstride (doubles), stored
+// unnormalised with the factor vscale[rhs * vsstride + i]; w at w + rhs * wstride.
+struct CgsArgs {
+    const double *vbase;
+    int64_t vstride, rstride;
+    const double *vscale;
+    int vsstride;
+    double *w;
+    int64_t wstride;
+    const double *coef;  // complex coefficients of rhs r at coef + r * cstride (modes 1, 2)
+    int cstride;
+    double *part;        // partial sums [nact][blas_partials][nval]
+    const int *active;
+    int nact;
+    int v0, nv;          // basis vectors v0 .. v0 + nv - 1 (nv <= 16)
+    int64_t n;
+    int vbh_shift;       // log2 of the half-block size Vbh
+};
+// Workgroups per rhs slot used by the Gram-Schmidt passes.
+int blas_partials(int64_t n, int nact);
+// mode 0: partial <v_i, w>; mode 1: w -= sum_i coef_i s_i v_i, then partial <v_i, w>;
+// mode 2: w -= sum_i coef_i s_i v_i, then partial |w|^2. Coefficient i of the pass is
+// coef[2 (v0 + i)] (re, im).
+hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st);
+// For every slot: v_k = sum over wg of part[slot][wg][k] (fixed order), times
+// mul[rhs * mstride + v0 + k / 2] if mul is set; written to out[rhs * ostride + k].
+// If isq is set, isq[rhs * istride] = 1 / sqrt(v_0) (0 if v_0 <= 0).
+hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
+                         int ostride, const double *mul, int mstride, int v0, double *isq, int istride,
+                         hipStream_t st);
+// x[rhs] += sum_j y[rhs][j] z_j[rhs]: y complex at y + rhs * ystride, z in P32 or P64 at
+// z + (rhs * zstride_rhs + j * zstride_j) elements.
+hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, int64_t zstride_j,
+                          int64_t zstride_rhs, const double *y, int ystride, int nz, const int *active, int nact,
+                          int64_t n, int vbh_shift, hipStream_t st);
+
+}  // namespace sapdd

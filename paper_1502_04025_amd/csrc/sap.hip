@@ -1,0 +1,296 @@
+// sap.hip - one colour half-sweep of the Schwarz alternating procedure (Sec. 3.1): for
+// every block B of one colour, in parallel, one workgroup
+//   1. forms the block residual rho_B: the stored even-site MR residual of B's previous
+//      solve (odd sites: 0), or the input eta on the first cycle, plus the change the
+//      other colour's last corrections made to it - a gather of the hops from the
+//      neighbouring blocks' corrections delta into B's boundary sites;
+//   2. solves M_B delta = rho_B approximately with even-odd preconditioning:
+//      bhat_e = rho_e - K_eo A_o^-1 rho_o, nmr minimal-residual steps on
+//      Dhat = A_e - K_eo A_o^-1 K_oe from zero, delta_o = A_o^-1 (rho_o - K_oe delta_e),
+//      with K = -kappa * (in-block hopping);
+//   3. adds delta to psi and keeps delta and the new even-site residual for the next
+//      half-sweep.
+// The block never leaves the workgroup during the MR iterations: spinors live in
+// registers and LDS, the in-block hops go through LDS (block_hop) and the MR inner
+// products are wave-shuffle plus LDS reductions in a fixed order (so results do not
+// depend on scheduling). Blocks of one colour share no site and no hop, so the gather
+// form (each block reads its neighbours, nobody writes into another block) is race free.
+//
+// Clover input X per rhs: X = kappa T on even sites (A_e = 1 + X) and
+// X = A_o^-1 - 1 on odd sites (A_o^-1 = 1 + X).
+#include "blockgeo.hpp"
+#include "kernels.hpp"
+
+namespace sapdd {
+
+template <class S, class P> struct SapArgs {
+    Geom geo;
+    const S *links;
+    const float *lscale;
+    const S *const *X;
+    const float *const *Xsc;
+    const double *kappa;
+    const double *eta;
+    const double *eta_scale;
+    int eta_scale_stride;
+    int64_t eta_stride;  // doubles per rhs
+    S *rres;
+    float *rres_sc;
+    S *delta;
+    float *delta_sc;
+    P *psi;
+    int64_t psi_stride;  // elements per rhs
+    const int *active;
+    int colour, mode, write_state, nmr;
+};
+
+// Sum three values over the workgroup in a fixed order; every thread gets the sums.
+template <class BK, class R>
+__device__ __forceinline__ void block_sum3(R &a, R &b, R &c, R *red) {
+#pragma unroll
+    for (int off = BK::W / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, BK::W);
+        b += __shfl_xor(b, off, BK::W);
+        c += __shfl_xor(c, off, BK::W);
+    }
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red[3 * wv] = a;
+        red[3 * wv + 1] = b;
+        red[3 * wv + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0;
+#pragma unroll
+    for (int q = 0; q < BK::NW; ++q) {
+        a += red[3 * q];
+        b += red[3 * q + 1];
+        c += red[3 * q + 2];
+    }
+}
+
+template <class BK, class S, class R, class P>
+__global__ __launch_bounds__(BK::NT) void sap_half_kernel(SapArgs<S, P> a) {
+    constexpr int Vbh = BK::Vbh;
+    constexpr bool CACHE = sizeof(R) == 4;  // FP32 arithmetic: keep links and clover in registers
+    __shared__ R sp[24 * Vbh];
+    __shared__ R hb[48 * Vbh];
+    __shared__ R red[3 * BK::NW];
+
+    const Geom &geo = a.geo;
+    const SiteInfo si = site_info<BK>(threadIdx.x);
+    const int64_t b = colour_block(geo.G, a.colour, blockIdx.x);
+    const int rhs = a.active[blockIdx.y];
+    const int64_t bp = 2 * b + si.p;
+    const R kappa = (R)a.kappa[rhs];
+    const int64_t V = geo.V;
+
+    SiteLinks<S, R, CACHE> U;
+    U.init(a.links, a.lscale, bp, si.s, Vbh);
+    SiteClover<S, R, CACHE> Xc;
+    Xc.init(a.X[rhs], a.Xsc ? a.Xsc[rhs] : nullptr, bp, si.s, Vbh);
+
+    S *dlt = a.delta + (int64_t)rhs * V * 24;
+    float *dlt_sc = a.delta_sc ? a.delta_sc + (int64_t)rhs * V : nullptr;
+
+    // ---- 1. block residual
+    R rho[24];
+    if (a.mode < 2) {
+        const double *e = a.eta + rhs * a.eta_stride + bp * 24 * (int64_t)Vbh + si.s;
+        const double f = a.eta_scale ? a.eta_scale[(int64_t)rhs * a.eta_scale_stride] : 1.0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) rho[k] = (R)(e[(int64_t)k * Vbh] * f);
+    } else if (si.p == 0) {
+        load_site<R, 24>(a.rres + (int64_t)rhs * V * 12, a.rres_sc ? a.rres_sc + (int64_t)rhs * (V / 2) : nullptr, b,
+                         si.s, Vbh, rho);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) rho[k] = 0;
+    }
+    if (a.mode >= 1) {
+        // rho(x) -= sum_y M_{x,y} delta(y) over hops from neighbouring blocks: M = -kappa * hop there.
+        int g[4];
+        block_coords(geo.G, b, g);
+        const int B[4] = {BK::bx, BK::by, BK::bz, BK::bt};
+        static_for<0, 4>([&](auto m) {
+            constexpr int MU = decltype(m)::value;
+            if (!(si.fin & (1u << MU))) {  // x + mu lies in the next block
+                int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
+                R sg = 1;
+                if (++gn[MU] == geo.G[MU]) {
+                    gn[MU] = 0;
+                    if (MU == 3 && geo.antiperiodic) sg = -1;
+                }
+                ln[MU] = 0;
+                const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
+                const int ns = local_half_index(B, ln);
+                R d[24], h[12], u[18], uh[12];
+                load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
+                project<MU, -1>(d, h);
+                U.template get<MU>(u);
+                su3_mul(u, h, uh);
+                accum_recon<MU, -1>(rho, uh, kappa * sg);
+            }
+            if (!(si.bin & (1u << MU))) {  // x - mu lies in the previous block
+                int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
+                R sg = 1;
+                if (--gn[MU] < 0) {
+                    gn[MU] = geo.G[MU] - 1;
+                    if (MU == 3 && geo.antiperiodic) sg = -1;
+                }
+                ln[MU] = B[MU] - 1;
+                const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
+                const int ns = local_half_index(B, ln);
+                R d[24], h[12], u[18], uh[12];
+                load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
+                {
+                    const S *lp = a.links + (nbp * 72 + MU * 18) * (int64_t)Vbh + ns;
+                    R sc = 1;
+                    if constexpr (Storage<S>::scaled) sc = (R)a.lscale[nbp * Vbh + ns];
+#pragma unroll
+                    for (int q = 0; q < 18; ++q) u[q] = (R)lp[(int64_t)q * Vbh] * sc;
+                }
+                project<MU, +1>(d, h);
+                su3_dag_mul(u, h, uh);
+                accum_recon<MU, +1>(rho, uh, kappa * sg);
+            }
+        });
+    }
+
+    // out = in + X in; X is re-expanded at each use to keep its live range short
+    auto capply = [&](const R in[24], R out[24]) {
+        R X[72];
+        Xc.get(X);
+        clover_apply(X, in, out);
+    };
+
+    // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o
+    R t[24], hop[24], r[24], xs[24];
+    if (si.p == 1) capply(rho, t);
+    block_hop<BK>(1, si, U, t, hop, sp, hb);
+    if (si.p == 0) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            r[k] = rho[k] + kappa * hop[k];
+            xs[k] = 0;
+        }
+    }
+
+    // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
+    const R k2 = kappa * kappa;
+    for (int it = 0; it < a.nmr; ++it) {
+        block_hop<BK>(0, si, U, r, hop, sp, hb);
+        if (si.p == 1) capply(hop, t);
+        block_hop<BK>(1, si, U, t, hop, sp, hb);
+        R p[24];
+        R pr_re = 0, pr_im = 0, pp = 0;
+        if (si.p == 0) {
+            capply(r, p);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) p[k] -= k2 * hop[k];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                pr_re += p[2 * k] * r[2 * k] + p[2 * k + 1] * r[2 * k + 1];
+                pr_im += p[2 * k] * r[2 * k + 1] - p[2 * k + 1] * r[2 * k];
+                pp += p[2 * k] * p[2 * k] + p[2 * k + 1] * p[2 * k + 1];
+            }
+        }
+        block_sum3<BK>(pr_re, pr_im, pp, red);
+        R ar = 0, ai = 0;
+        if (pp > 0) {
+            ar = pr_re / pp;
+            ai = pr_im / pp;
+        }
+        if (si.p == 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const R rr = r[2 * k], ri = r[2 * k + 1];
+                const R qr = p[2 * k], qi = p[2 * k + 1];
+                xs[2 * k] += ar * rr - ai * ri;
+                xs[2 * k + 1] += ar * ri + ai * rr;
+                r[2 * k] = rr - (ar * qr - ai * qi);
+                r[2 * k + 1] = ri - (ar * qi + ai * qr);
+            }
+        }
+    }
+
+    // ---- 4. delta_o = A_o^-1 (rho_o + kappa H_oe delta_e)
+    block_hop<BK>(0, si, U, xs, hop, sp, hb);
+    R dl[24];
+    if (si.p == 0) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) dl[k] = xs[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) t[k] = rho[k] + kappa * hop[k];
+        capply(t, dl);
+    }
+
+    // ---- 5. outputs
+    P *ps = a.psi + rhs * a.psi_stride + bp * 24 * (int64_t)Vbh + si.s;
+    if (a.mode == 2) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) ps[(int64_t)k * Vbh] = (P)((R)ps[(int64_t)k * Vbh] + dl[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) ps[(int64_t)k * Vbh] = (P)dl[k];
+    }
+    if (a.write_state) {
+        store_site<R, 24>(dlt, dlt_sc, bp, si.s, Vbh, dl);
+        if (si.p == 0)
+            store_site<R, 24>(a.rres + (int64_t)rhs * V * 12, a.rres_sc ? a.rres_sc + (int64_t)rhs * (V / 2) : nullptr,
+                              b, si.s, Vbh, r);
+    }
+}
+
+template <class BK, class S, class R, class P>
+static hipError_t sap_typed(const Geom &geo, const SapArgsHost &h, int colour, int mode, int ws, hipStream_t st) {
+    SapArgs<S, P> a;
+    a.geo = geo;
+    a.links = (const S *)h.links.data;
+    a.lscale = h.links.scale;
+    a.X = (const S *const *)h.X;
+    a.Xsc = h.Xsc;
+    a.kappa = h.kappa;
+    a.eta = h.eta;
+    a.eta_scale = h.eta_scale;
+    a.eta_scale_stride = h.eta_scale_stride;
+    a.eta_stride = (int64_t)h.eta_stride_rhs * geo.V * 24;
+    a.rres = (S *)h.rres.data;
+    a.rres_sc = h.rres.scale;
+    a.delta = (S *)h.delta.data;
+    a.delta_sc = h.delta.scale;
+    a.psi = (P *)h.psi;
+    a.psi_stride = (int64_t)h.psi_stride_rhs * geo.V * 24;
+    a.active = h.active;
+    a.colour = colour;
+    a.mode = mode;
+    a.write_state = ws;
+    a.nmr = h.nmr;
+    dim3 grid((unsigned)(geo.Nd / 2), (unsigned)h.nact);
+    hipLaunchKernelGGL((sap_half_kernel<BK, S, R, P>), grid, dim3(BK::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class BK>
+static hipError_t sap_shape(const Geom &geo, const SapArgsHost &h, int colour, int mode, int ws, hipStream_t st) {
+    const int sp = h.links.prec;
+    if (sp == P64 && h.psi_prec == P64) return sap_typed<BK, double, double, double>(geo, h, colour, mode, ws, st);
+    if (sp == P32 && h.psi_prec == P32) return sap_typed<BK, float, float, float>(geo, h, colour, mode, ws, st);
+    if (sp == P16 && h.psi_prec == P32) return sap_typed<BK, half_t, float, float>(geo, h, colour, mode, ws, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sap_half(const Geom &geo, const SapArgsHost &a, int colour, int mode, int write_state,
+                           hipStream_t st) {
+    if (a.nact <= 0) return hipSuccess;
+    if (geo.B[0] == 2 && geo.B[1] == 2 && geo.B[2] == 2 && geo.B[3] == 2)
+        return sap_shape<Blk<2, 2, 2, 2>>(geo, a, colour, mode, write_state, st);
+    if (geo.B[0] == 4 && geo.B[1] == 4 && geo.B[2] == 4 && geo.B[3] == 4)
+        return sap_shape<Blk<4, 4, 4, 4>>(geo, a, colour, mode, write_state, st);
+    if (geo.B[0] == 8 && geo.B[1] == 4 && geo.B[2] == 4 && geo.B[3] == 4)
+        return sap_shape<Blk<8, 4, 4, 4>>(geo, a, colour, mode, write_state, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace sapdd

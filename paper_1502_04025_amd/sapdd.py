@@ -1,0 +1,261 @@
+"""Python binding of libsapdd (the C ABI in include/sapdd.h): argument marshalling only.
+
+Every operation runs in the HIP library; this module converts numpy arrays (host
+pointers) or torch CUDA tensors (device pointers) into the C calls and raises
+SapddError on a negative status. There is no CPU fallback: if libsapdd.so is missing or
+cannot be loaded, `load_library` raises.
+
+Arrays use the canonical layouts of the header: complex128 links [t,z,y,x,4,3,3],
+spinors [rhs,t,z,y,x,4,3] (or [t,z,y,x,4,3] for one right-hand side) and clover
+[t,z,y,x,12,12].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsapdd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN = 0, -1, -2, -3, -4, -5, -6
+F64, F32, F16 = 0, 1, 2
+DEVICE_PTRS, USE_X0, NO_GRAPH = 1, 2, 4
+PRECS = {"f64": F64, "f32": F32, "f16": F16}
+
+# Entry points declared in include/sapdd.h (the CPU tests check the library exports them).
+EXPORTS = (
+    "sapdd_create", "sapdd_destroy", "sapdd_last_error", "sapdd_load_gauge",
+    "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
+    "sapdd_apply_block_D", "sapdd_sap", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
+)
+
+
+class SapddError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sapdd error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("block", C.c_int * 4), ("nmr", C.c_int), ("ncy", C.c_int), ("restart", C.c_int),
+                ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("true_relres", C.c_double), ("implicit_relres", C.c_double),
+                ("t_total", C.c_double), ("t_sap", C.c_double), ("t_dslash", C.c_double),
+                ("t_gs", C.c_double), ("t_host", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsapdd.so and declare its signatures. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1502_04025_amd.build`")
+    lib = C.CDLL(path)
+    P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
+    lib.sapdd_create.argtypes = [I, VP, P(VP)]
+    lib.sapdd_destroy.argtypes = [VP]
+    lib.sapdd_destroy.restype = None
+    lib.sapdd_last_error.argtypes = [VP]
+    lib.sapdd_last_error.restype = C.c_char_p
+    lib.sapdd_load_gauge.argtypes = [VP, P(I), P(I), VP, I, I, P(VP)]
+    lib.sapdd_compute_clover.argtypes = [VP, VP, D]
+    lib.sapdd_load_clover.argtypes = [VP, VP, VP, I]
+    lib.sapdd_free_field.argtypes = [VP, VP]
+    lib.sapdd_apply_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
+    lib.sapdd_apply_block_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
+    lib.sapdd_sap.argtypes = [VP, VP, D, P(Params), I, VP, VP]
+    lib.sapdd_solve.argtypes = [VP, VP, P(D), P(Params), I, VP, VP, P(Stats)]
+    lib.sapdd_solve_footprint.argtypes = [VP, P(Params), I]
+    lib.sapdd_solve_footprint.restype = C.c_longlong
+    lib.sapdd_copy.argtypes = [VP, VP, VP, C.c_longlong]
+    for name in EXPORTS:
+        if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint"):
+            getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, writable=False):
+    """(pointer, is_device) of a C-contiguous complex128 numpy array or torch tensor."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        import torch
+        if a.dtype != torch.complex128:
+            raise ValueError("tensor must be complex128")
+        return C.c_void_p(a.data_ptr()), a.is_cuda
+    if not isinstance(a, np.ndarray) or a.dtype != np.complex128 or not a.flags.c_contiguous:
+        raise ValueError("array must be a C-contiguous complex128 numpy array")
+    if writable and not a.flags.writeable:
+        raise ValueError("output array is read-only")
+    return C.c_void_p(a.ctypes.data), False
+
+
+def _empty_like(a):
+    if _is_torch(a):
+        import torch
+        return torch.empty_like(a)
+    return np.empty_like(a)
+
+
+@dataclass
+class SolveResult:
+    x: object
+    stats: list
+    status: int
+
+
+class Context:
+    """One device + stream + workspaces. stream: a torch.cuda.Stream, a raw hipStream_t
+    integer, or None for the null stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load_library()
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        h = C.c_void_p()
+        rc = self.lib.sapdd_create(int(device), C.c_void_p(stream or 0), C.byref(h))
+        if rc != OK:
+            raise SapddError(rc, "sapdd_create failed")
+        self.h = h
+        self.device = device
+
+    def _check(self, rc):
+        if rc != OK:
+            raise SapddError(rc, self.lib.sapdd_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sapdd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_gauge(self, links, block, antiperiodic: bool = True) -> "Field":
+        lt, lz, ly, lx = links.shape[:4]
+        if tuple(links.shape[4:]) != (4, 3, 3):
+            raise ValueError("links must have shape [t,z,y,x,4,3,3]")
+        dims = (C.c_int * 4)(lx, ly, lz, lt)
+        blk = (C.c_int * 4)(*[int(b) for b in block])
+        p, dev = _ptr(links)
+        h = C.c_void_p()
+        self._check(self.lib.sapdd_load_gauge(self.h, dims, blk, p, int(bool(antiperiodic)),
+                                              DEVICE_PTRS if dev else 0, C.byref(h)))
+        return Field(self, h, (lx, ly, lz, lt), tuple(int(b) for b in block))
+
+    def copy(self, src, dst, nbytes: int):
+        self._check(self.lib.sapdd_copy(self.h, C.c_void_p(src), C.c_void_p(dst), int(nbytes)))
+
+
+class Field:
+    """A resident gauge field (links + clover term) with a fixed Schwarz blocking."""
+
+    def __init__(self, ctx: Context, h, dims, block):
+        self.ctx, self.h, self.dims, self.block = ctx, h, dims, block
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.sapdd_free_field(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                self.free()
+        except Exception:
+            pass
+
+    def compute_clover(self, csw: float):
+        self.ctx._check(self.ctx.lib.sapdd_compute_clover(self.ctx.h, self.h, float(csw)))
+
+    def load_clover(self, clover):
+        p, dev = _ptr(clover)
+        self.ctx._check(self.ctx.lib.sapdd_load_clover(self.ctx.h, self.h, p, DEVICE_PTRS if dev else 0))
+
+    @staticmethod
+    def _nrhs(psi):
+        return 1 if psi.ndim == 6 else int(psi.shape[0])
+
+    def _apply(self, fn, kappa, psi, prec, out):
+        out = _empty_like(psi) if out is None else out
+        pi, dev = _ptr(psi)
+        po, dev2 = _ptr(out, writable=True)
+        if dev != dev2:
+            raise ValueError("input and output must both be host or both be device arrays")
+        self.ctx._check(fn(self.ctx.h, self.h, float(kappa), PRECS[prec] if isinstance(prec, str) else int(prec),
+                           self._nrhs(psi), pi, po, DEVICE_PTRS if dev else 0))
+        return out
+
+    def apply_D(self, kappa, psi, prec="f64", out=None):
+        return self._apply(self.ctx.lib.sapdd_apply_D, kappa, psi, prec, out)
+
+    def apply_block_D(self, kappa, psi, prec="f64", out=None):
+        return self._apply(self.ctx.lib.sapdd_apply_block_D, kappa, psi, prec, out)
+
+    def params(self, nmr=4, ncy=5, restart=16, max_iter=1000, tol=1e-10, prec="f64", flags=0) -> Params:
+        p = Params()
+        for i in range(4):
+            p.block[i] = self.block[i]
+        p.nmr, p.ncy, p.restart, p.max_iter, p.tol = nmr, ncy, restart, max_iter, tol
+        p.sap_prec = PRECS[prec] if isinstance(prec, str) else int(prec)
+        p.flags = flags
+        return p
+
+    def sap(self, kappa, psi, out=None, **kw):
+        prm = self.params(**kw)
+        out = _empty_like(psi) if out is None else out
+        pi, dev = _ptr(psi)
+        po, _ = _ptr(out, writable=True)
+        if dev:
+            prm.flags |= DEVICE_PTRS
+        self.ctx._check(self.ctx.lib.sapdd_sap(self.ctx.h, self.h, float(kappa), C.byref(prm), self._nrhs(psi),
+                                               pi, po))
+        return out
+
+    def footprint(self, nrhs=1, **kw) -> int:
+        prm = self.params(**kw)
+        return int(self.ctx.lib.sapdd_solve_footprint(self.h, C.byref(prm), int(nrhs)))
+
+    def solve(self, kappa, b, x=None, x0=None, raise_on_noconv=True, **kw) -> SolveResult:
+        """Solve M x = b; kappa is a float or one value per right-hand side."""
+        nrhs = self._nrhs(b)
+        prm = self.params(**kw)
+        kap = np.broadcast_to(np.asarray(kappa, dtype=np.float64), (nrhs,)).copy()
+        if x is None:
+            x = _empty_like(b)
+        if x0 is not None:
+            x[...] = x0
+            prm.flags |= USE_X0
+        pb, dev = _ptr(b)
+        px, _ = _ptr(x, writable=True)
+        if dev:
+            prm.flags |= DEVICE_PTRS
+        stats = (Stats * nrhs)()
+        rc = self.ctx.lib.sapdd_solve(self.ctx.h, self.h, kap.ctypes.data_as(C.POINTER(C.c_double)),
+                                      C.byref(prm), nrhs, pb, px, stats)
+        if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
+            self.ctx._check(rc)
+        return SolveResult(x, [s.as_dict() for s in stats], rc)

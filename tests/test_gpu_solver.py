@@ -1,0 +1,206 @@
+"""GPU parity of the Schwarz preconditioner and of the full SAP-FGMRES solve.
+
+SAP output against the oracle's SAP on the same input (relative 2-norm error): FP64
+storage 1e-10 (the same algorithm in the same precision, different summation order);
+FP32 storage 2e-5 and FP16 storage 2e-2 (measured errors of lower-precision storage
+of a nonlinear iteration; the paper prints no values to pin these, so they are bounds on
+measured behaviour). Solves: every right-hand side reaches a true relative residual
+<= 1e-10 recomputed by the oracle's FP64 operator, in every precision mode.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import fgmres as ofg
+from oracle import sap as osap
+from oracle import wilson
+
+pytestmark = pytest.mark.gpu
+
+SAP_TOL = {"f64": 1e-10, "f32": 2e-5, "f16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1502_04025_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+_cache = {}
+
+
+def setup_case(ctx, dims, block, csw=1.0, eps=0.3, seed=5):
+    key = (dims, block, csw, eps, seed)
+    if key not in _cache:
+        u = synthetic.gauge_field(dims, eps, seed)
+        t = wilson.clover_term(u, csw)
+        f = ctx.load_gauge(u, block)
+        f.compute_clover(csw)
+        _cache[key] = (u, t, f)
+    return _cache[key]
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def oracle_relres(u, t, kappa, x, b):
+    return np.linalg.norm(b - wilson.apply_M(u, t, kappa, x)) / np.linalg.norm(b)
+
+
+SAP_CASES = [
+    ((4, 4, 4, 4), (2, 2, 2, 2), 0.12),
+    ((8, 8, 8, 8), (4, 4, 4, 4), 0.125),
+    ((16, 8, 8, 8), (8, 4, 4, 4), 0.125),
+]
+
+
+@pytest.mark.parametrize("dims,block,kappa", SAP_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_matches_oracle(ctx, dims, block, kappa, prec):
+    print(f"SAP {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    eta = synthetic.gaussian_source(dims, 1, 13)
+    out = f.sap(kappa, eta, nmr=4, ncy=3, prec=prec)
+    sys = osap.BlockSystem(u, t, kappa, block)
+    ref = osap.sap(sys, eta[0], 3, 4)
+    err = relerr(out[0], ref)
+    print(f"  SAP rel err {err:.3e}", flush=True)
+    assert err <= SAP_TOL[prec]
+
+
+def test_sap_single_cycle_and_point_source(ctx):
+    dims, block, kappa = (8, 8, 8, 8), (4, 4, 4, 4), 0.124
+    u, t, f = setup_case(ctx, dims, block)
+    eta = synthetic.point_sources(dims)[5:6].copy()  # most blocks see a zero residual
+    out = f.sap(kappa, eta, nmr=5, ncy=1, prec="f64")
+    ref = osap.sap(osap.BlockSystem(u, t, kappa, block), eta[0], 1, 5)
+    assert np.all(np.isfinite(out))
+    assert relerr(out[0], ref) <= SAP_TOL["f64"]
+
+
+def test_sap_deterministic(ctx):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block)
+    eta = synthetic.gaussian_source(dims, 2, 14)
+    a = f.sap(0.125, eta, nmr=4, ncy=2, prec="f32")
+    b = f.sap(0.125, eta, nmr=4, ncy=2, prec="f32")
+    assert np.array_equal(a, b)
+
+
+def test_solve_first_configuration_against_dense_lu(ctx):
+    """4^4, 2^4 blocks, kappa 0.12, c_sw 1, eps 0.3, nmr 4, ncy 5, FGMRES(16), FP64."""
+    cfg = synthetic.CONFIGS["c1_4x4x4x4_f64"]
+    dims, block = cfg["dims"], cfg["block"]
+    u = synthetic.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    t = wilson.clover_term(u, cfg["csw"])
+    b = synthetic.gaussian_source(dims, 1, cfg["source_seed"])
+    f = ctx.load_gauge(u, block)
+    f.compute_clover(cfg["csw"])
+    res = f.solve(cfg["kappa"], b, nmr=4, ncy=5, restart=16, tol=1e-10, prec="f64")
+    st = res.stats[0]
+    assert st["converged"] and st["true_relres"] <= 1e-10
+    assert oracle_relres(u, t, cfg["kappa"], res.x[0], b[0]) <= 1e-10
+    md = wilson.dense_matrix(u, t, cfg["kappa"])
+    x_lu = np.linalg.solve(md, b[0].reshape(-1)).reshape(b[0].shape)
+    assert relerr(res.x[0], x_lu) <= np.linalg.cond(md) * 1e-10
+    # the oracle's own SAP-FGMRES takes the same number of iterations (within one)
+    sys = osap.BlockSystem(u, t, cfg["kappa"], block)
+    _, info = ofg.fgmres(lambda v: wilson.apply_M(u, t, cfg["kappa"], v),
+                         lambda v: osap.sap(sys, v, 5, 4), b[0], m=16, tol=1e-10)
+    assert abs(info["iters"] - st["iters"]) <= 1
+    f.free()
+
+
+@pytest.mark.parametrize("dims,block,prec", [
+    ((8, 8, 8, 8), (4, 4, 4, 4), "f64"),
+    ((8, 8, 8, 8), (4, 4, 4, 4), "f32"),
+    ((8, 8, 8, 8), (4, 4, 4, 4), "f16"),
+    ((16, 8, 8, 8), (8, 4, 4, 4), "f32"),
+    ((16, 8, 8, 8), (8, 4, 4, 4), "f16"),
+])
+def test_solve_reaches_tolerance_all_precisions(ctx, dims, block, prec):
+    print(f"solve {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    b = synthetic.gaussian_source(dims, 1, 15)
+    res = f.solve(0.125, b, nmr=4, ncy=5, restart=16, tol=1e-10, prec=prec)
+    st = res.stats[0]
+    print(f"  iters {st['iters']} true {st['true_relres']:.2e}", flush=True)
+    assert st["converged"]
+    assert oracle_relres(u, t, 0.125, res.x[0], b[0]) <= 1e-10
+
+
+def test_multi_rhs_mixed_kappa_equals_single_solves(ctx):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block)
+    b = synthetic.gaussian_source(dims, 3, 16)
+    kap = np.array([0.120, 0.123, 0.126])
+    res = f.solve(kap, b, nmr=4, ncy=5, restart=16, tol=1e-10, prec="f16")
+    for r in range(3):
+        assert oracle_relres(u, t, kap[r], res.x[r], b[r]) <= 1e-10
+        alone = f.solve(kap[r], b[r:r + 1].copy(), nmr=4, ncy=5, restart=16, tol=1e-10, prec="f16")
+        assert np.array_equal(alone.x[0], res.x[r])  # batch composition does not change bits
+        assert alone.stats[0]["iters"] == res.stats[r]["iters"]
+
+
+def test_point_sources_multi_rhs(ctx):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block, eps=0.25, seed=6)
+    b = synthetic.point_sources(dims)
+    res = f.solve(0.126, b, nmr=4, ncy=5, restart=16, tol=1e-10, prec="f16")
+    for r in (0, 5, 11):
+        assert oracle_relres(u, t, 0.126, res.x[r], b[r]) <= 1e-10
+
+
+def test_half_precision_keeps_iteration_count(ctx):
+    """Sec. 3.3: half-precision storage did not noticeably change the outer iteration count."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block)
+    b = synthetic.gaussian_source(dims, 1, 17)
+    n32 = f.solve(0.125, b, prec="f32").stats[0]["iters"]
+    n16 = f.solve(0.125, b, prec="f16").stats[0]["iters"]
+    assert abs(n16 - n32) <= 1
+
+
+def test_start_vector_and_zero_rhs(ctx):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block)
+    b = synthetic.gaussian_source(dims, 1, 18)
+    first = f.solve(0.125, b, prec="f64")
+    again = f.solve(0.125, b, x0=first.x.copy(), prec="f64")
+    assert again.stats[0]["iters"] == 0 and again.stats[0]["converged"]
+    z = np.zeros_like(b)
+    zr = f.solve(0.125, z, prec="f64")
+    assert np.all(zr.x == 0) and zr.stats[0]["converged"]
+
+
+def test_error_paths(ctx):
+    from paper_1502_04025_amd import EINVAL, ENOCONV, ESINGULAR, SapddError
+    dims = (4, 4, 4, 4)
+    u = synthetic.gauge_field(dims, 0.3, 3)
+    with pytest.raises(SapddError) as e:
+        ctx.load_gauge(u, (4, 4, 4, 4))  # one block per direction: no two-colouring
+    assert e.value.code == EINVAL
+    with pytest.raises(SapddError) as e:
+        ctx.load_gauge(u, (2, 2, 2, 1))
+    assert e.value.code == EINVAL
+    f = ctx.load_gauge(u, (2, 2, 2, 2))
+    f.compute_clover(1.0)
+    b = synthetic.gaussian_source(dims, 1, 4)
+    res = f.solve(0.12, b, max_iter=1, raise_on_noconv=False, prec="f64")
+    assert res.status == ENOCONV and res.stats[0]["iters"] == 1
+    with pytest.raises(SapddError) as e:
+        f.solve(0.12, b, restart=40)
+    assert e.value.code == EINVAL
+    # A = 1 + kappa T singular on every site: T = -(1/kappa) 1
+    tsing = np.zeros(u.shape[:4] + (12, 12), dtype=np.complex128)
+    tsing[...] = -np.eye(12) / 0.12
+    f.load_clover(tsing)
+    with pytest.raises(SapddError) as e:
+        f.solve(0.12, b, prec="f64")
+    assert e.value.code == ESINGULAR
+    f.free()
