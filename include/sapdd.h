@@ -142,6 +142,25 @@ long long sapdd_solve_footprint(const sapdd_field *field, const sapdd_params *pa
  * bandwidth); src and dst are device pointers. */
 int sapdd_copy(sapdd_ctx *ctx, const void *src, void *dst, long long n);
 
+/* Per-kernel device time, measured with HIP events recorded on the context's stream
+ * around every launch of each kernel family while profiling is on. */
+enum {
+    SAPDD_K_SAP_HALF = 0,     /* fused gather + MR block solve, one colour           */
+    SAPDD_K_DSLASH = 1,       /* full Wilson-clover operator                        */
+    SAPDD_K_GS = 2,           /* Gram-Schmidt passes and their reductions            */
+    SAPDD_K_BLOCK_DSLASH = 3, /* block-diagonal operator M_B                        */
+    SAPDD_K_UPDATE = 4,       /* solution update x += Z y                            */
+    SAPDD_K_COPY = 5,         /* bandwidth-probe copy                                */
+    SAPDD_K_COUNT = 8
+};
+typedef struct {
+    long long launches[SAPDD_K_COUNT];
+    double seconds[SAPDD_K_COUNT];
+} sapdd_kernel_profile;
+/* Read (if out != NULL) and reset the accumulated profile, then switch profiling on
+ * (enable != 0) or off. Reading waits for the context's stream. */
+int sapdd_profile(sapdd_ctx *ctx, int enable, sapdd_kernel_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,13 @@ struct sapdd_ctx {
     size_t pinned_n = 0;
     hipEvent_t ev[8] = {};
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // SAP sweep per (nact, j)
+    // kernel profiling: event pairs recorded around launches, drained at sync points
+    bool prof = false;
+    std::vector<hipEvent_t> pev;
+    std::vector<int> pkind;
+    size_t pn = 0;
+    long long plaunch[SAPDD_K_COUNT] = {};
+    double psec[SAPDD_K_COUNT] = {};
 };
 
 namespace {
@@ -88,10 +95,58 @@ int fail(sapdd_ctx *c, int code, const char *fmt, ...) {
                         #call, hipGetErrorString(e_), __FILE__, __LINE__);                             \
     } while (0)
 
+// Accumulate the elapsed time of every recorded event pair (the stream must have
+// completed them) and recycle the pool.
+int prof_drain(sapdd_ctx *c) {
+    for (size_t i = 0; i < c->pn; ++i) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
+        c->psec[c->pkind[i]] += ms * 1e-3;
+        c->plaunch[c->pkind[i]] += 1;
+    }
+    c->pn = 0;
+    return SAPDD_OK;
+}
+
+// Record the start event of a profiled launch of family `kind` (no-op when profiling is off).
+int prof_begin(sapdd_ctx *c, int kind) {
+    if (!c->prof) return SAPDD_OK;
+    if (2 * (c->pn + 1) > c->pev.size()) {
+        if (c->pev.size() >= 8192) {  // pool full: wait for the stream and drain it
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            int r = prof_drain(c);
+            if (r != SAPDD_OK) return r;
+        } else {
+            const size_t old = c->pev.size();
+            c->pev.resize(old ? 2 * old : 256);
+            c->pkind.resize(c->pev.size() / 2);
+            for (size_t i = old; i < c->pev.size(); ++i) HIPCHK(c, hipEventCreate(&c->pev[i]));
+        }
+    }
+    c->pkind[c->pn] = kind;
+    HIPCHK(c, hipEventRecord(c->pev[2 * c->pn], c->stream));
+    return SAPDD_OK;
+}
+
+int prof_end(sapdd_ctx *c) {
+    if (!c->prof) return SAPDD_OK;
+    HIPCHK(c, hipEventRecord(c->pev[2 * c->pn + 1], c->stream));
+    c->pn += 1;
+    return SAPDD_OK;
+}
+
 #define CHK(expr)             \
     do {                      \
         int r_ = (expr);      \
         if (r_ != SAPDD_OK) return r_; \
+    } while (0)
+
+// A kernel launch timed under profiling.
+#define KLAUNCH(ctx, kind, call)            \
+    do {                                    \
+        CHK(prof_begin(ctx, kind));         \
+        HIPCHK(ctx, call);                  \
+        CHK(prof_end(ctx));                 \
     } while (0)
 
 // Named grow-only device buffer.
@@ -319,7 +374,7 @@ int sap_run(sapdd_ctx *c, const Geom &g, const SapState &s, const sapdd_params *
         for (int col = 0; col < 2; ++col) {
             const int mode = k == 0 ? col : 2;
             const int last = (k == p->ncy - 1) && col == 1;
-            HIPCHK(c, launch_sap_half(g, a, col, mode, !last, c->stream));
+            KLAUNCH(c, SAPDD_K_SAP_HALF, launch_sap_half(g, a, col, mode, !last, c->stream));
         }
     return SAPDD_OK;
 }
@@ -378,6 +433,8 @@ void sapdd_destroy(sapdd_ctx *c) {
     if (c->d_flag) (void)hipFree(c->d_flag);
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->pev)
         if (e) (void)hipEventDestroy(e);
     delete c;
 }
@@ -503,7 +560,7 @@ static int apply_common(sapdd_ctx *c, const sapdd_field *fc, double kappa, int p
     CHK(spinor_buf(c, "op_out", g, nrhs, prec, 24, &fout));
     HIPCHK(c, launch_pack(g, 24, nrhs, src, fin, c->stream));
     if (block) {
-        HIPCHK(c, launch_dslash_block(g, links_of(f, prec), tclov_of(f, prec), kappa, fin, fout, nrhs, c->stream));
+        KLAUNCH(c, SAPDD_K_BLOCK_DSLASH, launch_dslash_block(g, links_of(f, prec), tclov_of(f, prec), kappa, fin, fout, nrhs, c->stream));
     } else {
         int *ident;
         CHK(identity_list(c, nrhs, &ident));
@@ -513,7 +570,7 @@ static int apply_common(sapdd_ctx *c, const sapdd_field *fc, double kappa, int p
         io.active = ident;
         io.nact = nrhs;
         io.in_stride = io.out_stride = io.sub_stride = 1;
-        HIPCHK(c, launch_dslash_full(g, links_of(f, prec), tclov_of(f, prec), kappa, io, c->stream));
+        KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, prec), tclov_of(f, prec), kappa, io, c->stream));
     }
     double *dst = out;
     if (!(flags & SAPDD_DEVICE_PTRS)) {
@@ -589,10 +646,28 @@ long long sapdd_solve_footprint(const sapdd_field *f, const sapdd_params *p, int
     return fixed + per_rhs * nrhs;
 }
 
+int sapdd_profile(sapdd_ctx *c, int enable, sapdd_kernel_profile *out) {
+    if (!c) return SAPDD_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    CHK(prof_drain(c));
+    if (out)
+        for (int k = 0; k < SAPDD_K_COUNT; ++k) {
+            out->launches[k] = c->plaunch[k];
+            out->seconds[k] = c->psec[k];
+        }
+    for (int k = 0; k < SAPDD_K_COUNT; ++k) {
+        c->plaunch[k] = 0;
+        c->psec[k] = 0;
+    }
+    c->prof = enable != 0;
+    return SAPDD_OK;
+}
+
 int sapdd_copy(sapdd_ctx *c, const void *src, void *dst, long long n) {
     if (!c || !src || !dst || n < 0) return fail(c, SAPDD_EINVAL, "bad copy arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, launch_copy(src, dst, n, c->stream));
+    KLAUNCH(c, SAPDD_K_COPY, launch_copy(src, dst, n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return SAPDD_OK;
 }
@@ -736,8 +811,8 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
         a.nv = 0;
         a.n = ncx;
         a.vbh_shift = sh;
-        HIPCHK(c, launch_cgs(2, a, c->stream));
-        HIPCHK(c, launch_reduce(part, blas_partials(ncx, nrhs), 1, d_all, nrhs, coef + L.noff, L.CST, nullptr, 0, 0,
+        KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, blas_partials(ncx, nrhs), 1, d_all, nrhs, coef + L.noff, L.CST, nullptr, 0, 0,
                                 nullptr, 0, c->stream));
         HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -772,12 +847,13 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
         io.out_stride = m + 1;
         io.sub_stride = 1;
         io.kappa = dkappa;
-        HIPCHK(c, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
-        HIPCHK(c, launch_reduce(part, nwg_d, 1, d_act, nact, coef + L.noff, L.CST, nullptr, 0, 0, vscale, m + 1,
+        KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg_d, 1, d_act, nact, coef + L.noff, L.CST, nullptr, 0, 0, vscale, m + 1,
                                 c->stream));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
         HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->prof) CHK(prof_drain(c));
         {
             float ms;
             HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
@@ -833,7 +909,7 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             w.in_stride = m;
             w.out_stride = m + 1;
             w.kappa = dkappa;
-            HIPCHK(c, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, w, c->stream));
+            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, w, c->stream));
             HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
             // ---- CGS2 against v_0 .. v_j
             CgsArgs a{};
@@ -858,12 +934,12 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
                     a.v0 = v0;
                     a.nv = std::min(16, j + 1 - v0);
                     if (pass == 0) {
-                        HIPCHK(c, launch_cgs(0, a, c->stream));
+                        KLAUNCH(c, SAPDD_K_GS, launch_cgs(0, a, c->stream));
                     } else {
                         a.coef = coef + L.hoff;
-                        HIPCHK(c, launch_cgs(1, a, c->stream));
+                        KLAUNCH(c, SAPDD_K_GS, launch_cgs(1, a, c->stream));
                     }
-                    HIPCHK(c, launch_reduce(part, nwg, 2 * a.nv, d_cyc, ncyc, coef + outoff + 2 * v0, L.CST, vscale,
+                    KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg, 2 * a.nv, d_cyc, ncyc, coef + outoff + 2 * v0, L.CST, vscale,
                                             m + 1, v0, nullptr, 0, c->stream));
                 }
             }
@@ -871,12 +947,13 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             a.coef = coef + L.coff;
             a.v0 = 0;
             a.nv = j + 1;
-            HIPCHK(c, launch_cgs(2, a, c->stream));
-            HIPCHK(c, launch_reduce(part, nwg, 1, d_cyc, ncyc, coef + L.noff, L.CST, nullptr, 0, 0, vscale + j + 1,
+            KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
+            KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg, 1, d_cyc, ncyc, coef + L.noff, L.CST, nullptr, 0, 0, vscale + j + 1,
                                     m + 1, c->stream));
             HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
             HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->prof) CHK(prof_drain(c));
             const double th = now_s();
             {
                 float ms;
@@ -970,7 +1047,7 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             int *d_grp;
             CHK(upload_list(c, dlists, hlists, seg, nrhs, kv.second, &d_grp));
             seg = seg + 1 < nseg ? seg + 1 : 4;
-            HIPCHK(c, launch_zupdate(Xd, NS, Zb.data, zprec, NS, (int64_t)m * NS, ydev, 2 * m, kv.first, d_grp,
+            KLAUNCH(c, SAPDD_K_UPDATE, launch_zupdate(Xd, NS, Zb.data, zprec, NS, (int64_t)m * NS, ydev, 2 * m, kv.first, d_grp,
                                      (int)kv.second.size(), ncx, sh, c->stream));
             if (seg == 4) HIPCHK(c, hipStreamSynchronize(c->stream));
         }
@@ -996,8 +1073,8 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             io.out_stride = m + 1;
             io.sub_stride = 1;
             io.kappa = dkappa;
-            HIPCHK(c, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
-            HIPCHK(c, launch_reduce(part, nwg_d, 1, d_chk, io.nact, coef + L.noff, L.CST, nullptr, 0, 0, nullptr, 0,
+            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
+            KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg_d, 1, d_chk, io.nact, coef + L.noff, L.CST, nullptr, 0, 0, nullptr, 0,
                                     c->stream));
             HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -30,7 +30,9 @@ EXPORTS = (
     "sapdd_create", "sapdd_destroy", "sapdd_last_error", "sapdd_load_gauge",
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
     "sapdd_apply_block_D", "sapdd_sap", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
+    "sapdd_profile",
 )
+KERNELS = ("sap_half", "dslash", "gram_schmidt", "block_dslash", "update", "copy")
 
 
 class SapddError(RuntimeError):
@@ -42,6 +44,14 @@ class SapddError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("nmr", C.c_int), ("ncy", C.c_int), ("restart", C.c_int),
                 ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int)]
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_longlong * 8), ("seconds", C.c_double * 8)]
+
+    def as_dict(self):
+        return {k: dict(launches=int(self.launches[i]), seconds=float(self.seconds[i]))
+                for i, k in enumerate(KERNELS)}
 
 
 class Stats(C.Structure):
@@ -82,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_solve_footprint.argtypes = [VP, P(Params), I]
     lib.sapdd_solve_footprint.restype = C.c_longlong
     lib.sapdd_copy.argtypes = [VP, VP, VP, C.c_longlong]
+    lib.sapdd_profile.argtypes = [VP, I, P(KernelProfile)]
     for name in EXPORTS:
         if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint"):
             getattr(lib, name).restype = I
@@ -165,6 +176,13 @@ class Context:
         self._check(self.lib.sapdd_load_gauge(self.h, dims, blk, p, int(bool(antiperiodic)),
                                               DEVICE_PTRS if dev else 0, C.byref(h)))
         return Field(self, h, (lx, ly, lz, lt), tuple(int(b) for b in block))
+
+    def profile(self, enable: bool):
+        """Return the per-kernel profile accumulated so far, reset it and switch
+        profiling on or off."""
+        kp = KernelProfile()
+        self._check(self.lib.sapdd_profile(self.h, int(bool(enable)), C.byref(kp)))
+        return kp.as_dict()
 
     def copy(self, src, dst, nbytes: int):
         self._check(self.lib.sapdd_copy(self.h, C.c_void_p(src), C.c_void_p(dst), int(nbytes)))
