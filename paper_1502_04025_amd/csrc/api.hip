@@ -205,12 +205,6 @@ bool supported_block(const int b[4]) {
            (b[0] == 8 && b[1] == 4 && b[2] == 4 && b[3] == 4);
 }
 
-int vbh_shift(const Geom &g) {
-    int s = 0;
-    while ((1 << s) < g.Vbh) ++s;
-    return s;
-}
-
 // Host->device staging of a canonical array (or pass-through of a device pointer).
 int stage_in(sapdd_ctx *c, const char *name, const double *p, size_t ndouble, int flags, const double **out) {
     if (flags & SAPDD_DEVICE_PTRS) {
@@ -726,7 +720,6 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
     const int zprec = prec == P64 ? P64 : P32;
     const int64_t NS = g.V * 24;  // doubles per spinor field
     const int64_t ncx = g.V * 12; // complex entries per field
-    const int sh = vbh_shift(g);
     const int flags = p->flags;
     const size_t nd = (size_t)NS * nrhs;
 
@@ -810,7 +803,6 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
         a.nact = nrhs;
         a.nv = 0;
         a.n = ncx;
-        a.vbh_shift = sh;
         KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
         KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, blas_partials(ncx, nrhs), 1, d_all, nrhs, coef + L.noff, L.CST, nullptr, 0, 0,
                                 nullptr, 0, c->stream));
@@ -925,8 +917,7 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             a.active = d_cyc;
             a.nact = ncyc;
             a.n = ncx;
-            a.vbh_shift = sh;
-            const int nwg = blas_partials(ncx, ncyc);
+                const int nwg = blas_partials(ncx, ncyc);
             for (int pass = 0; pass < 2; ++pass) {
                 // pass 0: h = V^H w (then w -= V h in the next launch); pass 1: c = V^H w'
                 const int outoff = pass == 0 ? L.hoff : L.coff;
@@ -1048,7 +1039,7 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
             CHK(upload_list(c, dlists, hlists, seg, nrhs, kv.second, &d_grp));
             seg = seg + 1 < nseg ? seg + 1 : 4;
             KLAUNCH(c, SAPDD_K_UPDATE, launch_zupdate(Xd, NS, Zb.data, zprec, NS, (int64_t)m * NS, ydev, 2 * m, kv.first, d_grp,
-                                     (int)kv.second.size(), ncx, sh, c->stream));
+                                     (int)kv.second.size(), ncx, g.Vbh, c->stream));
             if (seg == 4) HIPCHK(c, hipStreamSynchronize(c->stream));
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -3,9 +3,10 @@
 // each pass streams w and the basis once), deterministic reductions of the partial sums,
 // and the solution update x += Z y.
 //
-// Complex entries in the block-tiled layout keep their real and imaginary parts Vbh
-// doubles apart (component 2k and 2k+1 of the site); entry e = r * Vbh + s of a vector
-// has its real part at 2 r Vbh + s and its imaginary part Vbh further on.
+// In the block-tiled FP64 layout every 16-byte vector is one complex component (real
+// and imaginary part adjacent) and all FP64 spinor fields share one element order, so
+// these kernels treat a vector as a flat array of 12 V complex numbers. FP32 fields
+// hold two complex components per 16-byte vector (see zupdate).
 //
 // Reductions are two-level and in a fixed order: every workgroup writes its partial sum,
 // and a second kernel adds the partial sums in workgroup order, so a result never
@@ -51,11 +52,9 @@ __global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
     constexpr int NVAL = MODE == 2 ? 1 : 2 * NV;
     const int slot = blockIdx.y;
     const int rhs = a.active[slot];
-    const double *v = a.vbase + rhs * a.rstride + (int64_t)a.v0 * a.vstride;
-    const int64_t vs = a.vstride;
-    double *w = a.w + rhs * a.wstride;
-    const int sh = a.vbh_shift;
-    const int64_t vbh = (int64_t)1 << sh;
+    const double2 *v = (const double2 *)(a.vbase + rhs * a.rstride + (int64_t)a.v0 * a.vstride);
+    const int64_t vs = a.vstride / 2;
+    double2 *w = (double2 *)(a.w + rhs * a.wstride);
     double cr[NV > 0 ? NV : 1], ci[NV > 0 ? NV : 1];
     if (MODE >= 1) {
         const double *c = a.coef + (int64_t)rhs * a.cstride;
@@ -72,19 +71,17 @@ __global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
     for (int k = 0; k < NVAL; ++k) acc[k] = 0;
     const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
     for (int64_t e = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; e < a.n; e += stride) {
-        const int64_t re = e + ((e >> sh) << sh), im = re + vbh;
         double2 vv[NV > 0 ? NV : 1];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) vv[i] = make_double2(v[i * vs + re], v[i * vs + im]);
-        double2 ww = make_double2(w[re], w[im]);
+        for (int i = 0; i < NV; ++i) vv[i] = v[i * vs + e];
+        double2 ww = w[e];
         if (MODE >= 1 && NV > 0) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 ww.x -= cr[i] * vv[i].x - ci[i] * vv[i].y;
                 ww.y -= cr[i] * vv[i].y + ci[i] * vv[i].x;
             }
-            w[re] = ww.x;
-            w[im] = ww.y;
+            w[e] = ww;
         }
         if (MODE <= 1) {
 #pragma unroll
@@ -159,39 +156,65 @@ hipError_t launch_reduce(const double *part, int nwg, int nval, const int *activ
     return hipGetLastError();
 }
 
-template <class Z>
-__global__ __launch_bounds__(BLAS_WG) void zupdate_kernel(double *x, int64_t xstride, const Z *z, int64_t zsj,
-                                                          int64_t zsr, const double *y, int ystride, int nz,
-                                                          const int *active, int64_t n, int sh) {
+// x += sum_j y_j z_j. FP64 z shares x's element order; an FP32 z holds the complex
+// components 2v and 2v + 1 of site (bp, s) in its float4 number (bp * 6 + v) * Vbh + s,
+// which map to the double2 numbers (bp * 12 + 2v) * Vbh + s and the one Vbh later.
+__global__ __launch_bounds__(BLAS_WG) void zupdate64_kernel(double *x, int64_t xstride, const double *z, int64_t zsj,
+                                                            int64_t zsr, const double *y, int ystride, int nz,
+                                                            const int *active, int64_t n) {
     const int rhs = active[blockIdx.y];
-    double *xr = x + rhs * xstride;
-    const Z *zr = z + rhs * zsr;
+    double2 *xr = (double2 *)(x + rhs * xstride);
+    const double2 *zr = (const double2 *)(z + rhs * zsr);
     const double *yr = y + (int64_t)rhs * ystride;
     const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
     for (int64_t e = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; e < n; e += stride) {
-        const int64_t ire = e + ((e >> sh) << sh), iim = ire + ((int64_t)1 << sh);
-        double re = xr[ire], im = xr[iim];
+        double2 acc = xr[e];
         for (int j = 0; j < nz; ++j) {
-            const double zr_ = (double)zr[j * zsj + ire], zi_ = (double)zr[j * zsj + iim];
-            re += yr[2 * j] * zr_ - yr[2 * j + 1] * zi_;
-            im += yr[2 * j] * zi_ + yr[2 * j + 1] * zr_;
+            const double2 q = zr[j * (zsj / 2) + e];
+            acc.x += yr[2 * j] * q.x - yr[2 * j + 1] * q.y;
+            acc.y += yr[2 * j] * q.y + yr[2 * j + 1] * q.x;
         }
-        xr[ire] = re;
-        xr[iim] = im;
+        xr[e] = acc;
+    }
+}
+
+__global__ __launch_bounds__(BLAS_WG) void zupdate32_kernel(double *x, int64_t xstride, const float *z, int64_t zsj,
+                                                            int64_t zsr, const double *y, int ystride, int nz,
+                                                            const int *active, int64_t n4, int vbh) {
+    const int rhs = active[blockIdx.y];
+    double2 *xr = (double2 *)(x + rhs * xstride);
+    const float4 *zr = (const float4 *)(z + rhs * zsr);
+    const double *yr = y + (int64_t)rhs * ystride;
+    const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
+    for (int64_t q = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; q < n4; q += stride) {
+        const int64_t t = q / vbh;
+        const int s = (int)(q - t * vbh);
+        const int64_t e0 = (2 * t) * vbh + s;  // (bp * 12 + 2v) * Vbh + s with t = bp * 6 + v
+        double2 a0 = xr[e0], a1 = xr[e0 + vbh];
+        for (int j = 0; j < nz; ++j) {
+            const float4 f = zr[j * (zsj / 4) + q];
+            const double yr_ = yr[2 * j], yi_ = yr[2 * j + 1];
+            a0.x += yr_ * f.x - yi_ * f.y;
+            a0.y += yr_ * f.y + yi_ * f.x;
+            a1.x += yr_ * f.z - yi_ * f.w;
+            a1.y += yr_ * f.w + yi_ * f.z;
+        }
+        xr[e0] = a0;
+        xr[e0 + vbh] = a1;
     }
 }
 
 hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, int64_t zstride_j,
                           int64_t zstride_rhs, const double *y, int ystride, int nz, const int *active, int nact,
-                          int64_t n, int vbh_shift, hipStream_t st) {
+                          int64_t n, int vbh, hipStream_t st) {
     if (nact <= 0 || nz <= 0) return hipSuccess;
     const int nwg = blas_partials(n, nact);
     if (zprec == P64)
-        hipLaunchKernelGGL((zupdate_kernel<double>), dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride,
-                           (const double *)z, zstride_j, zstride_rhs, y, ystride, nz, active, n, vbh_shift);
+        hipLaunchKernelGGL(zupdate64_kernel, dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride, (const double *)z,
+                           zstride_j, zstride_rhs, y, ystride, nz, active, n);
     else if (zprec == P32)
-        hipLaunchKernelGGL((zupdate_kernel<float>), dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride,
-                           (const float *)z, zstride_j, zstride_rhs, y, ystride, nz, active, n, vbh_shift);
+        hipLaunchKernelGGL(zupdate32_kernel, dim3(nwg, nact), dim3(BLAS_WG), 0, st, x, xstride, (const float *)z,
+                           zstride_j, zstride_rhs, y, ystride, nz, active, n / 2, vbh);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

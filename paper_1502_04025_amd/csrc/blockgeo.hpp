@@ -62,144 +62,197 @@ template <class BK> __device__ __forceinline__ SiteInfo site_info(int tid) {
     return si;
 }
 
-// The four forward links of a thread's own site, either held in registers (in storage
-// precision, converted on use) or re-read from global memory on every use.
+// The four forward links of a thread's own site, either held in registers (as the
+// storage-precision 16-byte vectors they were loaded in, converted on use) or re-read
+// from global memory on every use.
 template <class S, class R, bool CACHE> struct SiteLinks;
 
 template <class S, class R> struct SiteLinks<S, R, true> {
-    S u[72];
+    typedef typename Vec<S>::type VT;
+    static constexpr int W = Vec<S>::W;
+    VT u[72 / W];
     R sc;
     __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale,
                                          int64_t bp, int s, int Vbh) {
-        const S *p = base + bp * 72 * (int64_t)Vbh + s;
+        const VT *p = reinterpret_cast<const VT *>(base);
 #pragma unroll
-        for (int k = 0; k < 72; ++k) u[k] = p[(int64_t)k * Vbh];
+        for (int v = 0; v < 72 / W; ++v) u[v] = p[vec_index<S, 72>(bp, v, s, Vbh)];
         if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
         else sc = (R)1;
     }
     template <int MU> __device__ __forceinline__ void get(R out[18]) const {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            if constexpr (Storage<S>::scaled) out[k] = (R)(float)u[18 * MU + k] * sc;
-            else out[k] = (R)u[18 * MU + k];
+            const int q = 18 * MU + k;
+            if constexpr (Storage<S>::scaled) out[k] = (R)(float)u[q / W][q % W] * sc;
+            else out[k] = (R)u[q / W][q % W];
         }
     }
 };
 
 template <class S, class R> struct SiteLinks<S, R, false> {
-    const S *p;
-    R sc;
-    int Vbh;
-    __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale,
-                                         int64_t bp, int s, int vbh) {
+    const S *base;
+    const float *scale;
+    int64_t bp;
+    int s, Vbh;
+    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ sc, int64_t bp_, int s_,
+                                         int vbh) {
+        base = b;
+        scale = sc;
+        bp = bp_;
+        s = s_;
         Vbh = vbh;
-        p = base + bp * 72 * (int64_t)Vbh + s;
-        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
-        else sc = (R)1;
     }
     template <int MU> __device__ __forceinline__ void get(R out[18]) const {
-#pragma unroll
-        for (int k = 0; k < 18; ++k) {
-            if constexpr (Storage<S>::scaled) out[k] = (R)(float)p[(int64_t)(18 * MU + k) * Vbh] * sc;
-            else out[k] = (R)p[(int64_t)(18 * MU + k) * Vbh];
-        }
+        load_reals<R, 72, 18 * MU, 18>(base, scale, bp, s, Vbh, out);
     }
 };
 
-// Per-site packed clover (72 reals), held or re-read like the links.
+// Per-site packed clover (72 reals) in registers as the storage-precision vectors it was
+// loaded in; entries are converted one at a time where they are used.
+template <class S, class R> struct CloverRegs {
+    typedef typename Vec<S>::type VT;
+    static constexpr int W = Vec<S>::W;
+    VT x[72 / W];
+    R sc;
+    __device__ __forceinline__ void load(const S *__restrict__ base, const float *__restrict__ scale, int64_t bp,
+                                         int s, int Vbh) {
+        const VT *p = reinterpret_cast<const VT *>(base);
+#pragma unroll
+        for (int v = 0; v < 72 / W; ++v) x[v] = p[vec_index<S, 72>(bp, v, s, Vbh)];
+        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
+        else sc = (R)1;
+    }
+    __device__ __forceinline__ R at(int k) const {
+        if constexpr (Storage<S>::scaled) return (R)(float)x[k / W][k % W] * sc;
+        else return (R)x[k / W][k % W];
+    }
+};
+
+// out = in + kx * X in for the two packed Hermitian 6x6 blocks of X.
+template <class S, class R>
+__device__ __forceinline__ void clover_mul(const CloverRegs<S, R> &X, const R (&in)[24], R (&out)[24], R kx) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const int o = 12 * blk;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const R d = kx * X.at(36 * blk + i) + (R)1;
+            out[o + 2 * i] = d * in[o + 2 * i];
+            out[o + 2 * i + 1] = d * in[o + 2 * i + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) {
+                const int q = 36 * blk + 6 + 2 * (i * 5 - i * (i - 1) / 2 + (j - i - 1));
+                const R xr = kx * X.at(q), xi = kx * X.at(q + 1);
+                out[o + 2 * i] += xr * in[o + 2 * j] - xi * in[o + 2 * j + 1];
+                out[o + 2 * i + 1] += xr * in[o + 2 * j + 1] + xi * in[o + 2 * j];
+                out[o + 2 * j] += xr * in[o + 2 * i] + xi * in[o + 2 * i + 1];
+                out[o + 2 * j + 1] += xr * in[o + 2 * i + 1] - xi * in[o + 2 * i];
+            }
+    }
+}
+
+// The clover of a thread's own site, held in registers for the whole kernel or re-read
+// (from the L1/L2 caches) at every use.
 template <class S, class R, bool CACHE> struct SiteClover;
 
 template <class S, class R> struct SiteClover<S, R, true> {
-    S x[72];
-    R sc;
-    __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale,
-                                         int64_t bp, int s, int Vbh) {
-        const S *p = base + bp * 72 * (int64_t)Vbh + s;
-#pragma unroll
-        for (int k = 0; k < 72; ++k) x[k] = p[(int64_t)k * Vbh];
-        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
-        else sc = (R)1;
+    CloverRegs<S, R> c;
+    __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale, int64_t bp,
+                                         int s, int Vbh) {
+        c.load(base, scale, bp, s, Vbh);
     }
-    __device__ __forceinline__ void get(R out[72]) const {
-#pragma unroll
-        for (int k = 0; k < 72; ++k) {
-            if constexpr (Storage<S>::scaled) out[k] = (R)(float)x[k] * sc;
-            else out[k] = (R)x[k];
-        }
-    }
+    __device__ __forceinline__ void mul(const R (&in)[24], R (&out)[24], R kx) const { clover_mul(c, in, out, kx); }
 };
 
 template <class S, class R> struct SiteClover<S, R, false> {
-    const S *p;
-    R sc;
-    int Vbh;
-    __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale,
-                                         int64_t bp, int s, int vbh) {
+    const S *base;
+    const float *scale;
+    int64_t bp;
+    int s, Vbh;
+    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ sc, int64_t bp_, int s_,
+                                         int vbh) {
+        base = b;
+        scale = sc;
+        bp = bp_;
+        s = s_;
         Vbh = vbh;
-        p = base + bp * 72 * (int64_t)Vbh + s;
-        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
-        else sc = (R)1;
     }
-    __device__ __forceinline__ void get(R out[72]) const {
-#pragma unroll
-        for (int k = 0; k < 72; ++k) {
-            if constexpr (Storage<S>::scaled) out[k] = (R)(float)p[(int64_t)k * Vbh] * sc;
-            else out[k] = (R)p[(int64_t)k * Vbh];
-        }
+    __device__ __forceinline__ void mul(const R (&in)[24], R (&out)[24], R kx) const {
+        CloverRegs<S, R> c;
+        c.load(base, scale, bp, s, Vbh);
+        clover_mul(c, in, out, kx);
     }
 };
 
 // In-block hopping term between the two parities, via LDS.
 //   Threads of parity `src` supply `in`. Threads of the other parity receive
 //   out = sum_mu [ (1 - gamma_mu) U_mu(x) in(x + mu) + (1 + gamma_mu) U_mu(x - mu)^+ in(x - mu) ]
-//   over the neighbours inside the block (hops leaving the block are dropped).
+//   over the neighbours inside the block (hops leaving the block are dropped); source
+//   threads leave `out` untouched.
 // Source threads store their spinor (for the forward hops of their backward neighbours)
 // and, for every in-block forward neighbour, the transported half spinor
 // U_mu(x)^+ (1 + gamma_mu) in(x); the receiving threads then need only their own links.
 // Every thread of the workgroup must call this; it contains two barriers.
+template <int MU, class BK, class R, class LK>
+__device__ __forceinline__ void push_dir(const SiteInfo &si, const LK &U, const R (&in)[24], R *__restrict__ hb) {
+    constexpr int Vbh = BK::Vbh;
+    if (si.fin & (1u << MU)) {
+        R h[12], uh[12], u[18];
+        project<MU, +1>(in, h);
+        U.template get<MU>(u);
+        su3_dag_mul(u, h, uh);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hb[(MU * 12 + k) * Vbh + si.s] = uh[k];
+    }
+}
+
+template <int MU, class BK, class R, class LK>
+__device__ __forceinline__ void pull_dir(const SiteInfo &si, const LK &U, R (&out)[24], const R *__restrict__ sp,
+                                         const R *__restrict__ hb) {
+    constexpr int Vbh = BK::Vbh;
+    if (si.fin & (1u << MU)) {
+        R chi[24], h[12], uh[12], u[18];
+        const int n = si.nbf[MU];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) chi[k] = sp[k * Vbh + n];
+        project<MU, -1>(chi, h);
+        U.template get<MU>(u);
+        su3_mul(u, h, uh);
+        accum_recon<MU, -1>(out, uh, (R)1);
+    }
+    if (si.bin & (1u << MU)) {
+        R uh[12];
+        const int n = si.nbb[MU];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) uh[k] = hb[(MU * 12 + k) * Vbh + n];
+        accum_recon<MU, +1>(out, uh, (R)1);
+    }
+}
+
 template <class BK, class R, class LK>
-__device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK &U, const R in[24], R out[24],
+__device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK &U, const R (&in)[24], R (&out)[24],
                                           R *__restrict__ sp, R *__restrict__ hb) {
     constexpr int Vbh = BK::Vbh;
     if (si.p == src) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) sp[k * Vbh + si.s] = in[k];
-        static_for<0, 4>([&](auto m) {
-            constexpr int MU = decltype(m)::value;
-            if (si.fin & (1u << MU)) {
-                R h[12], uh[12], u[18];
-                project<MU, +1>(in, h);
-                U.template get<MU>(u);
-                su3_dag_mul(u, h, uh);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) hb[(MU * 12 + k) * Vbh + si.s] = uh[k];
-            }
-        });
+        push_dir<0, BK>(si, U, in, hb);
+        push_dir<1, BK>(si, U, in, hb);
+        push_dir<2, BK>(si, U, in, hb);
+        push_dir<3, BK>(si, U, in, hb);
     }
     __syncthreads();
     if (si.p != src) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) out[k] = 0;
-        static_for<0, 4>([&](auto m) {
-            constexpr int MU = decltype(m)::value;
-            if (si.fin & (1u << MU)) {
-                R chi[24], h[12], uh[12], u[18];
-                const int n = si.nbf[MU];
-#pragma unroll
-                for (int k = 0; k < 24; ++k) chi[k] = sp[k * Vbh + n];
-                project<MU, -1>(chi, h);
-                U.template get<MU>(u);
-                su3_mul(u, h, uh);
-                accum_recon<MU, -1>(out, uh, (R)1);
-            }
-            if (si.bin & (1u << MU)) {
-                R uh[12];
-                const int n = si.nbb[MU];
-#pragma unroll
-                for (int k = 0; k < 12; ++k) uh[k] = hb[(MU * 12 + k) * Vbh + n];
-                accum_recon<MU, +1>(out, uh, (R)1);
-            }
-        });
+        pull_dir<0, BK>(si, U, out, sp, hb);
+        pull_dir<1, BK>(si, U, out, sp, hb);
+        pull_dir<2, BK>(si, U, out, sp, hb);
+        pull_dir<3, BK>(si, U, out, sp, hb);
     }
     __syncthreads();
 }

@@ -59,14 +59,11 @@ __device__ M3 link_at(const Geom &geo, const double *links, const int xin[4], in
     int64_t bp;
     int s;
     site_of(geo, x, bp, s);
-    const double *p = links + (bp * 72 + mu * 18) * (int64_t)geo.Vbh + s;
     M3 u;
-#pragma unroll
     for (int a = 0; a < 3; ++a)
-#pragma unroll
         for (int b = 0; b < 3; ++b) {
-            u.e[a][b].r = p[(int64_t)(2 * (3 * a + b)) * geo.Vbh];
-            u.e[a][b].i = p[(int64_t)(2 * (3 * a + b) + 1) * geo.Vbh];
+            u.e[a][b].r = links[real_index<double, 72>(bp, 18 * mu + 2 * (3 * a + b), s, geo.Vbh)];
+            u.e[a][b].i = links[real_index<double, 72>(bp, 18 * mu + 2 * (3 * a + b) + 1, s, geo.Vbh)];
         }
     return u;
 }

@@ -1,10 +1,12 @@
 // core.hpp - device-side building blocks shared by the sapdd kernels.
 //
-// * Block-tiled even-odd structure-of-arrays layout (the GPU re-make of the SoA layout
-//   of Sec. 3.2): for a field with `ncomp` reals per site, real k of the site with
-//   parity p and half-site index s in Schwarz block b lives at
-//       ((b * 2 + p) * ncomp + k) * Vbh + s,      Vbh = (sites per block) / 2.
-//   Lanes map to consecutive s, so every component is one coalesced run per block.
+// * Block-tiled even-odd layout, structure of short arrays (the GPU re-make of the SoA
+//   layout of Sec. 3.2): the reals of a site are grouped into 16-byte vectors of W reals
+//   (W = 2 doubles, 4 floats or 8 halves); for a field with N reals per site, vector v of
+//   the site with parity p and half-site index s in Schwarz block b is vector number
+//       ((b * 2 + p) * (N / W) + v) * Vbh + s,      Vbh = (sites per block) / 2.
+//   Lane s of a wave loads one whole vector per instruction and a wave reads 1 KB
+//   contiguous; the real and imaginary parts of a complex component are adjacent.
 //   In FP16 storage every site also carries one FP32 scale at (b * 2 + p) * Vbh + s.
 // * Spinor reals: index 2 * (3 * spin + colour) + (0 re, 1 im), 24 per site.
 //   Links: 4 directions x 18 reals, index 18 * mu + 2 * (3 * row + col) + re/im.
@@ -37,6 +39,33 @@ template <> struct Storage<half_t> {
     static constexpr int bytes = 2;
 };
 
+// 16-byte vector of a storage type: the unit one lane loads or stores.
+template <class S> struct Vec;
+template <> struct Vec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+};
+template <> struct Vec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+};
+template <> struct Vec<half_t> {
+    typedef half_t type __attribute__((ext_vector_type(8)));
+    static constexpr int W = 8;
+};
+
+// Index (in vectors) of vector v of site (bp, s) in a field of N reals per site.
+template <class S, int N>
+__host__ __device__ __forceinline__ int64_t vec_index(int64_t bp, int v, int s, int Vbh) {
+    static_assert(N % Vec<S>::W == 0, "field width must be a multiple of the vector width");
+    return (bp * (N / Vec<S>::W) + v) * (int64_t)Vbh + s;
+}
+// Index (in reals) of real k of site (bp, s).
+template <class S, int N>
+__host__ __device__ __forceinline__ int64_t real_index(int64_t bp, int k, int s, int Vbh) {
+    return vec_index<S, N>(bp, k / Vec<S>::W, s, Vbh) * Vec<S>::W + k % Vec<S>::W;
+}
+
 // A field in the block-tiled layout: data plus (FP16 only) per-site scales.
 template <class S> struct FieldPtr {
     S *data;
@@ -47,18 +76,34 @@ template <class S> struct CFieldPtr {
     const float *scale;
 };
 
+// Reals [K0, K0 + K) of site (bp, s) of an N-real field, through whole 16-byte vectors.
+template <class R, int N, int K0, int K, class S>
+__device__ __forceinline__ void load_reals(const S *__restrict__ data, const float *__restrict__ scale, int64_t bp,
+                                           int s, int Vbh, R out[K]) {
+    typedef typename Vec<S>::type VT;
+    constexpr int W = Vec<S>::W;
+    constexpr int v0 = K0 / W, v1 = (K0 + K - 1) / W;
+    const VT *p = reinterpret_cast<const VT *>(data);
+    R sc = (R)1;
+    if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
+#pragma unroll
+    for (int v = v0; v <= v1; ++v) {
+        const VT x = p[vec_index<S, N>(bp, v, s, Vbh)];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int k = v * W + w - K0;
+            if (k >= 0 && k < K) {
+                if constexpr (Storage<S>::scaled) out[k] = (R)(float)x[w] * sc;
+                else out[k] = (R)x[w];
+            }
+        }
+    }
+}
+
 template <class R, int N, class S>
 __device__ __forceinline__ void load_site(const S *__restrict__ data, const float *__restrict__ scale,
                                           int64_t bp, int s, int Vbh, R out[N]) {
-    const S *p = data + bp * (int64_t)N * Vbh + s;
-    if constexpr (Storage<S>::scaled) {
-        const R sc = (R)scale[bp * Vbh + s];
-#pragma unroll
-        for (int k = 0; k < N; ++k) out[k] = (R)(float)p[(int64_t)k * Vbh] * sc;
-    } else {
-#pragma unroll
-        for (int k = 0; k < N; ++k) out[k] = (R)p[(int64_t)k * Vbh];
-    }
+    load_reals<R, N, 0, N, S>(data, scale, bp, s, Vbh, out);
 }
 
 // Store N reals of one site; FP16 storage divides by the site's max |value| and rounds
@@ -66,7 +111,9 @@ __device__ __forceinline__ void load_site(const S *__restrict__ data, const floa
 template <class R, int N, class S>
 __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restrict__ scale, int64_t bp,
                                            int s, int Vbh, const R in[N]) {
-    S *p = data + bp * (int64_t)N * Vbh + s;
+    typedef typename Vec<S>::type VT;
+    constexpr int W = Vec<S>::W;
+    VT *p = reinterpret_cast<VT *>(data);
     if constexpr (Storage<S>::scaled) {
         float m = 0.f;
 #pragma unroll
@@ -74,10 +121,20 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
         scale[bp * Vbh + s] = m;
         const float inv = m > 0.f ? 1.0f / m : 0.f;
 #pragma unroll
-        for (int k = 0; k < N; ++k) p[(int64_t)k * Vbh] = (half_t)((float)in[k] * inv);
+        for (int v = 0; v < N / W; ++v) {
+            VT x;
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = (half_t)((float)in[v * W + w] * inv);
+            p[vec_index<S, N>(bp, v, s, Vbh)] = x;
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < N; ++k) p[(int64_t)k * Vbh] = (S)in[k];
+        for (int v = 0; v < N / W; ++v) {
+            VT x;
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = (S)in[v * W + w];
+            p[vec_index<S, N>(bp, v, s, Vbh)] = x;
+        }
     }
 }
 

@@ -91,13 +91,7 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
                 R chi[24], h[12], u[18], uh[12];
                 load_site<R, 24>(ind, ins, nbp, ns, Vbh, chi);
                 project<MU, -1>(chi, h);
-                {
-                    const S *lp = links.data + (bp * 72 + MU * 18) * (int64_t)Vbh + s;
-                    R sc = 1;
-                    if constexpr (Storage<S>::scaled) sc = (R)links.scale[bp * Vbh + s];
-#pragma unroll
-                    for (int q = 0; q < 18; ++q) u[q] = (R)lp[(int64_t)q * Vbh] * sc;
-                }
+                load_reals<R, 72, 18 * MU, 18>(links.data, links.scale, bp, s, Vbh, u);
                 su3_mul(u, h, uh);
                 accum_recon<MU, -1>(acc, uh, sg);
             }
@@ -114,28 +108,23 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
                 R chi[24], h[12], u[18], uh[12];
                 load_site<R, 24>(ind, ins, nbp, ns, Vbh, chi);
                 project<MU, +1>(chi, h);
-                {
-                    const S *lp = links.data + (nbp * 72 + MU * 18) * (int64_t)Vbh + ns;
-                    R sc = 1;
-                    if constexpr (Storage<S>::scaled) sc = (R)links.scale[nbp * Vbh + ns];
-#pragma unroll
-                    for (int q = 0; q < 18; ++q) u[q] = (R)lp[(int64_t)q * Vbh] * sc;
-                }
+                load_reals<R, 72, 18 * MU, 18>(links.data, links.scale, nbp, ns, Vbh, u);
                 su3_dag_mul(u, h, uh);
                 accum_recon<MU, +1>(acc, uh, sg);
             }
         });
-        R psi[24], tp[24], cl[72];
+        R psi[24], res[24];
         load_site<R, 24>(ind, ins, bp, s, Vbh, psi);
-        load_site<R, 72>(tclov.data, tclov.scale, bp, s, Vbh, cl);
-        clover_apply_k(cl, psi, (R)1, tp);  // T psi
-        R res[24];
+        CloverRegs<S, R> cl;
+        cl.load(tclov.data, tclov.scale, bp, s, Vbh);
+        clover_mul(cl, psi, res, kappa);  // (1 + kappa T) psi
 #pragma unroll
-        for (int c = 0; c < 24; ++c) res[c] = psi[c] + kappa * (tp[c] - acc[c]);
+        for (int c = 0; c < 24; ++c) res[c] -= kappa * acc[c];
         if (sub) {
-            const double *sb = sub + (int64_t)rhs * subs_ * geo.V * 24 + bp * 24 * (int64_t)Vbh + s;
+            double sb[24];
+            load_site<double, 24>(sub + (int64_t)rhs * subs_ * geo.V * 24, nullptr, bp, s, Vbh, sb);
 #pragma unroll
-            for (int c = 0; c < 24; ++c) res[c] = (R)sb[(int64_t)c * Vbh] - res[c];
+            for (int c = 0; c < 24; ++c) res[c] = (R)sb[c] - res[c];
         }
         store_site<R, 24>(out.data + ooff, out.scale ? out.scale + (int64_t)rhs * outs_ * geo.V : nullptr, bp, s, Vbh,
                           res);
@@ -233,15 +222,16 @@ __global__ __launch_bounds__(BK::NT) void dslash_block_kernel(Geom geo, CF<S> li
     const int64_t ioff = (int64_t)rhs * geo.V * 24, soff = (int64_t)rhs * geo.V;
     SiteLinks<S, R, true> U;
     U.init(links.data, links.scale, bp, si.s, Vbh);
-    R psi[24], h0[24], h1[24];
+    R psi[24], hop[24];
     load_site<R, 24>(in.data + ioff, in.scale ? in.scale + soff : nullptr, bp, si.s, Vbh, psi);
-    block_hop<BK>(0, si, U, psi, h0, sp, hb);  // odd sites receive
-    block_hop<BK>(1, si, U, psi, h1, sp, hb);  // even sites receive
-    R cl[72], tp[24], res[24];
-    load_site<R, 72>(tclov.data, tclov.scale, bp, si.s, Vbh, cl);
-    clover_apply_k(cl, psi, (R)1, tp);
+    block_hop<BK>(0, si, U, psi, hop, sp, hb);  // odd sites receive
+    block_hop<BK>(1, si, U, psi, hop, sp, hb);  // even sites receive
+    R res[24];
+    CloverRegs<S, R> cl;
+    cl.load(tclov.data, tclov.scale, bp, si.s, Vbh);
+    clover_mul(cl, psi, res, kappa);
 #pragma unroll
-    for (int c = 0; c < 24; ++c) res[c] = psi[c] + kappa * (tp[c] - (si.p ? h0[c] : h1[c]));
+    for (int c = 0; c < 24; ++c) res[c] -= kappa * hop[c];
     store_site<R, 24>(out.data + ioff, out.scale ? out.scale + soff : nullptr, bp, si.s, Vbh, res);
 }
 

@@ -83,7 +83,8 @@ hipError_t launch_sap_half(const Geom &geo, const SapArgsHost &a, int colour, in
                            hipStream_t st);
 
 // ---- FP64 Krylov kernels (blas.hip)
-// Vectors are complex FP64 in the block-tiled layout, n = 12 V complex entries each. For the
+// Vectors are complex FP64 in the block-tiled layout, n = 12 V complex entries each
+// (a flat complex array: the layout keeps real and imaginary parts adjacent). For the
 // rhs of slot q: basis vector i at vbase + rhs * rstride + i * vstride (doubles), stored
 // unnormalised with the factor vscale[rhs * vsstride + i]; w at w + rhs * wstride.
 struct CgsArgs {
@@ -100,7 +101,6 @@ struct CgsArgs {
     int nact;
     int v0, nv;          // basis vectors v0 .. v0 + nv - 1 (nv <= 16)
     int64_t n;
-    int vbh_shift;       // log2 of the half-block size Vbh
 };
 // Workgroups per rhs slot used by the Gram-Schmidt passes.
 int blas_partials(int64_t n, int nact);
@@ -118,6 +118,6 @@ hipError_t launch_reduce(const double *part, int nwg, int nval, const int *activ
 // z + (rhs * zstride_rhs + j * zstride_j) elements.
 hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, int64_t zstride_j,
                           int64_t zstride_rhs, const double *y, int ystride, int nz, const int *active, int nact,
-                          int64_t n, int vbh_shift, hipStream_t st);
+                          int64_t n, int vbh, hipStream_t st);
 
 }  // namespace sapdd

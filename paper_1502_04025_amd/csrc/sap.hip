@@ -41,6 +41,8 @@ template <class S, class P> struct SapArgs {
     P *psi;
     int64_t psi_stride;  // elements per rhs
     const int *active;
+    int nact;
+    int64_t nblk;  // blocks of one colour
     int colour, mode, write_state, nmr;
 };
 
@@ -69,130 +71,154 @@ __device__ __forceinline__ void block_sum3(R &a, R &b, R &c, R *red) {
     }
 }
 
-template <class BK, class S, class R, class P>
-__global__ __launch_bounds__(BK::NT) void sap_half_kernel(SapArgs<S, P> a) {
+// Register policy: whether a thread keeps its links / clover in registers for the whole
+// block solve (re-reading them from the L1/L2 caches otherwise).
+#ifndef SAPDD_SAP_CACHE_LINKS
+#define SAPDD_SAP_CACHE_LINKS 0
+#endif
+#ifndef SAPDD_SAP_CACHE_CLOVER
+#define SAPDD_SAP_CACHE_CLOVER 0
+#endif
+
+#ifndef SAPDD_SAP_WAVES_PER_EU
+#define SAPDD_SAP_WAVES_PER_EU 2
+#endif
+
+// Hops into site x across its block faces in direction mu, from the neighbouring blocks'
+// corrections delta: rho += kappa * [ (1 - gamma) U_mu(x) delta(x + mu) on the forward
+// face, (1 + gamma) U_mu(x - mu)^+ delta(x - mu) on the backward face ].
+template <int MU, class BK, class S, class P, class R, class LK>
+__device__ __forceinline__ void gather_dir(const SapArgs<S, P> &a, const SiteInfo &si, const LK &U, const int (&g)[4],
+                                           const S *dlt, const float *dlt_sc, R kappa, R (&rho)[24]) {
     constexpr int Vbh = BK::Vbh;
-    constexpr bool CACHE = sizeof(R) == 4;  // FP32 arithmetic: keep links and clover in registers
+    const Geom &geo = a.geo;
+    const int B[4] = {BK::bx, BK::by, BK::bz, BK::bt};
+    if (!(si.fin & (1u << MU))) {  // x + mu lies in the next block
+        int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
+        R sg = 1;
+        if (++gn[MU] == geo.G[MU]) {
+            gn[MU] = 0;
+            if (MU == 3 && geo.antiperiodic) sg = -1;
+        }
+        ln[MU] = 0;
+        const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
+        const int ns = local_half_index(B, ln);
+        R d[24], h[12], u[18], uh[12];
+        load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
+        project<MU, -1>(d, h);
+        U.template get<MU>(u);
+        su3_mul(u, h, uh);
+        accum_recon<MU, -1>(rho, uh, kappa * sg);
+    }
+    if (!(si.bin & (1u << MU))) {  // x - mu lies in the previous block
+        int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
+        R sg = 1;
+        if (--gn[MU] < 0) {
+            gn[MU] = geo.G[MU] - 1;
+            if (MU == 3 && geo.antiperiodic) sg = -1;
+        }
+        ln[MU] = B[MU] - 1;
+        const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
+        const int ns = local_half_index(B, ln);
+        R d[24], h[12], u[18], uh[12];
+        load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
+        load_reals<R, 72, 18 * MU, 18>(a.links, a.lscale, nbp, ns, Vbh, u);
+        project<MU, +1>(d, h);
+        su3_dag_mul(u, h, uh);
+        accum_recon<MU, +1>(rho, uh, kappa * sg);
+    }
+}
+
+template <class BK, class S, class R, class P>
+__global__ __launch_bounds__(BK::NT) __attribute__((amdgpu_waves_per_eu(SAPDD_SAP_WAVES_PER_EU)))
+void sap_half_kernel(SapArgs<S, P> a) {
+    constexpr int Vbh = BK::Vbh;
+    constexpr bool CACHE_L = sizeof(R) == 4 && SAPDD_SAP_CACHE_LINKS;
+    constexpr bool CACHE_X = sizeof(R) == 4 && SAPDD_SAP_CACHE_CLOVER;
     __shared__ R sp[24 * Vbh];
     __shared__ R hb[48 * Vbh];
     __shared__ R red[3 * BK::NW];
 
     const Geom &geo = a.geo;
     const SiteInfo si = site_info<BK>(threadIdx.x);
-    const int64_t b = colour_block(geo.G, a.colour, blockIdx.x);
-    const int rhs = a.active[blockIdx.y];
+    // Workgroup w runs on XCD w mod 8. Number the (block, rhs) pairs so that the nact
+    // right-hand sides of one block follow each other on the same XCD: the block's links
+    // and clover are then re-read from that XCD's L2 instead of HBM.
+    const int64_t w = blockIdx.x;
+    const int64_t kq = w >> 3;
+    const int slot = (int)(kq % a.nact);
+    const int64_t kb = (kq / a.nact) * 8 + (w & 7);
+    if (kb >= a.nblk) return;  // padding of the last group of 8 (uniform per workgroup)
+    const int64_t b = colour_block(geo.G, a.colour, kb);
+    const int rhs = a.active[slot];
     const int64_t bp = 2 * b + si.p;
     const R kappa = (R)a.kappa[rhs];
     const int64_t V = geo.V;
+    const bool even = si.p == 0;
 
-    SiteLinks<S, R, CACHE> U;
+    SiteLinks<S, R, CACHE_L> U;
     U.init(a.links, a.lscale, bp, si.s, Vbh);
-    SiteClover<S, R, CACHE> Xc;
+    SiteClover<S, R, CACHE_X> Xc;
     Xc.init(a.X[rhs], a.Xsc ? a.Xsc[rhs] : nullptr, bp, si.s, Vbh);
 
     S *dlt = a.delta + (int64_t)rhs * V * 24;
     float *dlt_sc = a.delta_sc ? a.delta_sc + (int64_t)rhs * V : nullptr;
 
-    // ---- 1. block residual
-    R rho[24];
+    // Per-thread spinors. Even sites: A = MR residual r, B = MR solution; odd sites:
+    // A = block residual rho_o. T and H are scratch (H receives the in-block hops).
+    R A[24], B[24], T[24], H[24];
+
+    // ---- 1. block residual rho into A
     if (a.mode < 2) {
-        const double *e = a.eta + rhs * a.eta_stride + bp * 24 * (int64_t)Vbh + si.s;
+        double e[24];
+        load_site<double, 24>(a.eta + rhs * a.eta_stride, nullptr, bp, si.s, Vbh, e);
         const double f = a.eta_scale ? a.eta_scale[(int64_t)rhs * a.eta_scale_stride] : 1.0;
 #pragma unroll
-        for (int k = 0; k < 24; ++k) rho[k] = (R)(e[(int64_t)k * Vbh] * f);
-    } else if (si.p == 0) {
+        for (int k = 0; k < 24; ++k) A[k] = (R)(e[k] * f);
+    } else if (even) {
         load_site<R, 24>(a.rres + (int64_t)rhs * V * 12, a.rres_sc ? a.rres_sc + (int64_t)rhs * (V / 2) : nullptr, b,
-                         si.s, Vbh, rho);
+                         si.s, Vbh, A);
     } else {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) rho[k] = 0;
+        for (int k = 0; k < 24; ++k) A[k] = 0;
     }
     if (a.mode >= 1) {
         // rho(x) -= sum_y M_{x,y} delta(y) over hops from neighbouring blocks: M = -kappa * hop there.
         int g[4];
         block_coords(geo.G, b, g);
-        const int B[4] = {BK::bx, BK::by, BK::bz, BK::bt};
-        static_for<0, 4>([&](auto m) {
-            constexpr int MU = decltype(m)::value;
-            if (!(si.fin & (1u << MU))) {  // x + mu lies in the next block
-                int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
-                R sg = 1;
-                if (++gn[MU] == geo.G[MU]) {
-                    gn[MU] = 0;
-                    if (MU == 3 && geo.antiperiodic) sg = -1;
-                }
-                ln[MU] = 0;
-                const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
-                const int ns = local_half_index(B, ln);
-                R d[24], h[12], u[18], uh[12];
-                load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
-                project<MU, -1>(d, h);
-                U.template get<MU>(u);
-                su3_mul(u, h, uh);
-                accum_recon<MU, -1>(rho, uh, kappa * sg);
-            }
-            if (!(si.bin & (1u << MU))) {  // x - mu lies in the previous block
-                int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
-                R sg = 1;
-                if (--gn[MU] < 0) {
-                    gn[MU] = geo.G[MU] - 1;
-                    if (MU == 3 && geo.antiperiodic) sg = -1;
-                }
-                ln[MU] = B[MU] - 1;
-                const int64_t nbp = 2 * block_index(geo.G, gn) + (1 - si.p);
-                const int ns = local_half_index(B, ln);
-                R d[24], h[12], u[18], uh[12];
-                load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
-                {
-                    const S *lp = a.links + (nbp * 72 + MU * 18) * (int64_t)Vbh + ns;
-                    R sc = 1;
-                    if constexpr (Storage<S>::scaled) sc = (R)a.lscale[nbp * Vbh + ns];
-#pragma unroll
-                    for (int q = 0; q < 18; ++q) u[q] = (R)lp[(int64_t)q * Vbh] * sc;
-                }
-                project<MU, +1>(d, h);
-                su3_dag_mul(u, h, uh);
-                accum_recon<MU, +1>(rho, uh, kappa * sg);
-            }
-        });
+        gather_dir<0, BK>(a, si, U, g, dlt, dlt_sc, kappa, A);
+        gather_dir<1, BK>(a, si, U, g, dlt, dlt_sc, kappa, A);
+        gather_dir<2, BK>(a, si, U, g, dlt, dlt_sc, kappa, A);
+        gather_dir<3, BK>(a, si, U, g, dlt, dlt_sc, kappa, A);
     }
 
-    // out = in + X in; X is re-expanded at each use to keep its live range short
-    auto capply = [&](const R in[24], R out[24]) {
-        R X[72];
-        Xc.get(X);
-        clover_apply(X, in, out);
-    };
-
-    // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o
-    R t[24], hop[24], r[24], xs[24];
-    if (si.p == 1) capply(rho, t);
-    block_hop<BK>(1, si, U, t, hop, sp, hb);
-    if (si.p == 0) {
+    // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o (odd: T = A_o^-1 rho_o)
+    if (!even) Xc.mul(A, T, (R)1);
+    block_hop<BK>(1, si, U, T, H, sp, hb);
+    if (even) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
-            r[k] = rho[k] + kappa * hop[k];
-            xs[k] = 0;
+            A[k] += kappa * H[k];
+            B[k] = 0;
         }
     }
 
     // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
     const R k2 = kappa * kappa;
     for (int it = 0; it < a.nmr; ++it) {
-        block_hop<BK>(0, si, U, r, hop, sp, hb);
-        if (si.p == 1) capply(hop, t);
-        block_hop<BK>(1, si, U, t, hop, sp, hb);
-        R p[24];
+        block_hop<BK>(0, si, U, A, H, sp, hb);  // odd: H = H_oe r
+        if (!even) Xc.mul(H, T, (R)1);          // odd: T = A_o^-1 H_oe r
+        block_hop<BK>(1, si, U, T, H, sp, hb);  // even: H = H_eo T
         R pr_re = 0, pr_im = 0, pp = 0;
-        if (si.p == 0) {
-            capply(r, p);
+        if (even) {
+            Xc.mul(A, T, (R)1);  // even: T = p = A_e r - kappa^2 H
 #pragma unroll
-            for (int k = 0; k < 24; ++k) p[k] -= k2 * hop[k];
+            for (int k = 0; k < 24; ++k) T[k] -= k2 * H[k];
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                pr_re += p[2 * k] * r[2 * k] + p[2 * k + 1] * r[2 * k + 1];
-                pr_im += p[2 * k] * r[2 * k + 1] - p[2 * k + 1] * r[2 * k];
-                pp += p[2 * k] * p[2 * k] + p[2 * k + 1] * p[2 * k + 1];
+                pr_re += T[2 * k] * A[2 * k] + T[2 * k + 1] * A[2 * k + 1];
+                pr_im += T[2 * k] * A[2 * k + 1] - T[2 * k + 1] * A[2 * k];
+                pp += T[2 * k] * T[2 * k] + T[2 * k + 1] * T[2 * k + 1];
             }
         }
         block_sum3<BK>(pr_re, pr_im, pp, red);
@@ -201,45 +227,42 @@ __global__ __launch_bounds__(BK::NT) void sap_half_kernel(SapArgs<S, P> a) {
             ar = pr_re / pp;
             ai = pr_im / pp;
         }
-        if (si.p == 0) {
+        if (even) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                const R rr = r[2 * k], ri = r[2 * k + 1];
-                const R qr = p[2 * k], qi = p[2 * k + 1];
-                xs[2 * k] += ar * rr - ai * ri;
-                xs[2 * k + 1] += ar * ri + ai * rr;
-                r[2 * k] = rr - (ar * qr - ai * qi);
-                r[2 * k + 1] = ri - (ar * qi + ai * qr);
+                const R rr = A[2 * k], ri = A[2 * k + 1];
+                const R qr = T[2 * k], qi = T[2 * k + 1];
+                B[2 * k] += ar * rr - ai * ri;
+                B[2 * k + 1] += ar * ri + ai * rr;
+                A[2 * k] = rr - (ar * qr - ai * qi);
+                A[2 * k + 1] = ri - (ar * qi + ai * qr);
             }
         }
     }
 
-    // ---- 4. delta_o = A_o^-1 (rho_o + kappa H_oe delta_e)
-    block_hop<BK>(0, si, U, xs, hop, sp, hb);
-    R dl[24];
-    if (si.p == 0) {
+    // ---- 4. delta: even B, odd A_o^-1 (rho_o + kappa H_oe delta_e)
+    block_hop<BK>(0, si, U, B, H, sp, hb);
+    if (!even) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) dl[k] = xs[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) t[k] = rho[k] + kappa * hop[k];
-        capply(t, dl);
+        for (int k = 0; k < 24; ++k) T[k] = A[k] + kappa * H[k];
+        Xc.mul(T, B, (R)1);  // odd: B = delta_o
     }
 
-    // ---- 5. outputs
-    P *ps = a.psi + rhs * a.psi_stride + bp * 24 * (int64_t)Vbh + si.s;
+    // ---- 5. outputs: psi += delta, keep delta and the even-site residual
+    P *ps = a.psi + rhs * a.psi_stride;
     if (a.mode == 2) {
+        load_site<R, 24>(ps, nullptr, bp, si.s, Vbh, T);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) ps[(int64_t)k * Vbh] = (P)((R)ps[(int64_t)k * Vbh] + dl[k]);
+        for (int k = 0; k < 24; ++k) T[k] += B[k];
+        store_site<R, 24>(ps, nullptr, bp, si.s, Vbh, T);
     } else {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) ps[(int64_t)k * Vbh] = (P)dl[k];
+        store_site<R, 24>(ps, nullptr, bp, si.s, Vbh, B);
     }
     if (a.write_state) {
-        store_site<R, 24>(dlt, dlt_sc, bp, si.s, Vbh, dl);
-        if (si.p == 0)
+        store_site<R, 24>(dlt, dlt_sc, bp, si.s, Vbh, B);
+        if (even)
             store_site<R, 24>(a.rres + (int64_t)rhs * V * 12, a.rres_sc ? a.rres_sc + (int64_t)rhs * (V / 2) : nullptr,
-                              b, si.s, Vbh, r);
+                              b, si.s, Vbh, A);
     }
 }
 
@@ -263,11 +286,15 @@ static hipError_t sap_typed(const Geom &geo, const SapArgsHost &h, int colour, i
     a.psi = (P *)h.psi;
     a.psi_stride = (int64_t)h.psi_stride_rhs * geo.V * 24;
     a.active = h.active;
+    a.nact = h.nact;
+    a.nblk = geo.Nd / 2;
     a.colour = colour;
     a.mode = mode;
     a.write_state = ws;
     a.nmr = h.nmr;
-    dim3 grid((unsigned)(geo.Nd / 2), (unsigned)h.nact);
+    const int64_t nwg = (geo.Nd / 2 + 7) / 8 * 8 * h.nact;
+    if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nwg);
     hipLaunchKernelGGL((sap_half_kernel<BK, S, R, P>), grid, dim3(BK::NT), 0, st, a);
     return hipGetLastError();
 }
