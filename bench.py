@@ -27,10 +27,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# name: (configuration, SAP storage precision, overrides)
 WORKLOADS = {
-    "c2": ("c2_16x16x16x32_f32", "f32", None),
-    "c2_f64": ("c2_16x16x16x32_f32", "f64", None),
-    "c3": ("c3_32x32x32x64_f16", "f16", None),
+    "c2": ("c2_16x16x16x32_f32", "f32", {}),
+    "c2_f64": ("c2_16x16x16x32_f32", "f64", {}),
+    "c3": ("c3_32x32x32x64_f16", "f16", {}),
+    "c3_f64_1rhs": ("c3_32x32x32x64_f16", "f64", {"nrhs": 1, "source": "gaussian"}),
+    "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 4}),
 }
 
 
@@ -150,12 +153,70 @@ def cpu_baseline(cfg, iters, restarts):
                        f"operator), scaled to {iters} outer iterations x {2 * ncy} half-sweeps")
 
 
+def run_serving(args):
+    """Serving stream: Poisson arrivals of 1-12 RHS solve requests on resident fields of
+    16^3x32, 24^3x48 and 32^3x64 (4^4 domains, FP16 SAP, FP64 FGMRES(16)), kappa uniform
+    in [0.120, 0.126]; admission by HBM budget, continuous batching per volume."""
+    import torch
+
+    import synthetic
+    from paper_1502_04025_amd import serving as sv
+    torch.cuda.init()
+    kw = dict(prec="f16", nmr=4, ncy=5, restart=16, tol=1e-10)
+    vols = [sv.TorchVolume(f"{'x'.join(map(str, d))}", d, (4, 4, 4, 4), 0.3, 14 + i, 1.0, 0, kw)
+            for i, d in enumerate(synthetic.SERVING_VOLUMES)]
+    plans = sv.plan_capacity([v.plan() for v in vols], int(args.hbm_budget_gb * 1e9), max_slots=16)
+    for v, p in zip(vols, plans):
+        v.start(p.capacity)
+
+    def serve(reqs, realtime):
+        workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity), None, None)
+                   for v, p in zip(vols, plans)]
+        srv = sv.Server(workers)
+        t0 = time.perf_counter()
+        done = srv.run(reqs, realtime=realtime)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = sv.summarize(done, wall)
+        out["steps"] = [w.steps for w in workers]
+        out["converged"] = all(all(st["converged"] for st in r.stats) for r in done if r.error is None)
+        return out
+
+    def stream_of(n, rate, seed):
+        rs = synthetic.serving_requests(n, rate=rate, seed=seed, volumes=synthetic.SERVING_VOLUMES)
+        return [sv.Request(r["id"], r["t_arrival"] if rate < 1e8 else 0.0, r["vol"], r["kappa"], r["nrhs"],
+                           r["seed"]) for r in rs]
+
+    serve(stream_of(6, 1e9, 30), False)  # warm up: graphs, clover inverses
+    sat = serve(stream_of(args.requests, 1e9, 31), False)  # closed loop: all at t = 0
+    runs = {}
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat["requests_per_s"]
+        runs[str(frac)] = dict(rate_req_s=round(rate, 4), **serve(stream_of(args.requests, rate, 32), True))
+    line = {
+        "metric": "Dslash HBM GB/s (% peak); SAP-FGMRES solves/s @ rel. residual 1e-10; p50/p99",
+        "value": round(sat["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": 6, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16+f64", "data": "synthetic",
+        "config": {"workload": "serving stream: Poisson arrivals, volumes 16^3x32 / 24^3x48 / 32^3x64 "
+                               "(4^4 domains, links exp(i 0.3 H), c_sw 1), kappa U[0.120,0.126], 1-12 "
+                               "Gaussian RHS, FP16 SAP + FP64 FGMRES(16) to 1e-10",
+                   "slots_per_volume": plans[0].capacity, "hbm_budget_gb": args.hbm_budget_gb},
+        "saturation": sat, "poisson": runs,
+    }
+    print(json.dumps(line), flush=True)
+    for v in vols:
+        v.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--requests", type=int, default=60, help="serve: requests per arrival rate")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: HBM budget for admission")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the Dslash/copy/FP64 side measurements")
     args = ap.parse_args()
@@ -170,11 +231,15 @@ def main():
     from paper_1502_04025_amd import Context
     from paper_1502_04025_amd import perfmodel as pm
 
-    name, prec, _ = WORKLOADS[args.workload]
+    if args.workload == "serve":
+        return run_serving(args)
+    name, prec, over = WORKLOADS[args.workload]
     cfg = dict(synthetic.CONFIGS[name])
-    nmr, ncy, restart, tol = 4, 5, 16, 1e-10
+    cfg.update(over)
+    nmr, ncy, restart, tol = 4, 5, cfg.get("restart", 16), 1e-10
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # a real stream: the SAP sweep replays from HIP graphs
+    torch.cuda.set_stream(stream)
     ctx = Context(0, stream=stream)
     u, field = make_field(ctx, cfg)
     b = torch.from_numpy(make_source(cfg)).cuda()

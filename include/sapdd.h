@@ -47,6 +47,7 @@ extern "C" {
 
 typedef struct sapdd_ctx sapdd_ctx;     /* device, stream, workspaces, last error      */
 typedef struct sapdd_field sapdd_field; /* one resident gauge field and its clover term */
+typedef struct sapdd_batch sapdd_batch; /* continuous-batching solver state (slots)    */
 
 enum {
     SAPDD_OK = 0,
@@ -55,7 +56,8 @@ enum {
     SAPDD_EDEVICE = -3,   /* HIP runtime error                                      */
     SAPDD_ENOCONV = -4,   /* solver hit max_iter; x and stats hold the best iterate */
     SAPDD_ESINGULAR = -5, /* a clover block 1 + kappa T is singular (pivot < 1e-12) */
-    SAPDD_ENAN = -6       /* NaN or Inf in a residual                               */
+    SAPDD_ENAN = -6,      /* NaN or Inf in a residual                               */
+    SAPDD_EFULL = -7      /* no free slot in a batch                                */
 };
 
 enum { SAPDD_F64 = 0, SAPDD_F32 = 1, SAPDD_F16 = 2 }; /* storage precisions */
@@ -126,13 +128,41 @@ int sapdd_apply_block_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, 
  * FP64 canonical in and out, internal storage params->sap_prec. */
 int sapdd_sap(sapdd_ctx *ctx, const sapdd_field *field, double kappa, const sapdd_params *params,
               int nrhs, const double *in, double *out);
-/* Solve M x = b for nrhs right-hand sides with SAP-preconditioned FGMRES(m) in FP64.
+/* Solve M x = b for nrhs right-hand sides with SAP-preconditioned FGMRES(m) in FP64
+ * (a batch of nrhs slots stepped to completion; the context keeps it for later calls).
  * kappa[nrhs] may differ per RHS. x holds nrhs canonical spinors (read as the start
  * vector if SAPDD_USE_X0). stats may be NULL, else it has nrhs entries. Returns
  * SAPDD_ENOCONV if some RHS missed tol within max_iter. */
 int sapdd_solve(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa,
                 const sapdd_params *params, int nrhs, const double *b, double *x,
                 sapdd_stats *stats);
+
+/* Continuous batching (the serving form of the solver). A batch holds up to `capacity`
+ * right-hand sides on one field, each with its own kappa and its own FP64 FGMRES(m)
+ * state. sapdd_batch_step runs one restart cycle for every unfinished slot: one SAP
+ * launch sequence (replayed from a HIP graph captured per slot count and Arnoldi step,
+ * unless SAPDD_NO_GRAPH), one operator launch and three Gram-Schmidt passes per Arnoldi
+ * step serve the whole batch, and a true FP64 residual at the end of the cycle decides
+ * convergence. Right-hand sides join with sapdd_batch_add and leave with
+ * sapdd_batch_take between steps. A slot's result does not depend on which other slots
+ * share the batch (slots are processed independently, reductions in a fixed order).
+ * The batch allocates its device memory at creation (sapdd_solve_footprint bytes for
+ * `capacity` RHS, clover inverses per kappa excluded) and uses the context's stream; a
+ * batch and its context belong to one host thread at a time. */
+int sapdd_batch_create(sapdd_ctx *ctx, const sapdd_field *field, const sapdd_params *params, int capacity,
+                       sapdd_batch **out);
+int sapdd_batch_destroy(sapdd_batch *batch);
+/* Admit one right-hand side b (canonical spinor; x0 = start vector or NULL for zero;
+ * flags: SAPDD_DEVICE_PTRS). Returns SAPDD_EFULL if every slot is taken. */
+int sapdd_batch_add(sapdd_batch *batch, double kappa, const double *b, const double *x0, int flags, int *slot);
+/* One restart cycle for every unfinished slot; *running = slots still unfinished. */
+int sapdd_batch_step(sapdd_batch *batch, int *running);
+/* 1 if the slot is finished (converged, failed or out of iterations), 0 if running;
+ * fills stats when not NULL. */
+int sapdd_batch_poll(const sapdd_batch *batch, int slot, sapdd_stats *stats);
+/* Copy the slot's solution to x (canonical; flags: SAPDD_DEVICE_PTRS), fill stats and
+ * free the slot. */
+int sapdd_batch_take(sapdd_batch *batch, int slot, double *x, int flags, sapdd_stats *stats);
 
 /* Bytes of device memory a solve of nrhs RHS with these parameters allocates on top of
  * the resident field (Krylov bases, SAP state, operator copies), for admission control. */

@@ -39,6 +39,7 @@ struct XEntry {  // SAP clover X for one (kappa, precision)
     int prec;
     Fld x;
     unsigned long long last_use;
+    int refs;  // batch slots using it; entries with refs > 0 are never evicted
 };
 
 }  // namespace
@@ -63,11 +64,11 @@ struct sapdd_ctx {
     char *pinned = nullptr;  // host staging for small transfers
     size_t pinned_n = 0;
     hipEvent_t ev[8] = {};
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // SAP sweep per (nact, j)
+    sapdd_batch *solve_batch = nullptr;  // kept between sapdd_solve calls
     // kernel profiling: event pairs recorded around launches, drained at sync points
     bool prof = false;
     std::vector<hipEvent_t> pev;
-    std::vector<int> pkind;
+    std::vector<int> pkind, pcount;
     size_t pn = 0;
     long long plaunch[SAPDD_K_COUNT] = {};
     double psec[SAPDD_K_COUNT] = {};
@@ -102,7 +103,7 @@ int prof_drain(sapdd_ctx *c) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
         c->psec[c->pkind[i]] += ms * 1e-3;
-        c->plaunch[c->pkind[i]] += 1;
+        c->plaunch[c->pkind[i]] += c->pcount[i];
     }
     c->pn = 0;
     return SAPDD_OK;
@@ -120,16 +121,20 @@ int prof_begin(sapdd_ctx *c, int kind) {
             const size_t old = c->pev.size();
             c->pev.resize(old ? 2 * old : 256);
             c->pkind.resize(c->pev.size() / 2);
+            c->pcount.resize(c->pev.size() / 2);
             for (size_t i = old; i < c->pev.size(); ++i) HIPCHK(c, hipEventCreate(&c->pev[i]));
         }
     }
     c->pkind[c->pn] = kind;
+    c->pcount[c->pn] = 1;
     HIPCHK(c, hipEventRecord(c->pev[2 * c->pn], c->stream));
     return SAPDD_OK;
 }
 
-int prof_end(sapdd_ctx *c) {
+// End a profiled region that contained `count` launches of its family (a graph replay).
+int prof_end(sapdd_ctx *c, int count = 1) {
     if (!c->prof) return SAPDD_OK;
+    c->pcount[c->pn] = count;
     HIPCHK(c, hipEventRecord(c->pev[2 * c->pn + 1], c->stream));
     c->pn += 1;
     return SAPDD_OK;
@@ -251,18 +256,23 @@ void free_fld(Fld &x) {
     x = Fld{};
 }
 
-// SAP clover X for (kappa, prec), cached on the field (a few entries, least recently used out).
-int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out) {
+// SAP clover X for (kappa, prec), cached on the field: at most 16 unreferenced entries
+// are kept, the least recently used one goes first. `ref` adds a reference that
+// sap_clover_release drops.
+int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, bool ref = false) {
     for (auto &e : f->xcache)
         if (e.kappa == kappa && e.prec == prec) {
             e.last_use = ++f->use_clock;
+            e.refs += ref ? 1 : 0;
             *out = e.x;
             return SAPDD_OK;
         }
     const size_t max_entries = 16;
-    if (f->xcache.size() >= max_entries) {
-        auto it = std::min_element(f->xcache.begin(), f->xcache.end(),
-                                   [](const XEntry &a, const XEntry &b) { return a.last_use < b.last_use; });
+    while (f->xcache.size() >= max_entries) {
+        auto it = f->xcache.end();
+        for (auto q = f->xcache.begin(); q != f->xcache.end(); ++q)
+            if (q->refs == 0 && (it == f->xcache.end() || q->last_use < it->last_use)) it = q;
+        if (it == f->xcache.end()) break;  // every entry in use: grow instead
         HIPCHK(c, hipStreamSynchronize(c->stream));
         free_fld(it->x);
         f->xcache.erase(it);
@@ -272,6 +282,7 @@ int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out) {
     e.kappa = kappa;
     e.prec = prec;
     e.last_use = ++f->use_clock;
+    e.refs = ref ? 1 : 0;
     size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
     const size_t sc_off = (bytes + 255) / 256 * 256;
     if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
@@ -290,6 +301,14 @@ int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out) {
     f->xcache.push_back(e);
     *out = e.x;
     return SAPDD_OK;
+}
+
+void sap_clover_release(sapdd_field *f, double kappa, int prec) {
+    for (auto &e : f->xcache)
+        if (e.kappa == kappa && e.prec == prec && e.refs > 0) {
+            e.refs -= 1;
+            return;
+        }
 }
 
 int check_params(sapdd_ctx *c, const sapdd_field *f, const sapdd_params *p) {
@@ -421,7 +440,7 @@ void sapdd_destroy(sapdd_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->solve_batch) sapdd_batch_destroy(c->solve_batch);
     for (auto &kv : c->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (c->d_flag) (void)hipFree(c->d_flag);
@@ -668,43 +687,379 @@ int sapdd_copy(sapdd_ctx *c, const void *src, void *dst, long long n) {
 
 }  // extern "C"
 
-// ====================================================================== FGMRES
+
+// ====================================================================== FGMRES batch
+// A batch holds up to `cap` right-hand sides (slots) on one field, each with its own
+// kappa and Krylov state. One step is one FGMRES(m) restart cycle for every active slot:
+// the SAP preconditioner, the FP64 operator and the Gram-Schmidt passes of the whole
+// batch run as single launches over the active slots, and the true FP64 residual at the
+// end of the cycle both decides convergence (the reliable update) and starts the next
+// cycle. Slots join (sapdd_batch_add) and leave (sapdd_batch_take) between steps, which
+// is what the serving loop's continuous batching uses. Every per-slot result is
+// independent of which other slots share the batch: kernels treat slots independently
+// and all reductions run in a fixed order.
 namespace {
 
 typedef std::complex<double> cd;
 
-struct RhsState {
-    int rhs;
-    double bnorm = 0, beta = 0, est = 0, true_relres = 0;
-    int iters = 0, restarts = 0, converged = 0, nz = 0;
-    bool in_cycle = false;
-    bool dirty = false;  // x changed since the last true residual
-    std::vector<cd> H;  // (m+1) x m column major: H[i + (m+1) j]
-    std::vector<cd> cs, sn, gv;
+struct Slot {
+    bool used = false, finished = false, ready = false, dirty = false, in_cycle = false;
+    double kappa = 0, bnorm = 0, beta = 0, est = 0, true_relres = 0;
+    int iters = 0, restarts = 0, converged = 0, nz = 0, status = SAPDD_OK;
+    std::vector<cd> H, cs, sn, gv;
 };
 
-struct Layout {
-    int m;
-    int CST;  // doubles per rhs in the coefficient block: h[2(m+1)], c[2(m+1)], nrm
-    int hoff, coff, noff;
+enum { SEG_CHECK = 0, SEG_CYCLE = 1, SEG_GROUP = 2, NSEG = 8 };
+
+}  // namespace
+
+struct sapdd_batch {
+    sapdd_ctx *c = nullptr;
+    sapdd_field *f = nullptr;
+    sapdd_params p{};
+    int cap = 0, m = 0, prec = 0, zprec = 0;
+    Geom g{};
+    int64_t NS = 0, ncx = 0;
+    Fld Vb{}, Zb{}, Bb{}, Xb{};
+    SapState ss{};
+    double *coef = nullptr, *vscale = nullptr, *part = nullptr, *ydev = nullptr;
+    int *dlists = nullptr;
+    char *pin = nullptr;
+    int *hlists = nullptr;
+    double *hcoef = nullptr, *hy = nullptr;
+    char *hmeta = nullptr;
+    int CST = 0, hoff = 0, coff = 0, noff = 0, nwg_d = 0;
+    bool use_graph = false;
+    std::vector<Slot> slots;
+    std::vector<void *> allocs;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    double t_sap = 0, t_d = 0, t_gs = 0, t_host = 0;
 };
 
-// Upload an int list into device segment `seg` of the list pool (pinned staging `host`).
-int upload_list(sapdd_ctx *c, int *dpool, int *hpool, int seg, int maxn, const std::vector<int> &v, int **out) {
-    for (size_t i = 0; i < v.size(); ++i) hpool[seg * maxn + i] = v[i];
-    HIPCHK(c, hipMemcpyAsync(dpool + seg * maxn, hpool + seg * maxn, v.size() * sizeof(int), hipMemcpyHostToDevice,
-                             c->stream));
-    *out = dpool + seg * maxn;
+namespace {
+
+int balloc(sapdd_batch *B, size_t bytes, void **out) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(B->c, SAPDD_ENOMEM, "hipMalloc of %zu bytes for a solver batch failed", bytes);
+    }
+    B->allocs.push_back(q);
+    *out = q;
     return SAPDD_OK;
+}
+
+int bfield(sapdd_batch *B, int nf, int prec, int ncomp, Fld *f) {
+    const size_t nd = (size_t)B->g.V * ncomp * nf;
+    size_t bytes = nd * prec_bytes(prec);
+    const size_t sc_off = (bytes + 255) / 256 * 256;
+    if (prec == P16) bytes = sc_off + (size_t)B->g.V * nf * sizeof(float);
+    void *q;
+    CHK(balloc(B, bytes, &q));
+    *f = Fld{q, prec == P16 ? (float *)((char *)q + sc_off) : nullptr, prec};
+    return SAPDD_OK;
+}
+
+int upload(sapdd_batch *B, int seg, const std::vector<int> &v, int **out) {
+    int *h = B->hlists + (size_t)seg * B->cap;
+    for (size_t i = 0; i < v.size(); ++i) h[i] = v[i];
+    int *d = B->dlists + (size_t)seg * B->cap;
+    HIPCHK(B->c, hipMemcpyAsync(d, h, v.size() * sizeof(int), hipMemcpyHostToDevice, B->c->stream));
+    *out = d;
+    return SAPDD_OK;
+}
+
+// Copy the coefficient blocks to the host and wait (the once-per-step sync point).
+int fetch_coef(sapdd_batch *B) {
+    sapdd_ctx *c = B->c;
+    HIPCHK(c, hipMemcpyAsync(B->hcoef, B->coef, (size_t)B->cap * B->CST * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->prof) CHK(prof_drain(c));
+    return SAPDD_OK;
+}
+
+// True residual r = b - M x of the listed slots into basis slot 0, |r|, vscale[0] = 1/|r|;
+// decides convergence (tol), failure (non-finite) and exhaustion (max_iter).
+int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
+    if (list.empty()) return SAPDD_OK;
+    sapdd_ctx *c = B->c;
+    int *d_list;
+    CHK(upload(B, SEG_CHECK, list, &d_list));
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    DslashIO io{};
+    io.in = B->Xb;
+    io.out = Fld{B->Vb.data, nullptr, P64};
+    io.sub = (const double *)B->Bb.data;
+    io.part = B->part;
+    io.active = d_list;
+    io.nact = (int)list.size();
+    io.in_stride = 1;
+    io.out_stride = B->m + 1;
+    io.sub_stride = 1;
+    io.kappa = B->ss.kappa;
+    KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(B->g, links_of(B->f, P64), tclov_of(B->f, P64), 0.0, io, c->stream));
+    KLAUNCH(c, SAPDD_K_DSLASH, launch_reduce(B->part, B->nwg_d, 1, d_list, io.nact, B->coef + B->noff, B->CST, nullptr,
+                                             0, 0, B->vscale, B->m + 1, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    CHK(fetch_coef(B));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    B->t_d += ms * 1e-3;
+    for (int r : list) {
+        Slot &s = B->slots[r];
+        s.dirty = false;
+        s.beta = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
+        s.true_relres = s.beta / s.bnorm;
+        s.ready = false;
+        if (!std::isfinite(s.beta)) {
+            s.status = SAPDD_ENAN;
+            s.finished = true;
+        } else if (s.true_relres <= B->p.tol) {
+            s.converged = 1;
+            s.finished = true;
+        } else if (s.iters >= B->p.max_iter) {
+            s.status = SAPDD_ENOCONV;
+            s.finished = true;
+        } else {
+            s.ready = true;
+        }
+    }
+    return SAPDD_OK;
+}
+
+// z_j = SAP(v_j) for the cycle list (device list in segment SEG_CYCLE, ncyc slots),
+// replayed from a graph captured once per (ncyc, j) when graphs are enabled.
+int batch_sap(sapdd_batch *B, int j, const int *d_cyc, int ncyc) {
+    sapdd_ctx *c = B->c;
+    const double *eta = (const double *)B->Vb.data + (size_t)j * B->NS;
+    void *psi = (char *)B->Zb.data + (size_t)j * B->NS * prec_bytes(B->zprec);
+    if (!B->use_graph)
+        return sap_run(c, B->g, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m, d_cyc, ncyc);
+    auto key = std::make_pair(ncyc, j);
+    auto it = B->graphs.find(key);
+    if (it == B->graphs.end()) {
+        const bool prof = c->prof;
+        c->prof = false;  // no event records inside the captured sequence
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int r = sap_run(c, B->g, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m, d_cyc,
+                        ncyc);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        c->prof = prof;
+        if (r != SAPDD_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        HIPCHK(c, e);
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, e);
+        it = B->graphs.emplace(key, exec).first;
+    }
+    CHK(prof_begin(c, SAPDD_K_SAP_HALF));
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    CHK(prof_end(c, 2 * B->p.ncy));
+    return SAPDD_OK;
+}
+
+// One FGMRES(m) restart cycle over every ready slot.
+int batch_cycle(sapdd_batch *B) {
+    sapdd_ctx *c = B->c;
+    const int m = B->m;
+    std::vector<int> cycle;
+    for (int r = 0; r < B->cap; ++r)
+        if (B->slots[r].used && !B->slots[r].finished && B->slots[r].ready) cycle.push_back(r);
+    if (cycle.empty()) return SAPDD_OK;
+    for (int r : cycle) {
+        Slot &s = B->slots[r];
+        std::fill(s.H.begin(), s.H.end(), 0.0);
+        std::fill(s.gv.begin(), s.gv.end(), 0.0);
+        s.gv[0] = s.beta;
+        s.in_cycle = true;
+        s.nz = 0;
+    }
+    const std::vector<int> members = cycle;
+    int *d_cyc;
+    CHK(upload(B, SEG_CYCLE, cycle, &d_cyc));
+    int ncyc = (int)cycle.size();
+    double *Vd = (double *)B->Vb.data;
+    const int nwg = blas_partials(B->ncx, ncyc);
+    for (int j = 0; j < m && ncyc > 0; ++j) {
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        CHK(batch_sap(B, j, d_cyc, ncyc));
+        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+        // w = M z_j into basis slot j + 1
+        DslashIO w{};
+        w.in = Fld{(char *)B->Zb.data + (size_t)j * B->NS * prec_bytes(B->zprec), nullptr, B->zprec};
+        w.out = Fld{Vd + (size_t)(j + 1) * B->NS, nullptr, P64};
+        w.active = d_cyc;
+        w.nact = ncyc;
+        w.in_stride = m;
+        w.out_stride = m + 1;
+        w.kappa = B->ss.kappa;
+        KLAUNCH(c, SAPDD_K_DSLASH,
+                launch_dslash_full(B->g, links_of(B->f, P64), tclov_of(B->f, P64), 0.0, w, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+        // classical Gram-Schmidt, twice: h = V^H w; w' = w - V h and c = V^H w' in one
+        // pass; w'' = w' - V c and |w''|^2 in one pass
+        CgsArgs a{};
+        a.vbase = Vd;
+        a.vstride = B->NS;
+        a.rstride = (int64_t)(m + 1) * B->NS;
+        a.vscale = B->vscale;
+        a.vsstride = m + 1;
+        a.w = Vd + (size_t)(j + 1) * B->NS;
+        a.wstride = (int64_t)(m + 1) * B->NS;
+        a.cstride = B->CST;
+        a.part = B->part;
+        a.active = d_cyc;
+        a.nact = ncyc;
+        a.n = B->ncx;
+        a.v0 = 0;
+        a.nv = j + 1;
+        KLAUNCH(c, SAPDD_K_GS, launch_cgs(0, a, c->stream));
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 2 * a.nv, d_cyc, ncyc, B->coef + B->hoff, B->CST,
+                                             B->vscale, m + 1, 0, nullptr, 0, c->stream));
+        a.coef = B->coef + B->hoff;
+        KLAUNCH(c, SAPDD_K_GS, launch_cgs(1, a, c->stream));
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 2 * a.nv, d_cyc, ncyc, B->coef + B->coff, B->CST,
+                                             B->vscale, m + 1, 0, nullptr, 0, c->stream));
+        a.coef = B->coef + B->coff;
+        KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 1, d_cyc, ncyc, B->coef + B->noff, B->CST, nullptr, 0, 0,
+                                             B->vscale + j + 1, m + 1, c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+        CHK(fetch_coef(B));
+        const double th = now_s();
+        {
+            float ms;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+            B->t_sap += ms * 1e-3;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+            B->t_d += ms * 1e-3;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+            B->t_gs += ms * 1e-3;
+        }
+        // host: Hessenberg column, Givens rotations, least-squares residual estimate
+        std::vector<int> still;
+        for (int r : cycle) {
+            Slot &s = B->slots[r];
+            const double *hc = B->hcoef + (size_t)r * B->CST;
+            cd *col = &s.H[(size_t)(m + 1) * j];
+            for (int i = 0; i <= j; ++i)
+                col[i] = cd(hc[B->hoff + 2 * i] + hc[B->coff + 2 * i], hc[B->hoff + 2 * i + 1] + hc[B->coff + 2 * i + 1]);
+            const double hn = std::sqrt(std::max(0.0, hc[B->noff]));
+            col[j + 1] = hn;
+            for (int i = 0; i < j; ++i) {
+                const cd t = std::conj(s.cs[i]) * col[i] + std::conj(s.sn[i]) * col[i + 1];
+                col[i + 1] = -s.sn[i] * col[i] + s.cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+            cd cj = 1.0, sj = 0.0;
+            if (den > 0) {
+                cj = col[j] / den;
+                sj = col[j + 1] / den;
+            }
+            s.cs[j] = cj;
+            s.sn[j] = sj;
+            col[j] = den;
+            col[j + 1] = 0.0;
+            s.gv[j + 1] = -sj * s.gv[j];
+            s.gv[j] = std::conj(cj) * s.gv[j];
+            s.est = std::abs(s.gv[j + 1]) / s.bnorm;
+            s.iters += 1;
+            s.nz = j + 1;
+            if (!std::isfinite(s.est) || den == 0.0) {  // the x update below is skipped for this slot
+                if (!std::isfinite(s.est)) s.status = SAPDD_ENAN;
+                s.in_cycle = false;
+                if (!std::isfinite(s.est)) s.nz = 0;
+                continue;
+            }
+            if (s.est <= B->p.tol || hn == 0.0 || s.iters >= B->p.max_iter) {
+                s.in_cycle = false;
+                continue;
+            }
+            still.push_back(r);
+        }
+        B->t_host += now_s() - th;
+        if (still.size() != (size_t)ncyc) {
+            cycle = still;
+            ncyc = (int)cycle.size();
+            if (ncyc) CHK(upload(B, SEG_CYCLE, cycle, &d_cyc));
+        }
+    }
+    // x += Z y, one launch per basis size
+    std::map<int, std::vector<int>> groups;
+    for (int r : members)
+        if (B->slots[r].nz > 0) groups[B->slots[r].nz].push_back(r);
+    for (auto &kv : groups) {
+        const int nz = kv.first;
+        for (int r : kv.second) {
+            Slot &s = B->slots[r];
+            std::vector<cd> y(nz);
+            for (int i = nz - 1; i >= 0; --i) {  // back substitution R y = g
+                cd t = s.gv[i];
+                for (int k = i + 1; k < nz; ++k) t -= s.H[(size_t)(m + 1) * k + i] * y[k];
+                const cd d = s.H[(size_t)(m + 1) * i + i];
+                y[i] = d != 0.0 ? t / d : 0.0;
+            }
+            for (int i = 0; i < nz; ++i) {
+                B->hy[(size_t)r * 2 * m + 2 * i] = y[i].real();
+                B->hy[(size_t)r * 2 * m + 2 * i + 1] = y[i].imag();
+            }
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(B->ydev, B->hy, (size_t)B->cap * 2 * m * 8, hipMemcpyHostToDevice, c->stream));
+    int seg = SEG_GROUP;
+    for (auto &kv : groups) {
+        if (seg == NSEG) {  // every staging segment in flight: let them land first
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            seg = SEG_GROUP;
+        }
+        int *d_grp;
+        CHK(upload(B, seg++, kv.second, &d_grp));
+        KLAUNCH(c, SAPDD_K_UPDATE, launch_zupdate((double *)B->Xb.data, B->NS, B->Zb.data, B->zprec, B->NS,
+                                                  (int64_t)m * B->NS, B->ydev, 2 * m, kv.first, d_grp,
+                                                  (int)kv.second.size(), B->ncx, B->g.Vbh, c->stream));
+    }
+    std::vector<int> check;
+    for (int r : members) {
+        Slot &s = B->slots[r];
+        s.restarts += 1;
+        s.in_cycle = false;
+        s.ready = false;
+        if (s.status == SAPDD_ENAN) {
+            s.finished = true;
+            continue;
+        }
+        if (s.nz > 0) s.dirty = true;
+        s.nz = 0;
+        check.push_back(r);
+    }
+    return batch_residual(B, check);
+}
+
+void batch_free(sapdd_batch *B) {
+    if (!B) return;
+    if (B->c) (void)hipStreamSynchronize(B->c->stream);
+    for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &s : B->slots)
+        if (s.used) sap_clover_release(B->f, s.kappa, B->prec);
+    for (void *q : B->allocs) (void)hipFree(q);
+    if (B->pin) (void)hipHostFree(B->pin);
+    delete B;
 }
 
 }  // namespace
 
-extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const sapdd_params *p, int nrhs,
-                           const double *b, double *x, sapdd_stats *stats) {
-    const double t0 = now_s();
-    if (!c || !fc || !kappa || !b || !x) return fail(c, SAPDD_EINVAL, "null argument");
-    if (nrhs < 1) return fail(c, SAPDD_EINVAL, "nrhs must be >= 1");
+extern "C" {
+
+int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *p, int cap, sapdd_batch **out) {
+    if (!c || !fc || !out) return fail(c, SAPDD_EINVAL, "null argument");
+    *out = nullptr;
     c->err.clear();
     HIPCHK(c, hipSetDevice(c->device));
     sapdd_field *f = const_cast<sapdd_field *>(fc);
@@ -712,399 +1067,274 @@ extern "C" int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *ka
     // the fused correct-and-dot Gram-Schmidt pass holds all basis vectors of a step at once
     if (p->restart < 1 || p->restart > 16) return fail(c, SAPDD_EINVAL, "restart must be in 1..16");
     if (!(p->tol > 0) || p->max_iter < 1) return fail(c, SAPDD_EINVAL, "tol must be > 0 and max_iter >= 1");
-    for (int r = 0; r < nrhs; ++r)
-        if (!(kappa[r] > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
-    const Geom &g = f->geo;
-    const int m = p->restart;
-    const int prec = p->sap_prec;
-    const int zprec = prec == P64 ? P64 : P32;
-    const int64_t NS = g.V * 24;  // doubles per spinor field
-    const int64_t ncx = g.V * 12; // complex entries per field
-    const int flags = p->flags;
-    const size_t nd = (size_t)NS * nrhs;
-
-    // ---- buffers
-    Fld Vb, Zb, Bb, Xb;
-    CHK(spinor_buf(c, "kry_V", g, nrhs * (m + 1), P64, 24, &Vb));
-    CHK(spinor_buf(c, "kry_Z", g, nrhs * m, zprec, 24, &Zb));
-    CHK(spinor_buf(c, "kry_b", g, nrhs, P64, 24, &Bb));
-    CHK(spinor_buf(c, "kry_x", g, nrhs, P64, 24, &Xb));
-    double *Vd = (double *)Vb.data, *Bd = (double *)Bb.data, *Xd = (double *)Xb.data;
-    SapState ss;
-    CHK(sap_prepare(c, f, kappa, nrhs, prec, &ss));
-    Layout L;
-    L.m = m;
-    L.hoff = 0;
-    L.coff = 2 * (m + 1);
-    L.noff = 4 * (m + 1);
-    L.CST = 4 * (m + 1) + 2;
-    const int nwg_d = dslash_full_partials(g);
-    const int nwg_b = std::max(blas_partials(ncx, nrhs), blas_partials(ncx, 1));
-    const int maxval = 32;
-    double *coef, *vscale, *part, *ydev;
-    {
-        void *q;
-        CHK(buf(c, "kry_coef", (size_t)nrhs * L.CST * 8, &q));
-        coef = (double *)q;
-        CHK(buf(c, "kry_vscale", (size_t)nrhs * (m + 1) * 8, &q));
-        vscale = (double *)q;
-        CHK(buf(c, "kry_part", (size_t)nrhs * std::max(nwg_d, nwg_b * maxval) * 8, &q));
-        part = (double *)q;
-        CHK(buf(c, "kry_y", (size_t)nrhs * 2 * m * 8, &q));
-        ydev = (double *)q;
+    if (cap < 1) return fail(c, SAPDD_EINVAL, "a batch needs at least one slot");
+    sapdd_batch *B = new sapdd_batch;
+    B->c = c;
+    B->f = f;
+    B->p = *p;
+    B->cap = cap;
+    B->m = p->restart;
+    B->prec = p->sap_prec;
+    B->zprec = B->prec == P64 ? P64 : P32;
+    B->g = f->geo;
+    B->NS = B->g.V * 24;
+    B->ncx = B->g.V * 12;
+    B->hoff = 0;
+    B->coff = 2 * (B->m + 1);
+    B->noff = 4 * (B->m + 1);
+    B->CST = 4 * (B->m + 1) + 2;
+    B->nwg_d = dslash_full_partials(B->g);
+    B->use_graph = !(p->flags & SAPDD_NO_GRAPH) && c->stream != nullptr;
+    B->slots.resize(cap);
+    for (auto &s : B->slots) {
+        s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
+        s.cs.assign(B->m, 0.0);
+        s.sn.assign(B->m, 0.0);
+        s.gv.assign(B->m + 1, 0.0);
     }
-    const int nseg = 8;
-    int *dlists;
-    {
-        void *q;
-        CHK(buf(c, "kry_lists", (size_t)nseg * nrhs * sizeof(int), &q));
-        dlists = (int *)q;
+    int r = SAPDD_OK;
+    void *q = nullptr;
+    const int nwg_b = blas_partials(B->ncx, 1);
+    const size_t meta_bytes = (size_t)cap * (2 * sizeof(void *) + sizeof(double));
+    do {
+        if ((r = lo_copies(c, f, B->prec)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap * (B->m + 1), P64, 24, &B->Vb)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap * B->m, B->zprec, 24, &B->Zb)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, P64, 24, &B->Bb)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, P64, 24, &B->Xb)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, B->prec, 12, &B->ss.rres)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, B->prec, 24, &B->ss.delta)) != SAPDD_OK) break;
+        if ((r = balloc(B, meta_bytes, &q)) != SAPDD_OK) break;
+        B->ss.X = (const void **)q;
+        B->ss.Xsc = (const float **)((char *)q + cap * sizeof(void *));
+        B->ss.kappa = (double *)((char *)q + 2 * cap * sizeof(void *));
+        B->ss.links = links_of(f, B->prec);
+        if ((r = balloc(B, (size_t)cap * B->CST * 8, &q)) != SAPDD_OK) break;
+        B->coef = (double *)q;
+        if ((r = balloc(B, (size_t)cap * (B->m + 1) * 8, &q)) != SAPDD_OK) break;
+        B->vscale = (double *)q;
+        if ((r = balloc(B, (size_t)cap * std::max(B->nwg_d, nwg_b * 32) * 8, &q)) != SAPDD_OK) break;
+        B->part = (double *)q;
+        if ((r = balloc(B, (size_t)cap * 2 * B->m * 8, &q)) != SAPDD_OK) break;
+        B->ydev = (double *)q;
+        if ((r = balloc(B, (size_t)NSEG * cap * sizeof(int), &q)) != SAPDD_OK) break;
+        B->dlists = (int *)q;
+        const size_t pin_bytes =
+            (size_t)NSEG * cap * sizeof(int) + (size_t)cap * B->CST * 8 + (size_t)cap * 2 * B->m * 8 + meta_bytes;
+        if (hipHostMalloc((void **)&B->pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            r = fail(c, SAPDD_ENOMEM, "pinned staging allocation failed");
+            break;
+        }
+        B->hlists = (int *)B->pin;
+        B->hcoef = (double *)(B->pin + (size_t)NSEG * cap * sizeof(int));
+        B->hy = B->hcoef + (size_t)cap * B->CST;
+        B->hmeta = (char *)(B->hy + (size_t)cap * 2 * B->m);
+        memset(B->hy, 0, (size_t)cap * 2 * B->m * 8);
+    } while (false);
+    if (r != SAPDD_OK) {
+        batch_free(B);
+        return r;
     }
-    const size_t pin_bytes = (size_t)nseg * nrhs * sizeof(int) + (size_t)nrhs * L.CST * 8 + (size_t)nrhs * 2 * m * 8;
-    void *pin;
-    CHK(pinned(c, pin_bytes, &pin));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    int *hlists = (int *)pin;
-    double *hcoef = (double *)((char *)pin + (size_t)nseg * nrhs * sizeof(int));
-    double *hy = hcoef + (size_t)nrhs * L.CST;
-    double *dkappa = ss.kappa;
+    *out = B;
+    return SAPDD_OK;
+}
 
-    // ---- inputs into the device layout
-    const double *bsrc;
-    CHK(stage_in(c, "stage_in", b, nd, flags, &bsrc));
-    HIPCHK(c, launch_pack(g, 24, nrhs, bsrc, Bb, c->stream));
-    if (flags & SAPDD_USE_X0) {
-        const double *xsrc;
-        CHK(stage_in(c, "stage_in2", x, nd, flags, &xsrc));
-        HIPCHK(c, launch_pack(g, 24, nrhs, xsrc, Xb, c->stream));
+int sapdd_batch_destroy(sapdd_batch *B) {
+    batch_free(B);
+    return SAPDD_OK;
+}
+
+int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double *x0, int flags, int *slot_out) {
+    if (!B || !b || !slot_out) return SAPDD_EINVAL;
+    sapdd_ctx *c = B->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!(kappa > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
+    int r = -1;
+    for (int q = 0; q < B->cap; ++q)
+        if (!B->slots[q].used) {
+            r = q;
+            break;
+        }
+    if (r < 0) return fail(c, SAPDD_EFULL, "no free slot in the batch (capacity %d)", B->cap);
+    Fld xf;
+    CHK(sap_clover(c, B->f, kappa, B->prec, &xf, true));
+    Slot &s = B->slots[r];
+    s = Slot();
+    s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
+    s.cs.assign(B->m, 0.0);
+    s.sn.assign(B->m, 0.0);
+    s.gv.assign(B->m + 1, 0.0);
+    s.used = true;
+    s.kappa = kappa;
+    // per-slot clover pointers and kappa for the kernels
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the pinned mirror may still feed a copy
+    const void **hx = (const void **)B->hmeta;
+    const float **hs = (const float **)(B->hmeta + B->cap * sizeof(void *));
+    double *hk = (double *)(B->hmeta + 2 * B->cap * sizeof(void *));
+    hx[r] = xf.data;
+    hs[r] = xf.scale;
+    hk[r] = kappa;
+    HIPCHK(c, hipMemcpyAsync((void *)(B->ss.X + r), hx + r, sizeof(void *), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((void *)(B->ss.Xsc + r), hs + r, sizeof(void *), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B->ss.kappa + r, hk + r, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // b and x into the device layout
+    const double *src;
+    CHK(stage_in(c, "stage_in", b, (size_t)B->NS, flags, &src));
+    Fld bslot{(double *)B->Bb.data + (size_t)r * B->NS, nullptr, P64};
+    HIPCHK(c, launch_pack(B->g, 24, 1, src, bslot, c->stream));
+    double *xslot = (double *)B->Xb.data + (size_t)r * B->NS;
+    if (x0) {
+        CHK(stage_in(c, "stage_in2", x0, (size_t)B->NS, flags, &src));
+        HIPCHK(c, launch_pack(B->g, 24, 1, src, Fld{xslot, nullptr, P64}, c->stream));
     } else {
-        HIPCHK(c, hipMemsetAsync(Xd, 0, nd * 8, c->stream));
+        HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
     }
+    // |b|
+    std::vector<int> one(1, r);
+    int *d_one;
+    CHK(upload(B, SEG_CHECK, one, &d_one));
+    CgsArgs a{};
+    a.w = (double *)B->Bb.data;
+    a.wstride = B->NS;
+    a.part = B->part;
+    a.active = d_one;
+    a.nact = 1;
+    a.nv = 0;
+    a.n = B->ncx;
+    KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
+    KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, blas_partials(B->ncx, 1), 1, d_one, 1, B->coef + B->noff, B->CST,
+                                         nullptr, 0, 0, nullptr, 0, c->stream));
+    CHK(fetch_coef(B));
+    s.bnorm = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
+    if (s.bnorm == 0.0) {
+        HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
+        s.finished = true;
+        s.converged = 1;
+    } else if (!std::isfinite(s.bnorm)) {
+        s.finished = true;
+        s.status = SAPDD_ENAN;
+    } else {
+        s.dirty = true;  // its first residual is computed by the next step
+    }
+    *slot_out = r;
+    return SAPDD_OK;
+}
 
-    std::vector<RhsState> st(nrhs);
-    std::vector<int> all(nrhs);
-    for (int r = 0; r < nrhs; ++r) {
-        all[r] = r;
-        st[r].rhs = r;
-        st[r].H.assign((size_t)(m + 1) * m, 0.0);
-        st[r].cs.assign(m, 0.0);
-        st[r].sn.assign(m, 0.0);
-        st[r].gv.assign(m + 1, 0.0);
-    }
-    int *d_all;
-    CHK(upload_list(c, dlists, hlists, 0, nrhs, all, &d_all));
-    // |b| per rhs
-    {
-        CgsArgs a{};
-        a.w = Bd;
-        a.wstride = NS;
-        a.part = part;
-        a.active = d_all;
-        a.nact = nrhs;
-        a.nv = 0;
-        a.n = ncx;
-        KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
-        KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, blas_partials(ncx, nrhs), 1, d_all, nrhs, coef + L.noff, L.CST, nullptr, 0, 0,
-                                nullptr, 0, c->stream));
-        HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int r = 0; r < nrhs; ++r) st[r].bnorm = std::sqrt(hcoef[(size_t)r * L.CST + L.noff]);
-    }
+int sapdd_batch_step(sapdd_batch *B, int *n_running) {
+    if (!B) return SAPDD_EINVAL;
+    sapdd_ctx *c = B->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<int> check;
+    for (int r = 0; r < B->cap; ++r)
+        if (B->slots[r].used && !B->slots[r].finished && B->slots[r].dirty) check.push_back(r);
+    CHK(batch_residual(B, check));
+    CHK(batch_cycle(B));
+    int n = 0;
+    for (auto &s : B->slots) n += s.used && !s.finished;
+    if (n_running) *n_running = n;
+    return SAPDD_OK;
+}
 
-    double t_sap = 0, t_d = 0, t_gs = 0, t_host = 0;
-    int status = SAPDD_OK;
-    std::vector<int> active;  // rhs still unconverged
-    for (int r = 0; r < nrhs; ++r) {
-        if (st[r].bnorm == 0.0) {
-            st[r].converged = 1;  // x = 0 solves b = 0
-        } else {
-            active.push_back(r);
-        }
+int sapdd_batch_poll(const sapdd_batch *B, int slot, sapdd_stats *st) {
+    if (!B || slot < 0 || slot >= B->cap || !B->slots[slot].used) return SAPDD_EINVAL;
+    const Slot &s = B->slots[slot];
+    if (st) {
+        st->iters = s.iters;
+        st->restarts = s.restarts;
+        st->converged = s.converged;
+        st->true_relres = s.true_relres;
+        st->implicit_relres = s.est;
+        st->t_total = 0;
+        st->t_sap = B->t_sap;
+        st->t_dslash = B->t_d;
+        st->t_gs = B->t_gs;
+        st->t_host = B->t_host;
     }
+    return s.finished ? 1 : 0;
+}
 
-    while (!active.empty()) {
-        int *d_act;
-        CHK(upload_list(c, dlists, hlists, 1, nrhs, active, &d_act));
-        const int nact = (int)active.size();
-        // ---- true residual r = b - M x into basis slot 0, |r|^2, vscale[0] = 1/|r|
-        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-        DslashIO io{};
-        io.in = Xb;
-        io.out = Fld{Vd, nullptr, P64};
-        io.sub = Bd;
-        io.part = part;
-        io.active = d_act;
-        io.nact = nact;
-        io.in_stride = 1;
-        io.out_stride = m + 1;
-        io.sub_stride = 1;
-        io.kappa = dkappa;
-        KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
-        KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg_d, 1, d_act, nact, coef + L.noff, L.CST, nullptr, 0, 0, vscale, m + 1,
-                                c->stream));
-        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
-        HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->prof) CHK(prof_drain(c));
-        {
-            float ms;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-            t_d += ms * 1e-3;
-        }
-        std::vector<int> cycle;
-        for (int r : active) {
-            RhsState &s = st[r];
-            s.dirty = false;
-            s.beta = std::sqrt(hcoef[(size_t)r * L.CST + L.noff]);
-            s.true_relres = s.beta / s.bnorm;
-            if (!std::isfinite(s.beta)) {
-                status = fail(c, SAPDD_ENAN, "non-finite residual for rhs %d", r);
-                continue;
-            }
-            if (s.true_relres <= p->tol) {
-                s.converged = 1;
-                continue;
-            }
-            if (s.iters >= p->max_iter) continue;
-            cycle.push_back(r);
-        }
-        if (status != SAPDD_OK) break;
-        // unconverged rhs out of iterations leave the active set
-        std::vector<int> next_active;
-        for (int r : active)
-            if (!st[r].converged && st[r].iters < p->max_iter) next_active.push_back(r);
-        active = next_active;
-        if (cycle.empty()) break;
-        for (int r : cycle) {
-            RhsState &s = st[r];
-            std::fill(s.H.begin(), s.H.end(), 0.0);
-            std::fill(s.gv.begin(), s.gv.end(), 0.0);
-            s.gv[0] = s.beta;
-            s.in_cycle = true;
-            s.nz = 0;
-        }
-        int *d_cyc;
-        CHK(upload_list(c, dlists, hlists, 2, nrhs, cycle, &d_cyc));
-        int ncyc = (int)cycle.size();
-        for (int j = 0; j < m && ncyc > 0; ++j) {
-            // ---- z_j = SAP(v_j)
-            HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-            CHK(sap_run(c, g, ss, p, Vd + (size_t)j * NS, m + 1, vscale + j, m + 1,
-                        (char *)Zb.data + (size_t)j * NS * prec_bytes(zprec), zprec, m, d_cyc, ncyc));
-            HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
-            // ---- w = M z_j into basis slot j + 1
-            DslashIO w{};
-            w.in = Fld{(char *)Zb.data + (size_t)j * NS * prec_bytes(zprec), nullptr, zprec};
-            w.out = Fld{Vd + (size_t)(j + 1) * NS, nullptr, P64};
-            w.active = d_cyc;
-            w.nact = ncyc;
-            w.in_stride = m;
-            w.out_stride = m + 1;
-            w.kappa = dkappa;
-            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, w, c->stream));
-            HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-            // ---- CGS2 against v_0 .. v_j
-            CgsArgs a{};
-            a.vbase = Vd;
-            a.vstride = NS;
-            a.rstride = (int64_t)(m + 1) * NS;
-            a.vscale = vscale;
-            a.vsstride = m + 1;
-            a.w = Vd + (size_t)(j + 1) * NS;
-            a.wstride = (int64_t)(m + 1) * NS;
-            a.cstride = L.CST;
-            a.part = part;
-            a.active = d_cyc;
-            a.nact = ncyc;
-            a.n = ncx;
-                const int nwg = blas_partials(ncx, ncyc);
-            for (int pass = 0; pass < 2; ++pass) {
-                // pass 0: h = V^H w (then w -= V h in the next launch); pass 1: c = V^H w'
-                const int outoff = pass == 0 ? L.hoff : L.coff;
-                for (int v0 = 0; v0 <= j; v0 += 16) {
-                    a.v0 = v0;
-                    a.nv = std::min(16, j + 1 - v0);
-                    if (pass == 0) {
-                        KLAUNCH(c, SAPDD_K_GS, launch_cgs(0, a, c->stream));
-                    } else {
-                        a.coef = coef + L.hoff;
-                        KLAUNCH(c, SAPDD_K_GS, launch_cgs(1, a, c->stream));
-                    }
-                    KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg, 2 * a.nv, d_cyc, ncyc, coef + outoff + 2 * v0, L.CST, vscale,
-                                            m + 1, v0, nullptr, 0, c->stream));
-                }
-            }
-            // w'' = w' - V c, |w''|^2, vscale[j+1] = 1/|w''|
-            a.coef = coef + L.coff;
-            a.v0 = 0;
-            a.nv = j + 1;
-            KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
-            KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg, 1, d_cyc, ncyc, coef + L.noff, L.CST, nullptr, 0, 0, vscale + j + 1,
-                                    m + 1, c->stream));
-            HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
-            HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            if (c->prof) CHK(prof_drain(c));
-            const double th = now_s();
-            {
-                float ms;
-                HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-                t_sap += ms * 1e-3;
-                HIPCHK(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
-                t_d += ms * 1e-3;
-                HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-                t_gs += ms * 1e-3;
-            }
-            // ---- host: Hessenberg column, Givens rotation, residual estimate
-            std::vector<int> still;
-            for (int r : cycle) {
-                RhsState &s = st[r];
-                if (!s.in_cycle) continue;
-                const double *hc = hcoef + (size_t)r * L.CST;
-                cd *col = &s.H[(size_t)(m + 1) * j];
-                for (int i = 0; i <= j; ++i)
-                    col[i] = cd(hc[L.hoff + 2 * i] + hc[L.coff + 2 * i], hc[L.hoff + 2 * i + 1] + hc[L.coff + 2 * i + 1]);
-                const double hn = std::sqrt(std::max(0.0, hc[L.noff]));
-                col[j + 1] = hn;
-                for (int i = 0; i < j; ++i) {  // previous rotations
-                    const cd t = std::conj(s.cs[i]) * col[i] + std::conj(s.sn[i]) * col[i + 1];
-                    col[i + 1] = -s.sn[i] * col[i] + s.cs[i] * col[i + 1];
-                    col[i] = t;
-                }
-                const double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
-                cd cj = 1.0, sj = 0.0;
-                if (den > 0) {
-                    cj = col[j] / den;
-                    sj = col[j + 1] / den;
-                }
-                s.cs[j] = cj;
-                s.sn[j] = sj;
-                col[j] = den;
-                col[j + 1] = 0.0;
-                s.gv[j + 1] = -sj * s.gv[j];
-                s.gv[j] = std::conj(cj) * s.gv[j];
-                s.est = std::abs(s.gv[j + 1]) / s.bnorm;
-                s.iters += 1;
-                s.nz = j + 1;
-                if (!std::isfinite(s.est)) {
-                    status = fail(c, SAPDD_ENAN, "non-finite Arnoldi coefficients for rhs %d", r);
-                    s.in_cycle = false;
-                    continue;
-                }
-                if (s.est <= p->tol || hn == 0.0 || den == 0.0 || s.iters >= p->max_iter) {
-                    s.in_cycle = false;
-                    continue;
-                }
-                still.push_back(r);
-            }
-            t_host += now_s() - th;
-            if (status != SAPDD_OK) break;
-            if (still.size() != (size_t)ncyc) {
-                cycle = still;
-                ncyc = (int)cycle.size();
-                if (ncyc) CHK(upload_list(c, dlists, hlists, 2 + ((j + 1) % 2), nrhs, cycle, &d_cyc));
-            }
-        }
-        if (status != SAPDD_OK) break;
-        // ---- x += Z y for every rhs that took part in this cycle, grouped by basis size
-        std::map<int, std::vector<int>> groups;
-        for (int r : all)
-            if (st[r].nz > 0) groups[st[r].nz].push_back(r);
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        int seg = 4;
-        for (auto &kv : groups) {
-            const int nz = kv.first;
-            for (int r : kv.second) {
-                RhsState &s = st[r];
-                // back substitution R y = g
-                std::vector<cd> y(nz);
-                for (int i = nz - 1; i >= 0; --i) {
-                    cd t = s.gv[i];
-                    for (int k = i + 1; k < nz; ++k) t -= s.H[(size_t)(m + 1) * k + i] * y[k];
-                    const cd d = s.H[(size_t)(m + 1) * i + i];
-                    y[i] = d != 0.0 ? t / d : 0.0;
-                }
-                for (int i = 0; i < nz; ++i) {
-                    hy[(size_t)r * 2 * m + 2 * i] = y[i].real();
-                    hy[(size_t)r * 2 * m + 2 * i + 1] = y[i].imag();
-                }
-                s.restarts += 1;
-                s.nz = 0;
-                s.dirty = true;
-            }
-        }
-        HIPCHK(c, hipMemcpyAsync(ydev, hy, (size_t)nrhs * 2 * m * 8, hipMemcpyHostToDevice, c->stream));
-        for (auto &kv : groups) {
-            int *d_grp;
-            CHK(upload_list(c, dlists, hlists, seg, nrhs, kv.second, &d_grp));
-            seg = seg + 1 < nseg ? seg + 1 : 4;
-            KLAUNCH(c, SAPDD_K_UPDATE, launch_zupdate(Xd, NS, Zb.data, zprec, NS, (int64_t)m * NS, ydev, 2 * m, kv.first, d_grp,
-                                     (int)kv.second.size(), ncx, g.Vbh, c->stream));
-            if (seg == 4) HIPCHK(c, hipStreamSynchronize(c->stream));
-        }
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
-
-    // ---- final true residuals for the record (rhs that stopped without a final check)
-    {
-        std::vector<int> chk;
-        for (int r = 0; r < nrhs; ++r)
-            if (st[r].bnorm > 0 && st[r].dirty) chk.push_back(r);
-        if (!chk.empty()) {
-            int *d_chk;
-            CHK(upload_list(c, dlists, hlists, 1, nrhs, chk, &d_chk));
-            DslashIO io{};
-            io.in = Xb;
-            io.out = Fld{Vd, nullptr, P64};
-            io.sub = Bd;
-            io.part = part;
-            io.active = d_chk;
-            io.nact = (int)chk.size();
-            io.in_stride = 1;
-            io.out_stride = m + 1;
-            io.sub_stride = 1;
-            io.kappa = dkappa;
-            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), 0.0, io, c->stream));
-            KLAUNCH(c, SAPDD_K_GS, launch_reduce(part, nwg_d, 1, d_chk, io.nact, coef + L.noff, L.CST, nullptr, 0, 0, nullptr, 0,
-                                    c->stream));
-            HIPCHK(c, hipMemcpyAsync(hcoef, coef, (size_t)nrhs * L.CST * 8, hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            for (int r : chk) {
-                st[r].true_relres = std::sqrt(hcoef[(size_t)r * L.CST + L.noff]) / st[r].bnorm;
-                st[r].converged = st[r].true_relres <= p->tol;
-                st[r].dirty = false;
-            }
-        }
-    }
-    // ---- x back to the canonical layout
+int sapdd_batch_take(sapdd_batch *B, int slot, double *x, int flags, sapdd_stats *st) {
+    if (!B || !x || slot < 0 || slot >= B->cap || !B->slots[slot].used) return SAPDD_EINVAL;
+    sapdd_ctx *c = B->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    Slot &s = B->slots[slot];
+    sapdd_batch_poll(B, slot, st);
     double *dst = x;
     if (!(flags & SAPDD_DEVICE_PTRS)) {
         void *d;
-        CHK(buf(c, "stage_out", nd * 8, &d));
+        CHK(buf(c, "stage_out", (size_t)B->NS * 8, &d));
         dst = (double *)d;
     }
-    HIPCHK(c, launch_unpack(g, 24, nrhs, Xb, dst, c->stream));
-    if (!(flags & SAPDD_DEVICE_PTRS)) HIPCHK(c, hipMemcpyAsync(x, dst, nd * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, launch_unpack(B->g, 24, 1, Fld{(double *)B->Xb.data + (size_t)slot * B->NS, nullptr, P64}, dst,
+                            c->stream));
+    if (!(flags & SAPDD_DEVICE_PTRS))
+        HIPCHK(c, hipMemcpyAsync(x, dst, (size_t)B->NS * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double t1 = now_s();
-    bool all_conv = true;
-    for (int r = 0; r < nrhs; ++r) {
-        all_conv = all_conv && st[r].converged;
-        if (stats) {
-            sapdd_stats &o = stats[r];
-            o.iters = st[r].iters;
-            o.restarts = st[r].restarts;
-            o.converged = st[r].converged;
-            o.true_relres = st[r].true_relres;
-            o.implicit_relres = st[r].est;
-            o.t_total = t1 - t0;
-            o.t_sap = t_sap;
-            o.t_dslash = t_d;
-            o.t_gs = t_gs;
-            o.t_host = t_host;
-        }
-    }
-    if (status != SAPDD_OK) return status;
-    if (!all_conv) return fail(c, SAPDD_ENOCONV, "not converged within max_iter = %d", p->max_iter);
+    const int status = s.status;
+    sap_clover_release(B->f, s.kappa, B->prec);
+    s = Slot();
+    s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
+    s.cs.assign(B->m, 0.0);
+    s.sn.assign(B->m, 0.0);
+    s.gv.assign(B->m + 1, 0.0);
+    if (status == SAPDD_ENAN) return fail(c, SAPDD_ENAN, "non-finite residual in slot %d", slot);
     return SAPDD_OK;
 }
+
+// Solve = one batch holding every right-hand side, stepped until all are finished. The
+// context keeps the batch between calls with compatible arguments, so repeated solves
+// allocate nothing.
+int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const sapdd_params *p, int nrhs,
+                const double *b, double *x, sapdd_stats *stats) {
+    const double t0 = now_s();
+    if (!c || !fc || !kappa || !b || !x || !p) return fail(c, SAPDD_EINVAL, "null argument");
+    if (nrhs < 1) return fail(c, SAPDD_EINVAL, "nrhs must be >= 1");
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    sapdd_batch *B = c->solve_batch;
+    const bool reuse = B && B->f == fc && B->cap >= nrhs && B->p.restart == p->restart && B->p.nmr == p->nmr &&
+                       B->p.ncy == p->ncy && B->p.sap_prec == p->sap_prec &&
+                       ((B->p.flags ^ p->flags) & SAPDD_NO_GRAPH) == 0;
+    if (reuse) {  // a call that failed half way may have left slots behind
+        for (int r = 0; r < B->cap; ++r)
+            if (B->slots[r].used) {
+                sap_clover_release(B->f, B->slots[r].kappa, B->prec);
+                B->slots[r].used = false;
+            }
+    } else {
+        if (B) batch_free(B);
+        c->solve_batch = nullptr;
+        sapdd_params q = *p;
+        CHK(sapdd_batch_create(c, fc, &q, nrhs, &B));
+        c->solve_batch = B;
+    }
+    B->p.tol = p->tol;
+    B->p.max_iter = p->max_iter;
+    B->t_sap = B->t_d = B->t_gs = B->t_host = 0;
+    const size_t NS = (size_t)B->NS;
+    std::vector<int> slot(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        CHK(sapdd_batch_add(B, kappa[r], b + r * NS, (p->flags & SAPDD_USE_X0) ? x + r * NS : nullptr,
+                            p->flags & SAPDD_DEVICE_PTRS, &slot[r]));
+    }
+    int running = nrhs;
+    while (running > 0) CHK(sapdd_batch_step(B, &running));
+    int status = SAPDD_OK;
+    const double t1 = now_s();
+    for (int r = 0; r < nrhs; ++r) {
+        sapdd_stats st;
+        const int rc = sapdd_batch_take(B, slot[r], x + r * NS, p->flags & SAPDD_DEVICE_PTRS, &st);
+        st.t_total = t1 - t0;
+        if (stats) stats[r] = st;
+        if (rc != SAPDD_OK) status = rc;
+        else if (!st.converged && status == SAPDD_OK) status = SAPDD_ENOCONV;
+    }
+    if (status == SAPDD_ENOCONV) return fail(c, SAPDD_ENOCONV, "not converged within max_iter = %d", p->max_iter);
+    return status;
+}
+
+}  // extern "C"

@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsapdd.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16 = 0, 1, 2
 DEVICE_PTRS, USE_X0, NO_GRAPH = 1, 2, 4
 PRECS = {"f64": F64, "f32": F32, "f16": F16}
@@ -30,7 +30,8 @@ EXPORTS = (
     "sapdd_create", "sapdd_destroy", "sapdd_last_error", "sapdd_load_gauge",
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
     "sapdd_apply_block_D", "sapdd_sap", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
-    "sapdd_profile",
+    "sapdd_profile", "sapdd_batch_create", "sapdd_batch_destroy", "sapdd_batch_add",
+    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_take",
 )
 KERNELS = ("sap_half", "dslash", "gram_schmidt", "block_dslash", "update", "copy")
 
@@ -93,6 +94,12 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_solve_footprint.restype = C.c_longlong
     lib.sapdd_copy.argtypes = [VP, VP, VP, C.c_longlong]
     lib.sapdd_profile.argtypes = [VP, I, P(KernelProfile)]
+    lib.sapdd_batch_create.argtypes = [VP, VP, P(Params), I, P(VP)]
+    lib.sapdd_batch_destroy.argtypes = [VP]
+    lib.sapdd_batch_add.argtypes = [VP, D, VP, VP, I, P(I)]
+    lib.sapdd_batch_step.argtypes = [VP, P(I)]
+    lib.sapdd_batch_poll.argtypes = [VP, I, P(Stats)]
+    lib.sapdd_batch_take.argtypes = [VP, I, VP, I, P(Stats)]
     for name in EXPORTS:
         if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint"):
             getattr(lib, name).restype = I
@@ -277,3 +284,65 @@ class Field:
         if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
             self.ctx._check(rc)
         return SolveResult(x, [s.as_dict() for s in stats], rc)
+
+
+class Batch:
+    """Continuous-batching solver on one field (sapdd_batch_*): slots join with add(),
+    every step() runs one FGMRES restart cycle for all unfinished slots, finished slots
+    leave with take()."""
+
+    def __init__(self, field: "Field", capacity: int, **kw):
+        self.field = field
+        self.ctx = field.ctx
+        prm = field.params(**kw)
+        self.prm = prm
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.sapdd_batch_create(self.ctx.h, field.h, C.byref(prm), int(capacity),
+                                                        C.byref(h)))
+        self.h = h
+        self.capacity = int(capacity)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sapdd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.ctx.h:
+                self.close()
+        except Exception:
+            pass
+
+    def add(self, kappa: float, b, x0=None) -> int:
+        """Admit one right-hand side (canonical spinor [t,z,y,x,4,3]); returns its slot.
+        Raises SapddError with code EFULL when every slot is taken."""
+        pb, dev = _ptr(b)
+        px = C.c_void_p(0)
+        if x0 is not None:
+            px, _ = _ptr(x0)
+        slot = C.c_int()
+        self.ctx._check(self.ctx.lib.sapdd_batch_add(self.h, float(kappa), pb, px, DEVICE_PTRS if dev else 0,
+                                                     C.byref(slot)))
+        return slot.value
+
+    def step(self) -> int:
+        """One restart cycle for every unfinished slot; returns how many are unfinished."""
+        n = C.c_int()
+        self.ctx._check(self.ctx.lib.sapdd_batch_step(self.h, C.byref(n)))
+        return n.value
+
+    def poll(self, slot: int):
+        st = Stats()
+        rc = self.ctx.lib.sapdd_batch_poll(self.h, int(slot), C.byref(st))
+        if rc < 0:
+            raise SapddError(rc, "bad slot")
+        return bool(rc), st.as_dict()
+
+    def take(self, slot: int, out):
+        """Copy the solution of a slot into `out` (host array or device tensor), free it."""
+        po, dev = _ptr(out, writable=True)
+        st = Stats()
+        self.ctx._check(self.ctx.lib.sapdd_batch_take(self.h, int(slot), po, DEVICE_PTRS if dev else 0,
+                                                      C.byref(st)))
+        return st.as_dict()

@@ -1,0 +1,292 @@
+"""Continuous-batching solve server over resident gauge fields.
+
+Requests (a lattice volume, a kappa and 1..n right-hand sides) arrive over time. Every
+volume has its gauge field and clover term resident on the GPU and one worker thread
+with its own context, HIP stream and solver batch (`sapdd_batch_*`). A worker admits
+waiting requests of its volume into free batch slots between FGMRES restart cycles,
+steps the batch (one restart cycle for every active slot: all right-hand sides of the
+volume in one multi-RHS launch sequence), and hands back every request whose
+right-hand sides have all converged. Workers of different volumes run concurrently,
+so their kernels overlap on the device.
+
+Admission is by HBM footprint: the slot capacity of every volume's batch is planned
+from the memory budget (fields + per-RHS Krylov state + clover inverses), and a request
+enters only when its right-hand sides fit in free slots of its volume.
+"""
+from __future__ import annotations
+
+import math
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    id: int
+    t_arrival: float  # seconds after the serving clock starts
+    vol: int
+    kappa: float
+    nrhs: int
+    seed: int
+    # filled by the server
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    slots: list = field(default_factory=list)
+    stats: list = field(default_factory=list)
+    x: object = None
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclass
+class VolumePlan:
+    name: str
+    field_bytes: int      # resident links + clover (all precisions in use)
+    per_rhs_bytes: int    # Krylov basis, preconditioned vectors, b, x, SAP state per slot
+    kappa_bytes: int      # one clover inverse for a new kappa
+    capacity: int = 0
+
+
+def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: int = 16):
+    """Split an HBM budget into batch capacities (slots) per volume.
+
+    The fields and a cache of `kappa_cache` clover inverses per volume are reserved
+    first; the rest buys the same number of slots in every volume (a slot of a large
+    volume costs more bytes), at most max_slots. Raises if not even one slot fits.
+    """
+    fixed = sum(p.field_bytes + kappa_cache * p.kappa_bytes for p in plans)
+    if fixed >= budget_bytes:
+        raise MemoryError(f"budget {budget_bytes} B cannot hold the resident fields ({fixed} B)")
+    cap = int(min(max_slots, (budget_bytes - fixed) // sum(p.per_rhs_bytes for p in plans)))
+    if cap < 1:
+        raise MemoryError("budget leaves no slot for every volume")
+    for p in plans:
+        p.capacity = cap
+    return plans
+
+
+class Admission:
+    """Slot bookkeeping of one volume (thread-safe)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity
+        self.free = capacity
+        self.lock = threading.Lock()
+
+    def fits_ever(self, n: int) -> bool:
+        return n <= self.capacity
+
+    def try_take(self, n: int) -> bool:
+        with self.lock:
+            if n <= self.free:
+                self.free -= n
+                return True
+            return False
+
+    def give_back(self, n: int) -> None:
+        with self.lock:
+            self.free += n
+            assert self.free <= self.capacity
+
+
+class VolumeWorker(threading.Thread):
+    """Serves the requests of one volume with one batch on its own stream.
+
+    `backend` provides make_source(req) -> list of right-hand sides, make_output(req)
+    -> list of outputs, and a batch object with add/step/poll/take (the sapdd Batch, or a
+    stand-in in host-only tests)."""
+
+    def __init__(self, name, batch, backend, admission: Admission, clock, on_done):
+        super().__init__(name=f"serve-{name}", daemon=True)
+        self.batch = batch
+        self.backend = backend
+        self.adm = admission
+        self.clock = clock
+        self.on_done = on_done
+        self.queue = deque()
+        self.cv = threading.Condition()
+        self.stop_when_idle = False
+        self.active = []
+        self.error = None
+        self.steps = 0
+
+    def submit(self, req: Request):
+        with self.cv:
+            if not self.adm.fits_ever(req.nrhs):
+                req.error = f"request needs {req.nrhs} slots, volume holds {self.adm.capacity}"
+                req.t_done = self.clock()
+                self.on_done(req)
+                return
+            self.queue.append(req)
+            self.cv.notify()
+
+    def finish(self):
+        with self.cv:
+            self.stop_when_idle = True
+            self.cv.notify()
+
+    def _admit(self):
+        while True:
+            with self.cv:
+                if not self.queue or not self.adm.try_take(self.queue[0].nrhs):
+                    return
+                req = self.queue.popleft()
+            req.t_admit = self.clock()
+            srcs = self.backend.make_source(req)
+            req.x = self.backend.make_output(req)
+            req.slots = [self.batch.add(req.kappa, b) for b in srcs]
+            self.active.append(req)
+
+    def _harvest(self):
+        still = []
+        for req in self.active:
+            done = all(self.batch.poll(s)[0] for s in req.slots)
+            if not done:
+                still.append(req)
+                continue
+            req.stats = [self.batch.take(s, out) for s, out in zip(req.slots, req.x)]
+            self.adm.give_back(req.nrhs)
+            req.t_done = self.clock()
+            self.on_done(req)
+        self.active = still
+
+    def run(self):
+        try:
+            with self.backend.thread_context():
+                self._loop()
+        except Exception as e:  # surfaced by Server.run
+            self.error = e
+
+    def _loop(self):
+        while True:
+            self._admit()
+            if self.active:
+                self.batch.step()
+                self.steps += 1
+                self._harvest()
+                continue
+            with self.cv:
+                if self.queue:
+                    continue
+                if self.stop_when_idle:
+                    return
+                self.cv.wait(timeout=0.05)
+
+
+class Server:
+    """Routes a request stream to per-volume workers and records latencies."""
+
+    def __init__(self, workers):
+        self.workers = workers
+        self.done = []
+        self.lock = threading.Lock()
+        self.t0 = None
+
+    def clock(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def _on_done(self, req):
+        with self.lock:
+            self.done.append(req)
+
+    def run(self, requests, realtime: bool = True):
+        """Release every request at its arrival time (or all at once if not realtime) and
+        wait for all of them. Returns the finished requests."""
+        self.t0 = time.perf_counter()
+        for w in self.workers:
+            w.clock = self.clock
+            w.on_done = self._on_done
+            w.start()
+        for req in sorted(requests, key=lambda r: r.t_arrival):
+            if realtime:
+                dt = req.t_arrival - self.clock()
+                if dt > 0:
+                    time.sleep(dt)
+            self.workers[req.vol].submit(req)
+        for w in self.workers:
+            w.finish()
+        for w in self.workers:
+            w.join()
+        errs = [w.error for w in self.workers if w.error is not None]
+        if errs:
+            raise errs[0]
+        return self.done
+
+
+def summarize(done, wall: float) -> dict:
+    ok = [r for r in done if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
+    rhs = sum(r.nrhs for r in ok)
+    return dict(requests=len(ok), rejected=len(done) - len(ok), rhs_solves=rhs,
+                solves_per_s=rhs / wall if wall > 0 else float("nan"),
+                requests_per_s=len(ok) / wall if wall > 0 else float("nan"),
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                mean_ms=float(np.mean(lat) * 1e3))
+
+
+class TorchVolume:
+    """GPU resources of one served volume: a stream, a context, the resident field, the
+    batch, and seeded Gaussian sources drawn on the device."""
+
+    def __init__(self, name, dims, block, eps, gauge_seed, csw, capacity, solver_kw, links=None):
+        import torch
+
+        import synthetic  # seeded input recipe shared with the tests
+        from .sapdd import Context
+        self.name = name
+        self.dims = tuple(dims)
+        self.solver_kw = dict(solver_kw)
+        self.stream = torch.cuda.Stream()
+        self.ctx = Context(0, stream=self.stream)
+        u = links if links is not None else synthetic.gauge_field(dims, eps, gauge_seed)
+        with torch.cuda.stream(self.stream):
+            self.field = self.ctx.load_gauge(u, block)
+            self.field.compute_clover(csw)
+        self.torch = torch
+        self.batch = None
+        if capacity:
+            self.start(capacity)
+
+    def plan(self) -> VolumePlan:
+        """Memory plan of this volume: resident field, bytes per slot, per-kappa clover."""
+        lx, ly, lz, lt = self.dims
+        v = lx * ly * lz * lt
+        per_rhs = self.field.footprint(2, **self.solver_kw) - self.field.footprint(1, **self.solver_kw)
+        lo = self.field.footprint(1, **self.solver_kw) - per_rhs
+        prec_b = {"f64": 8, "f32": 4, "f16": 2}[self.solver_kw.get("prec", "f64")]
+        return VolumePlan(self.name, 2 * v * 72 * 8 + lo, per_rhs, v * 72 * prec_b + v * 4)
+
+    def start(self, capacity: int):
+        from .sapdd import Batch
+        with self.torch.cuda.stream(self.stream):
+            self.batch = Batch(self.field, capacity, **self.solver_kw)
+
+    def thread_context(self):
+        return self.torch.cuda.stream(self.stream)
+
+    def make_source(self, req):
+        torch = self.torch
+        lx, ly, lz, lt = self.dims
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(req.seed))
+        r = torch.randn((req.nrhs, lt, lz, ly, lx, 4, 3, 2), generator=g, dtype=torch.float64, device="cuda")
+        b = torch.view_as_complex(r).contiguous()
+        return [b[i] for i in range(req.nrhs)]
+
+    def make_output(self, req):
+        torch = self.torch
+        lx, ly, lz, lt = self.dims
+        x = torch.empty((req.nrhs, lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device="cuda")
+        return [x[i] for i in range(req.nrhs)]
+
+    def close(self):
+        self.batch.close()
+        self.field.free()
+        self.ctx.close()

@@ -1,0 +1,105 @@
+"""Host-side tests of the serving loop: admission by memory budget, continuous batching,
+and completion bookkeeping, with an in-memory stand-in for the GPU batch."""
+import contextlib
+import math
+
+import pytest
+
+from paper_1502_04025_amd import serving as sv
+
+
+class FakeBatch:
+    """A slot holding source b finishes after 2 + b % 4 steps; records which slots shared
+    each step."""
+
+    def __init__(self, capacity, need=None):
+        self.cap = capacity
+        self.slots = {}
+        self.steps = []
+
+    @staticmethod
+    def need(b):
+        return 2 + b % 4
+
+    def add(self, kappa, b):
+        free = [s for s in range(self.cap) if s not in self.slots]
+        if not free:
+            raise RuntimeError("full")
+        self.slots[free[0]] = [0, b]
+        return free[0]
+
+    def step(self):
+        self.steps.append(sorted(self.slots))
+        for st in self.slots.values():
+            st[0] += 1
+        return sum(1 for st in self.slots.values() if st[0] < self.need(st[1]))
+
+    def poll(self, s):
+        return self.slots[s][0] >= self.need(self.slots[s][1]), {}
+
+    def take(self, s, out):
+        n, b = self.slots.pop(s)
+        out.append(b * 2)
+        return {"iters": n}
+
+
+class FakeBackend:
+    def thread_context(self):
+        return contextlib.nullcontext()
+
+    def make_source(self, req):
+        return [req.seed * 10 + i for i in range(req.nrhs)]
+
+    def make_output(self, req):
+        return [[] for _ in range(req.nrhs)]
+
+
+def test_plan_capacity_and_budget_errors():
+    plans = [sv.VolumePlan("a", 100, 10, 1), sv.VolumePlan("b", 300, 40, 2)]
+    sv.plan_capacity(plans, 400 + 16 * 3 + 5 * 50, max_slots=24)
+    assert [p.capacity for p in plans] == [5, 5]
+    sv.plan_capacity(plans, 10 ** 9, max_slots=24)
+    assert plans[0].capacity == 24
+    with pytest.raises(MemoryError):
+        sv.plan_capacity(plans, 300)
+    with pytest.raises(MemoryError):
+        sv.plan_capacity(plans, 400 + 16 * 3 + 10)
+
+
+def test_admission_is_all_or_nothing():
+    a = sv.Admission(4)
+    assert a.try_take(3) and not a.try_take(2) and a.try_take(1)
+    a.give_back(3)
+    assert a.free == 3 and not a.fits_ever(5)
+
+
+def _run(reqs, capacity):
+    batch = FakeBatch(capacity)
+    w = sv.VolumeWorker("v", batch, FakeBackend(), sv.Admission(capacity), None, None)
+    srv = sv.Server([w])
+    done = srv.run(reqs, realtime=False)
+    return batch, done
+
+
+def test_continuous_batching_joins_between_steps_and_completes_everything():
+    reqs = [sv.Request(i, 0.0, 0, 0.12, n, seed=i) for i, n in enumerate([2, 3, 1, 4, 2])]
+    batch, done = _run(reqs, capacity=5)
+    assert len(done) == 5 and all(r.error is None for r in done)
+    for r in done:  # every right-hand side came back through its own slot
+        assert [o[0] for o in r.x] == [2 * (r.seed * 10 + i) for i in range(r.nrhs)]
+        assert r.t_done >= r.t_admit >= 0 and not math.isnan(r.latency)
+    # the batch never held more than its capacity, and a later request joined a batch
+    # that was already running (continuous batching, not run-to-completion)
+    assert max(len(s) for s in batch.steps) <= 5
+    joined_late = any(set(batch.steps[k + 1]) - set(batch.steps[k]) and set(batch.steps[k])
+                      for k in range(len(batch.steps) - 1))
+    assert joined_late
+
+
+def test_oversized_request_is_rejected_not_stuck():
+    reqs = [sv.Request(0, 0.0, 0, 0.12, 7, seed=1), sv.Request(1, 0.0, 0, 0.12, 2, seed=2)]
+    _, done = _run(reqs, capacity=4)
+    bad = [r for r in done if r.error]
+    assert len(bad) == 1 and bad[0].id == 0
+    s = sv.summarize(done, wall=1.0)
+    assert s["requests"] == 1 and s["rejected"] == 1 and s["rhs_solves"] == 2
