@@ -56,6 +56,27 @@ def make_source(cfg):
     return synthetic.gaussian_source(cfg["dims"], cfg["nrhs"], cfg["source_seed"])
 
 
+def profiled_traffic(entry):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, or
+    None if the kernel's sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.txt")):
+        for line in open(path):
+            if not line.startswith("TRAFFIC "):
+                continue
+            rec = json.loads(line[len("TRAFFIC "):])
+            if rec["entry"] != entry:
+                continue
+            h = hashlib.sha256()
+            for f in rec["sources"]:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest()[:16] != rec["source_sha"]:
+                return None
+            return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
+
+
 def roofline_sap(prof, cfg, prec, nmr):
     from paper_1502_04025_amd import perfmodel as pm
     k = prof["sap_half"]
@@ -67,17 +88,19 @@ def roofline_sap(prof, cfg, prec, nmr):
     flops = pm.sap_half_flops(cfg["block"], nmr) * units
     byts = pm.sap_half_bytes(cfg["block"], prec) * units
     alu_peak = pm.ALU_PEAK_TFLOPS["f64" if prec == "f64" else "f32"]
+    traffic = profiled_traffic(f"sap_half_kernel {'x'.join(map(str, cfg['dims']))} {'x'.join(map(str, cfg['block']))} "
+                               f"{prec}") if cfg["nrhs_active"] == 1 else None
     t_alu = flops / (alu_peak * 1e12)
     t_hbm = byts / (pm.HBM_PEAK_GBS * 1e9)
     if t_alu >= t_hbm:
         ach = flops / avg / 1e12
         return dict(kernel="sap_half_kernel", bound="alu", achieved=round(ach, 3), peak=alu_peak,
-                    unit="TFLOP/s", frac=round(ach / alu_peak, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(ach / alu_peak, 4), traffic=traffic,
                     avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
                     algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts)
     ach = byts / avg / 1e9
     return dict(kernel="sap_half_kernel", bound="hbm", achieved=round(ach, 1), peak=pm.HBM_PEAK_GBS,
-                unit="GB/s", frac=round(ach / pm.HBM_PEAK_GBS, 4), traffic=None,
+                unit="GB/s", frac=round(ach / pm.HBM_PEAK_GBS, 4), traffic=traffic,
                 avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
                 algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts)
 
@@ -105,7 +128,8 @@ def dslash_bandwidth(ctx, reps=20):
         byts = pm.block_dslash_bytes(cfg["block"], prec) * V
         gbs = byts / avg / 1e9
         res[prec] = dict(GB_s=round(gbs, 1), frac=round(gbs / pm.HBM_PEAK_GBS, 4), avg_launch_us=round(avg * 1e6, 2),
-                         algorithmic_bytes_per_launch=byts)
+                         algorithmic_bytes_per_launch=byts,
+                         traffic=profiled_traffic(f"dslash_block_kernel 32x32x32x64 4x4x4x4 {prec}"))
     f.free()
     return dict(kernel="dslash_block_kernel", lattice="32x32x32x64", block=list(cfg["block"]), **res)
 
