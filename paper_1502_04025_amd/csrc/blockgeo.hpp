@@ -80,31 +80,41 @@ template <class S, class R> struct SiteLinks<S, R, true> {
         if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
         else sc = (R)1;
     }
+    // Link MU without the FP16 site scale (see scale()).
     template <int MU> __device__ __forceinline__ void get(R out[18]) const {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
             const int q = 18 * MU + k;
-            if constexpr (Storage<S>::scaled) out[k] = (R)(float)u[q / W][q % W] * sc;
+            if constexpr (Storage<S>::scaled) out[k] = (R)(float)u[q / W][q % W];
             else out[k] = (R)u[q / W][q % W];
         }
+    }
+    __device__ __forceinline__ R scale() const {
+        if constexpr (Storage<S>::scaled) return sc;
+        else return (R)1;
     }
 };
 
 template <class S, class R> struct SiteLinks<S, R, false> {
     const S *base;
-    const float *scale;
+    R sc;
     int64_t bp;
     int s, Vbh;
-    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ sc, int64_t bp_, int s_,
+    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ scl, int64_t bp_, int s_,
                                          int vbh) {
         base = b;
-        scale = sc;
         bp = bp_;
         s = s_;
         Vbh = vbh;
+        sc = site_scale<R, S>(scl, bp, s, Vbh);
     }
+    // Link MU without the FP16 site scale (see scale()).
     template <int MU> __device__ __forceinline__ void get(R out[18]) const {
-        load_reals<R, 72, 18 * MU, 18>(base, scale, bp, s, Vbh, out);
+        load_reals<R, 72, 18 * MU, 18, S, true>(base, nullptr, bp, s, Vbh, out);
+    }
+    __device__ __forceinline__ R scale() const {
+        if constexpr (Storage<S>::scaled) return sc;
+        else return (R)1;
     }
 };
 
@@ -123,35 +133,49 @@ template <class S, class R> struct CloverRegs {
         if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
         else sc = (R)1;
     }
+    // Entry k without the FP16 site scale (clover_mul applies it).
     __device__ __forceinline__ R at(int k) const {
-        if constexpr (Storage<S>::scaled) return (R)(float)x[k / W][k % W] * sc;
+        if constexpr (Storage<S>::scaled) return (R)(float)x[k / W][k % W];
         else return (R)x[k / W][k % W];
+    }
+    __device__ __forceinline__ R scale() const {
+        if constexpr (Storage<S>::scaled) return sc;
+        else return (R)1;
     }
 };
 
-// out = in + kx * X in for the two packed Hermitian 6x6 blocks of X.
+// out = in + kx * X in for the two packed Hermitian 6x6 blocks of X: X in is accumulated
+// from the stored entries with FMAs and scaled once (kx times the site scale).
 template <class S, class R>
 __device__ __forceinline__ void clover_mul(const CloverRegs<S, R> &X, const R (&in)[24], R (&out)[24], R kx) {
+    const R f = kx * X.scale();
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
         const int o = 12 * blk;
+        R t[12];
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            const R d = kx * X.at(36 * blk + i) + (R)1;
-            out[o + 2 * i] = d * in[o + 2 * i];
-            out[o + 2 * i + 1] = d * in[o + 2 * i + 1];
+            const R d = X.at(36 * blk + i);
+            t[2 * i] = d * in[o + 2 * i];
+            t[2 * i + 1] = d * in[o + 2 * i + 1];
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
             for (int j = i + 1; j < 6; ++j) {
                 const int q = 36 * blk + 6 + 2 * (i * 5 - i * (i - 1) / 2 + (j - i - 1));
-                const R xr = kx * X.at(q), xi = kx * X.at(q + 1);
-                out[o + 2 * i] += xr * in[o + 2 * j] - xi * in[o + 2 * j + 1];
-                out[o + 2 * i + 1] += xr * in[o + 2 * j + 1] + xi * in[o + 2 * j];
-                out[o + 2 * j] += xr * in[o + 2 * i] + xi * in[o + 2 * i + 1];
-                out[o + 2 * j + 1] += xr * in[o + 2 * i + 1] - xi * in[o + 2 * i];
+                const R xr = X.at(q), xi = X.at(q + 1);
+                t[2 * i] = fmac(xr, in[o + 2 * j], t[2 * i]);
+                t[2 * i] = fmac(-xi, in[o + 2 * j + 1], t[2 * i]);
+                t[2 * i + 1] = fmac(xr, in[o + 2 * j + 1], t[2 * i + 1]);
+                t[2 * i + 1] = fmac(xi, in[o + 2 * j], t[2 * i + 1]);
+                t[2 * j] = fmac(xr, in[o + 2 * i], t[2 * j]);
+                t[2 * j] = fmac(xi, in[o + 2 * i + 1], t[2 * j]);
+                t[2 * j + 1] = fmac(xr, in[o + 2 * i + 1], t[2 * j + 1]);
+                t[2 * j + 1] = fmac(-xi, in[o + 2 * i], t[2 * j + 1]);
             }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) out[o + k] = fmac(f, t[k], in[o + k]);
     }
 }
 
@@ -196,7 +220,8 @@ template <class S, class R> struct SiteClover<S, R, false> {
 // Source threads store their spinor (for the forward hops of their backward neighbours)
 // and, for every in-block forward neighbour, the transported half spinor
 // U_mu(x)^+ (1 + gamma_mu) in(x); the receiving threads then need only their own links.
-// Every thread of the workgroup must call this; it contains two barriers.
+// Every thread of the workgroup must call this; it contains one barrier (two with a
+// single LDS buffer).
 template <int MU, class BK, class R, class LK>
 __device__ __forceinline__ void push_dir(const SiteInfo &si, const LK &U, const R (&in)[24], R *__restrict__ hb) {
     constexpr int Vbh = BK::Vbh;
@@ -205,8 +230,9 @@ __device__ __forceinline__ void push_dir(const SiteInfo &si, const LK &U, const 
         project<MU, +1>(in, h);
         U.template get<MU>(u);
         su3_dag_mul(u, h, uh);
+        const R sc = U.scale();
 #pragma unroll
-        for (int k = 0; k < 12; ++k) hb[(MU * 12 + k) * Vbh + si.s] = uh[k];
+        for (int k = 0; k < 12; ++k) hb[(MU * 12 + k) * Vbh + si.s] = sc * uh[k];
     }
 }
 
@@ -222,7 +248,7 @@ __device__ __forceinline__ void pull_dir(const SiteInfo &si, const LK &U, R (&ou
         project<MU, -1>(chi, h);
         U.template get<MU>(u);
         su3_mul(u, h, uh);
-        accum_recon<MU, -1>(out, uh, (R)1);
+        accum_recon<MU, -1>(out, uh, U.scale());
     }
     if (si.bin & (1u << MU)) {
         R uh[12];
@@ -233,10 +259,26 @@ __device__ __forceinline__ void pull_dir(const SiteInfo &si, const LK &U, R (&ou
     }
 }
 
-template <class BK, class R, class LK>
+// LDS exchange area of block_hop: NBUF buffers of (spinor + 4 transported half
+// spinors) per source site. With two buffers consecutive hops alternate between them
+// and each hop needs only its middle barrier: a thread can only start writing buffer i
+// again (hop n + 2) after passing hop n + 1's barrier, which every thread reaches only
+// after finishing its reads of hop n.
+template <class BK, class R, int WANT = 2> struct HopLds {
+    static constexpr int PER = 72 * BK::Vbh;  // reals per buffer: 24 (spinor) + 48 (half spinors)
+    static constexpr int NBUF = WANT == 2 && 2 * PER * (int)sizeof(R) <= 150 * 1024 ? 2 : 1;
+    R *base;
+    int cur;
+    __device__ __forceinline__ R *sp() const { return base + cur * PER; }
+    __device__ __forceinline__ R *hb() const { return base + cur * PER + 24 * BK::Vbh; }
+};
+
+template <class BK, class R, class LK, int WANT>
 __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK &U, const R (&in)[24], R (&out)[24],
-                                          R *__restrict__ sp, R *__restrict__ hb) {
+                                          HopLds<BK, R, WANT> &lds) {
     constexpr int Vbh = BK::Vbh;
+    R *__restrict__ sp = lds.sp();
+    R *__restrict__ hb = lds.hb();
     if (si.p == src) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) sp[k * Vbh + si.s] = in[k];
@@ -254,7 +296,11 @@ __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK 
         pull_dir<2, BK>(si, U, out, sp, hb);
         pull_dir<3, BK>(si, U, out, sp, hb);
     }
-    __syncthreads();
+    if constexpr (HopLds<BK, R, WANT>::NBUF == 2) {
+        lds.cur ^= 1;
+    } else {
+        __syncthreads();  // one buffer: the next hop may only overwrite it after every read
+    }
 }
 
 }  // namespace sapdd

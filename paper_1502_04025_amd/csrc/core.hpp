@@ -77,7 +77,8 @@ template <class S> struct CFieldPtr {
 };
 
 // Reals [K0, K0 + K) of site (bp, s) of an N-real field, through whole 16-byte vectors.
-template <class R, int N, int K0, int K, class S>
+// With RAW the FP16 site scale is not applied (the caller folds it into a result).
+template <class R, int N, int K0, int K, class S, bool RAW = false>
 __device__ __forceinline__ void load_reals(const S *__restrict__ data, const float *__restrict__ scale, int64_t bp,
                                            int s, int Vbh, R out[K]) {
     typedef typename Vec<S>::type VT;
@@ -85,7 +86,7 @@ __device__ __forceinline__ void load_reals(const S *__restrict__ data, const flo
     constexpr int v0 = K0 / W, v1 = (K0 + K - 1) / W;
     const VT *p = reinterpret_cast<const VT *>(data);
     R sc = (R)1;
-    if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
+    if constexpr (Storage<S>::scaled && !RAW) sc = (R)scale[bp * Vbh + s];
 #pragma unroll
     for (int v = v0; v <= v1; ++v) {
         const VT x = p[vec_index<S, N>(bp, v, s, Vbh)];
@@ -93,11 +94,19 @@ __device__ __forceinline__ void load_reals(const S *__restrict__ data, const flo
         for (int w = 0; w < W; ++w) {
             const int k = v * W + w - K0;
             if (k >= 0 && k < K) {
-                if constexpr (Storage<S>::scaled) out[k] = (R)(float)x[w] * sc;
+                if constexpr (Storage<S>::scaled && !RAW) out[k] = (R)(float)x[w] * sc;
+                else if constexpr (Storage<S>::scaled) out[k] = (R)(float)x[w];
                 else out[k] = (R)x[w];
             }
         }
     }
+}
+
+// FP16 per-site scale of site (bp, s) (1 for unscaled storage).
+template <class R, class S>
+__device__ __forceinline__ R site_scale(const float *__restrict__ scale, int64_t bp, int s, int Vbh) {
+    if constexpr (Storage<S>::scaled) return (R)scale[bp * Vbh + s];
+    else return (R)1;
 }
 
 template <class R, int N, class S>
@@ -137,6 +146,12 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
         }
     }
 }
+
+// ------------------------------------------------------------------ arithmetic
+// Fused multiply-add in the arithmetic type (one v_fma per call; with an FP16 operand
+// converted in place the compiler forms v_fma_mix).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // ------------------------------------------------------------------ gamma structure
 // Multiply (re, im) by i^ph.
@@ -198,40 +213,46 @@ __device__ __forceinline__ void project(const R psi[24], R h[12]) {
 template <int MU, int SIGN, class R>
 __device__ __forceinline__ void accum_recon(R acc[24], const R h[12], R scale) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] += scale * h[k];
+    for (int k = 0; k < 12; ++k) acc[k] = fmac(scale, h[k], acc[k]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         {
             constexpr int col = GDrow<MU, 0>::col, ph = GDrow<MU, 0>::ph;
             R re, im;
             iph<ph>(h[2 * (3 * col + c)], h[2 * (3 * col + c) + 1], re, im);
-            acc[2 * (6 + c)] += (R)SIGN * scale * re;
-            acc[2 * (6 + c) + 1] += (R)SIGN * scale * im;
+            acc[2 * (6 + c)] = fmac((R)SIGN * scale, re, acc[2 * (6 + c)]);
+            acc[2 * (6 + c) + 1] = fmac((R)SIGN * scale, im, acc[2 * (6 + c) + 1]);
         }
         {
             constexpr int col = GDrow<MU, 1>::col, ph = GDrow<MU, 1>::ph;
             R re, im;
             iph<ph>(h[2 * (3 * col + c)], h[2 * (3 * col + c) + 1], re, im);
-            acc[2 * (9 + c)] += (R)SIGN * scale * re;
-            acc[2 * (9 + c) + 1] += (R)SIGN * scale * im;
+            acc[2 * (9 + c)] = fmac((R)SIGN * scale, re, acc[2 * (9 + c)]);
+            acc[2 * (9 + c) + 1] = fmac((R)SIGN * scale, im, acc[2 * (9 + c) + 1]);
         }
     }
 }
 
 // ------------------------------------------------------------------ SU(3) on half spinors
-// out = U h for both spins; U has 18 reals, row major complex.
+// out = U h for both spins; U has 18 reals, row major complex. Four FMAs per complex
+// multiply-add.
 template <class R> __device__ __forceinline__ void su3_mul(const R u[18], const R h[12], R out[12]) {
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R re = 0, im = 0;
+            R re = u[2 * (3 * a)] * h[2 * (3 * sp)];
+            R im = u[2 * (3 * a)] * h[2 * (3 * sp) + 1];
+            re = fmac(-u[2 * (3 * a) + 1], h[2 * (3 * sp) + 1], re);
+            im = fmac(u[2 * (3 * a) + 1], h[2 * (3 * sp)], im);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 1; b < 3; ++b) {
                 const R ur = u[2 * (3 * a + b)], ui = u[2 * (3 * a + b) + 1];
                 const R hr = h[2 * (3 * sp + b)], hi = h[2 * (3 * sp + b) + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+                re = fmac(ur, hr, re);
+                re = fmac(-ui, hi, re);
+                im = fmac(ur, hi, im);
+                im = fmac(ui, hr, im);
             }
             out[2 * (3 * sp + a)] = re;
             out[2 * (3 * sp + a) + 1] = im;
@@ -244,73 +265,22 @@ template <class R> __device__ __forceinline__ void su3_dag_mul(const R u[18], co
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R re = 0, im = 0;
+            R re = u[2 * a] * h[2 * (3 * sp)];
+            R im = u[2 * a] * h[2 * (3 * sp) + 1];
+            re = fmac(u[2 * a + 1], h[2 * (3 * sp) + 1], re);
+            im = fmac(-u[2 * a + 1], h[2 * (3 * sp)], im);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 1; b < 3; ++b) {
                 const R ur = u[2 * (3 * b + a)], ui = u[2 * (3 * b + a) + 1];
                 const R hr = h[2 * (3 * sp + b)], hi = h[2 * (3 * sp + b) + 1];
-                re += ur * hr + ui * hi;
-                im += ur * hi - ui * hr;
+                re = fmac(ur, hr, re);
+                re = fmac(ui, hi, re);
+                im = fmac(ur, hi, im);
+                im = fmac(-ui, hr, im);
             }
             out[2 * (3 * sp + a)] = re;
             out[2 * (3 * sp + a) + 1] = im;
         }
-}
-
-// ------------------------------------------------------------------ clover
-// out = in + X in, X two packed Hermitian 6x6 blocks (72 reals).
-template <class R> __device__ __forceinline__ void clover_apply(const R x[72], const R in[24], R out[24]) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const R *d = x + 36 * k;
-        const R *v = in + 12 * k;
-        R *o = out + 12 * k;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            R re = v[2 * i] + d[i] * v[2 * i];
-            R im = v[2 * i + 1] + d[i] * v[2 * i + 1];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                if (j == i) continue;
-                const int a = i < j ? i : j, b = i < j ? j : i;
-                const int idx = a * 5 - a * (a - 1) / 2 + (b - a - 1);  // position of (a,b), a<b
-                const R xr = d[6 + 2 * idx];
-                const R xi = (i < j) ? d[6 + 2 * idx + 1] : -d[6 + 2 * idx + 1];
-                re += xr * v[2 * j] - xi * v[2 * j + 1];
-                im += xr * v[2 * j + 1] + xi * v[2 * j];
-            }
-            o[2 * i] = re;
-            o[2 * i + 1] = im;
-        }
-    }
-}
-
-// out = kappa * X in (no identity part).
-template <class R>
-__device__ __forceinline__ void clover_apply_k(const R x[72], const R in[24], R kappa, R out[24]) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const R *d = x + 36 * k;
-        const R *v = in + 12 * k;
-        R *o = out + 12 * k;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            R re = d[i] * v[2 * i];
-            R im = d[i] * v[2 * i + 1];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                if (j == i) continue;
-                const int a = i < j ? i : j, b = i < j ? j : i;
-                const int idx = a * 5 - a * (a - 1) / 2 + (b - a - 1);
-                const R xr = d[6 + 2 * idx];
-                const R xi = (i < j) ? d[6 + 2 * idx + 1] : -d[6 + 2 * idx + 1];
-                re += xr * v[2 * j] - xi * v[2 * j + 1];
-                im += xr * v[2 * j + 1] + xi * v[2 * j];
-            }
-            o[2 * i] = kappa * re;
-            o[2 * i + 1] = kappa * im;
-        }
-    }
 }
 
 // ------------------------------------------------------------------ geometry

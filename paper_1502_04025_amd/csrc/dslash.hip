@@ -91,9 +91,9 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
                 R chi[24], h[12], u[18], uh[12];
                 load_site<R, 24>(ind, ins, nbp, ns, Vbh, chi);
                 project<MU, -1>(chi, h);
-                load_reals<R, 72, 18 * MU, 18>(links.data, links.scale, bp, s, Vbh, u);
+                load_reals<R, 72, 18 * MU, 18, S, true>(links.data, nullptr, bp, s, Vbh, u);
                 su3_mul(u, h, uh);
-                accum_recon<MU, -1>(acc, uh, sg);
+                accum_recon<MU, -1>(acc, uh, sg * site_scale<R, S>(links.scale, bp, s, Vbh));
             }
             {  // backward hop: (1 + gamma) U_mu(x - mu)^+ psi(x - mu)
                 int y[4] = {x[0], x[1], x[2], x[3]};
@@ -108,9 +108,9 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
                 R chi[24], h[12], u[18], uh[12];
                 load_site<R, 24>(ind, ins, nbp, ns, Vbh, chi);
                 project<MU, +1>(chi, h);
-                load_reals<R, 72, 18 * MU, 18>(links.data, links.scale, nbp, ns, Vbh, u);
+                load_reals<R, 72, 18 * MU, 18, S, true>(links.data, nullptr, nbp, ns, Vbh, u);
                 su3_dag_mul(u, h, uh);
-                accum_recon<MU, +1>(acc, uh, sg);
+                accum_recon<MU, +1>(acc, uh, sg * site_scale<R, S>(links.scale, nbp, ns, Vbh));
             }
         });
         R psi[24], res[24];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
         cl.load(tclov.data, tclov.scale, bp, s, Vbh);
         clover_mul(cl, psi, res, kappa);  // (1 + kappa T) psi
 #pragma unroll
-        for (int c = 0; c < 24; ++c) res[c] -= kappa * acc[c];
+        for (int c = 0; c < 24; ++c) res[c] = fmac(-kappa, acc[c], res[c]);
         if (sub) {
             double sb[24];
             load_site<double, 24>(sub + (int64_t)rhs * subs_ * geo.V * 24, nullptr, bp, s, Vbh, sb);
@@ -213,8 +213,10 @@ template <class BK, class S, class R>
 __global__ __launch_bounds__(BK::NT) void dslash_block_kernel(Geom geo, CF<S> links, CF<S> tclov, R kappa,
                                                                CF<S> in, MF<S> out) {
     constexpr int Vbh = BK::Vbh;
-    __shared__ R sp[24 * Vbh];
-    __shared__ R hb[48 * Vbh];
+    // one LDS buffer: this memory-bound kernel gains more from occupancy than from the
+    // barrier a second buffer would save
+    __shared__ R lds_hop[HopLds<BK, R, 1>::PER];
+    HopLds<BK, R, 1> lds{lds_hop, 0};
     const SiteInfo si = site_info<BK>(threadIdx.x);
     const int64_t b = blockIdx.x;
     const int rhs = blockIdx.y;
@@ -224,14 +226,14 @@ __global__ __launch_bounds__(BK::NT) void dslash_block_kernel(Geom geo, CF<S> li
     U.init(links.data, links.scale, bp, si.s, Vbh);
     R psi[24], hop[24];
     load_site<R, 24>(in.data + ioff, in.scale ? in.scale + soff : nullptr, bp, si.s, Vbh, psi);
-    block_hop<BK>(0, si, U, psi, hop, sp, hb);  // odd sites receive
-    block_hop<BK>(1, si, U, psi, hop, sp, hb);  // even sites receive
+    block_hop<BK>(0, si, U, psi, hop, lds);  // odd sites receive
+    block_hop<BK>(1, si, U, psi, hop, lds);  // even sites receive
     R res[24];
     CloverRegs<S, R> cl;
     cl.load(tclov.data, tclov.scale, bp, si.s, Vbh);
     clover_mul(cl, psi, res, kappa);
 #pragma unroll
-    for (int c = 0; c < 24; ++c) res[c] -= kappa * hop[c];
+    for (int c = 0; c < 24; ++c) res[c] = fmac(-kappa, hop[c], res[c]);
     store_site<R, 24>(out.data + ioff, out.scale ? out.scale + soff : nullptr, bp, si.s, Vbh, res);
 }
 

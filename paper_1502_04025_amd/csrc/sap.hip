@@ -108,7 +108,7 @@ __device__ __forceinline__ void gather_dir(const SapArgs<S, P> &a, const SiteInf
         project<MU, -1>(d, h);
         U.template get<MU>(u);
         su3_mul(u, h, uh);
-        accum_recon<MU, -1>(rho, uh, kappa * sg);
+        accum_recon<MU, -1>(rho, uh, kappa * sg * U.scale());
     }
     if (!(si.bin & (1u << MU))) {  // x - mu lies in the previous block
         int gn[4] = {g[0], g[1], g[2], g[3]}, ln[4] = {si.l[0], si.l[1], si.l[2], si.l[3]};
@@ -122,10 +122,11 @@ __device__ __forceinline__ void gather_dir(const SapArgs<S, P> &a, const SiteInf
         const int ns = local_half_index(B, ln);
         R d[24], h[12], u[18], uh[12];
         load_site<R, 24>(dlt, dlt_sc, nbp, ns, Vbh, d);
-        load_reals<R, 72, 18 * MU, 18>(a.links, a.lscale, nbp, ns, Vbh, u);
+        load_reals<R, 72, 18 * MU, 18, S, true>(a.links, nullptr, nbp, ns, Vbh, u);
+        const R lsc = site_scale<R, S>(a.lscale, nbp, ns, Vbh);
         project<MU, +1>(d, h);
         su3_dag_mul(u, h, uh);
-        accum_recon<MU, +1>(rho, uh, kappa * sg);
+        accum_recon<MU, +1>(rho, uh, kappa * sg * lsc);
     }
 }
 
@@ -135,9 +136,9 @@ void sap_half_kernel(SapArgs<S, P> a) {
     constexpr int Vbh = BK::Vbh;
     constexpr bool CACHE_L = sizeof(R) == 4 && SAPDD_SAP_CACHE_LINKS;
     constexpr bool CACHE_X = sizeof(R) == 4 && SAPDD_SAP_CACHE_CLOVER;
-    __shared__ R sp[24 * Vbh];
-    __shared__ R hb[48 * Vbh];
+    __shared__ R lds_hop[HopLds<BK, R>::NBUF * HopLds<BK, R>::PER];
     __shared__ R red[3 * BK::NW];
+    HopLds<BK, R> lds{lds_hop, 0};
 
     const Geom &geo = a.geo;
     const SiteInfo si = site_info<BK>(threadIdx.x);
@@ -194,11 +195,11 @@ void sap_half_kernel(SapArgs<S, P> a) {
 
     // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o (odd: T = A_o^-1 rho_o)
     if (!even) Xc.mul(A, T, (R)1);
-    block_hop<BK>(1, si, U, T, H, sp, hb);
+    block_hop<BK>(1, si, U, T, H, lds);
     if (even) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
-            A[k] += kappa * H[k];
+            A[k] = fmac(kappa, H[k], A[k]);
             B[k] = 0;
         }
     }
@@ -206,19 +207,22 @@ void sap_half_kernel(SapArgs<S, P> a) {
     // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
     const R k2 = kappa * kappa;
     for (int it = 0; it < a.nmr; ++it) {
-        block_hop<BK>(0, si, U, A, H, sp, hb);  // odd: H = H_oe r
-        if (!even) Xc.mul(H, T, (R)1);          // odd: T = A_o^-1 H_oe r
-        block_hop<BK>(1, si, U, T, H, sp, hb);  // even: H = H_eo T
+        block_hop<BK>(0, si, U, A, H, lds);  // odd: H = H_oe r
+        if (!even) Xc.mul(H, T, (R)1);       // odd: T = A_o^-1 H_oe r
+        block_hop<BK>(1, si, U, T, H, lds);  // even: H = H_eo T
         R pr_re = 0, pr_im = 0, pp = 0;
         if (even) {
             Xc.mul(A, T, (R)1);  // even: T = p = A_e r - kappa^2 H
 #pragma unroll
-            for (int k = 0; k < 24; ++k) T[k] -= k2 * H[k];
+            for (int k = 0; k < 24; ++k) T[k] = fmac(-k2, H[k], T[k]);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                pr_re += T[2 * k] * A[2 * k] + T[2 * k + 1] * A[2 * k + 1];
-                pr_im += T[2 * k] * A[2 * k + 1] - T[2 * k + 1] * A[2 * k];
-                pp += T[2 * k] * T[2 * k] + T[2 * k + 1] * T[2 * k + 1];
+                pr_re = fmac(T[2 * k], A[2 * k], pr_re);
+                pr_re = fmac(T[2 * k + 1], A[2 * k + 1], pr_re);
+                pr_im = fmac(T[2 * k], A[2 * k + 1], pr_im);
+                pr_im = fmac(-T[2 * k + 1], A[2 * k], pr_im);
+                pp = fmac(T[2 * k], T[2 * k], pp);
+                pp = fmac(T[2 * k + 1], T[2 * k + 1], pp);
             }
         }
         block_sum3<BK>(pr_re, pr_im, pp, red);
@@ -232,29 +236,30 @@ void sap_half_kernel(SapArgs<S, P> a) {
             for (int k = 0; k < 12; ++k) {
                 const R rr = A[2 * k], ri = A[2 * k + 1];
                 const R qr = T[2 * k], qi = T[2 * k + 1];
-                B[2 * k] += ar * rr - ai * ri;
-                B[2 * k + 1] += ar * ri + ai * rr;
-                A[2 * k] = rr - (ar * qr - ai * qi);
-                A[2 * k + 1] = ri - (ar * qi + ai * qr);
+                B[2 * k] = fmac(ar, rr, fmac(-ai, ri, B[2 * k]));
+                B[2 * k + 1] = fmac(ar, ri, fmac(ai, rr, B[2 * k + 1]));
+                A[2 * k] = fmac(-ar, qr, fmac(ai, qi, rr));
+                A[2 * k + 1] = fmac(-ar, qi, fmac(-ai, qr, ri));
             }
         }
     }
 
     // ---- 4. delta: even B, odd A_o^-1 (rho_o + kappa H_oe delta_e)
-    block_hop<BK>(0, si, U, B, H, sp, hb);
+    block_hop<BK>(0, si, U, B, H, lds);
     if (!even) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) T[k] = A[k] + kappa * H[k];
+        for (int k = 0; k < 24; ++k) T[k] = fmac(kappa, H[k], A[k]);
         Xc.mul(T, B, (R)1);  // odd: B = delta_o
     }
 
     // ---- 5. outputs: psi += delta, keep delta and the even-site residual
     P *ps = a.psi + rhs * a.psi_stride;
     if (a.mode == 2) {
-        load_site<R, 24>(ps, nullptr, bp, si.s, Vbh, T);
+        R old[24];
+        load_site<R, 24>(ps, nullptr, bp, si.s, Vbh, old);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) T[k] += B[k];
-        store_site<R, 24>(ps, nullptr, bp, si.s, Vbh, T);
+        for (int k = 0; k < 24; ++k) old[k] += B[k];
+        store_site<R, 24>(ps, nullptr, bp, si.s, Vbh, old);
     } else {
         store_site<R, 24>(ps, nullptr, bp, si.s, Vbh, B);
     }
