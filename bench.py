@@ -33,7 +33,9 @@ WORKLOADS = {
     "c2_f64": ("c2_16x16x16x32_f32", "f64", {}),
     "c3": ("c3_32x32x32x64_f16", "f16", {}),
     "c3_f64_1rhs": ("c3_32x32x32x64_f16", "f64", {"nrhs": 1, "source": "gaussian"}),
-    "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 4}),
+    # 12 RHS of FGMRES(3) on 48^3x96 need ~213 GB of Krylov state: b and x stay in host
+    # memory (staged over PCIe one right-hand side at a time, inside the timed region)
+    "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 3, "host_io": True}),
 }
 
 
@@ -43,7 +45,14 @@ def percentile(v, q):
 
 def make_field(ctx, cfg):
     import synthetic
-    u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"])
+    vol = int(np.prod(cfg["dims"]))
+    prog = None
+    if vol > 4_000_000:  # long generation: report progress so the run is visibly alive
+        def prog(done, total, _last=[0.0]):
+            if time.time() - _last[0] > 20:
+                print(f"# gauge field: {done}/{total} sites", flush=True)
+                _last[0] = time.time()
+    u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"], progress=prog)
     f = ctx.load_gauge(u, cfg["block"])
     f.compute_clover(cfg["csw"])
     return u, f
@@ -266,8 +275,12 @@ def main():
     torch.cuda.set_stream(stream)
     ctx = Context(0, stream=stream)
     u, field = make_field(ctx, cfg)
-    b = torch.from_numpy(make_source(cfg)).cuda()
-    x = torch.empty_like(b)
+    b = make_source(cfg)
+    if cfg.get("host_io"):
+        x = np.empty_like(b)
+    else:
+        b = torch.from_numpy(b).cuda()
+        x = torch.empty_like(b)
     nrhs = b.shape[0]
     cfg["nrhs_active"] = nrhs
 
@@ -296,13 +309,16 @@ def main():
     relres = [s["true_relres"] for s in stats]
     ok = all(s["converged"] for s in stats)
 
-    # oracle check of the last solution's residual (first right-hand side)
-    from oracle import wilson
-    t_or = wilson.clover_term(u, cfg["csw"])
-    x0 = x[0].cpu().numpy()
-    b0 = b[0].cpu().numpy()
-    oracle_relres = float(np.linalg.norm(b0 - wilson.apply_M(u, t_or, cfg["kappa"], x0)) / np.linalg.norm(b0))
-    del t_or
+    # oracle check of the last solution's residual (first right-hand side); above 4M sites
+    # the NumPy operator needs minutes and tens of GB, so it is left to the parity tests
+    oracle_relres = None
+    if int(np.prod(cfg["dims"])) <= 4_000_000:
+        from oracle import wilson
+        t_or = wilson.clover_term(u, cfg["csw"])
+        x0 = x[0] if isinstance(x, np.ndarray) else x[0].cpu().numpy()
+        b0 = b[0] if isinstance(b, np.ndarray) else b[0].cpu().numpy()
+        oracle_relres = float(np.linalg.norm(b0 - wilson.apply_M(u, t_or, cfg["kappa"], x0)) / np.linalg.norm(b0))
+        del t_or
 
     line = {
         "metric": "Dslash HBM GB/s (% peak); SAP-FGMRES solves/s @ rel. residual 1e-10; p50/p99",

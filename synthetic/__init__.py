@@ -40,12 +40,13 @@ def _exp_i_eps_h(g: np.ndarray, eps: float) -> np.ndarray:
     return np.einsum("...ab,...b,...cb->...ac", v, ph, np.conj(v))
 
 
-def gauge_field(dims, eps: float, seed: int, chunk_sites: int = 1 << 18) -> np.ndarray:
+def gauge_field(dims, eps: float, seed: int, chunk_sites: int = 1 << 18, progress=None) -> np.ndarray:
     """Random SU(3) gauge field U[t,z,y,x,mu,3,3] for lattice dims = (Lx, Ly, Lz, Lt).
 
     Links are generated in site chunks; numpy's Generator produces the same stream
     whether the normals are drawn at once or chunk by chunk, so the result does not
-    depend on chunk_sites.
+    depend on chunk_sites. `progress(done_sites, total_sites)` is called after every
+    chunk if given.
     """
     lx, ly, lz, lt = (int(d) for d in dims)
     vol = lx * ly * lz * lt
@@ -56,6 +57,8 @@ def gauge_field(dims, eps: float, seed: int, chunk_sites: int = 1 << 18) -> np.n
         g = rng.standard_normal((n, 4, 3, 3, 2))
         gc = g[..., 0] + 1j * g[..., 1]
         out[s0:s0 + n] = _exp_i_eps_h(gc, eps)
+        if progress is not None:
+            progress(s0 + n, vol)
     return out.reshape(lt, lz, ly, lx, 4, 3, 3)
 
 
