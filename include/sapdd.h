@@ -187,8 +187,10 @@ typedef struct {
     long long launches[SAPDD_K_COUNT];
     double seconds[SAPDD_K_COUNT];
 } sapdd_kernel_profile;
-/* Read (if out != NULL) and reset the accumulated profile, then switch profiling on
- * (enable != 0) or off. Reading waits for the context's stream. */
+/* Read (if out != NULL) and reset the accumulated profile, then switch profiling off
+ * (enable = 0), on for every family (enable = 1) or on for the families whose bits are
+ * set in enable >> 1 (bit k = family k; few families = fewer event records in flight).
+ * Reading waits for the context's stream. */
 int sapdd_profile(sapdd_ctx *ctx, int enable, sapdd_kernel_profile *out);
 
 #ifdef __cplusplus

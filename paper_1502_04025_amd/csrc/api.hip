@@ -65,8 +65,10 @@ struct sapdd_ctx {
     size_t pinned_n = 0;
     hipEvent_t ev[8] = {};
     sapdd_batch *solve_batch = nullptr;  // kept between sapdd_solve calls
-    // kernel profiling: event pairs recorded around launches, drained at sync points
-    bool prof = false;
+    // kernel profiling: event pairs recorded around launches of the selected families
+    // (bit k of prof_mask = family k), drained at sync points
+    bool prof = false, prof_open = false;
+    unsigned prof_mask = 0;
     std::vector<hipEvent_t> pev;
     std::vector<int> pkind, pcount;
     size_t pn = 0;
@@ -111,7 +113,8 @@ int prof_drain(sapdd_ctx *c) {
 
 // Record the start event of a profiled launch of family `kind` (no-op when profiling is off).
 int prof_begin(sapdd_ctx *c, int kind) {
-    if (!c->prof) return SAPDD_OK;
+    c->prof_open = c->prof && (c->prof_mask >> kind & 1u);
+    if (!c->prof_open) return SAPDD_OK;
     if (2 * (c->pn + 1) > c->pev.size()) {
         if (c->pev.size() >= 8192) {  // pool full: wait for the stream and drain it
             HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -133,7 +136,8 @@ int prof_begin(sapdd_ctx *c, int kind) {
 
 // End a profiled region that contained `count` launches of its family (a graph replay).
 int prof_end(sapdd_ctx *c, int count = 1) {
-    if (!c->prof) return SAPDD_OK;
+    if (!c->prof_open) return SAPDD_OK;
+    c->prof_open = false;
     c->pcount[c->pn] = count;
     HIPCHK(c, hipEventRecord(c->pev[2 * c->pn + 1], c->stream));
     c->pn += 1;
@@ -674,6 +678,7 @@ int sapdd_profile(sapdd_ctx *c, int enable, sapdd_kernel_profile *out) {
         c->psec[k] = 0;
     }
     c->prof = enable != 0;
+    c->prof_mask = enable == 1 ? ~0u : (unsigned)enable >> 1;
     return SAPDD_OK;
 }
 

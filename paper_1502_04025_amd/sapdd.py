@@ -184,11 +184,14 @@ class Context:
                                               DEVICE_PTRS if dev else 0, C.byref(h)))
         return Field(self, h, (lx, ly, lz, lt), tuple(int(b) for b in block))
 
-    def profile(self, enable: bool):
+    def profile(self, enable, families=None):
         """Return the per-kernel profile accumulated so far, reset it and switch
-        profiling on or off."""
+        profiling on or off; `families` (names from KERNELS) limits the recording."""
         kp = KernelProfile()
-        self._check(self.lib.sapdd_profile(self.h, int(bool(enable)), C.byref(kp)))
+        code = int(bool(enable))
+        if enable and families:
+            code = sum(1 << KERNELS.index(f) for f in families) << 1
+        self._check(self.lib.sapdd_profile(self.h, code, C.byref(kp)))
         return kp.as_dict()
 
     def copy(self, src, dst, nbytes: int):
