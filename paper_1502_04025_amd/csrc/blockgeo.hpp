@@ -72,11 +72,12 @@ template <class S, class R> struct SiteLinks<S, R, true> {
     static constexpr int W = Vec<S>::W;
     VT u[72 / W];
     R sc;
+    template <bool NT = false>
     __device__ __forceinline__ void init(const S *__restrict__ base, const float *__restrict__ scale,
                                          int64_t bp, int s, int Vbh) {
         const VT *p = reinterpret_cast<const VT *>(base);
 #pragma unroll
-        for (int v = 0; v < 72 / W; ++v) u[v] = p[vec_index<S, 72>(bp, v, s, Vbh)];
+        for (int v = 0; v < 72 / W; ++v) u[v] = ld_vec<NT>(p + vec_index<S, 72>(bp, v, s, Vbh));
         if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
         else sc = (R)1;
     }
@@ -125,11 +126,12 @@ template <class S, class R> struct CloverRegs {
     static constexpr int W = Vec<S>::W;
     VT x[72 / W];
     R sc;
+    template <bool NT = false>
     __device__ __forceinline__ void load(const S *__restrict__ base, const float *__restrict__ scale, int64_t bp,
                                          int s, int Vbh) {
         const VT *p = reinterpret_cast<const VT *>(base);
 #pragma unroll
-        for (int v = 0; v < 72 / W; ++v) x[v] = p[vec_index<S, 72>(bp, v, s, Vbh)];
+        for (int v = 0; v < 72 / W; ++v) x[v] = ld_vec<NT>(p + vec_index<S, 72>(bp, v, s, Vbh));
         if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
         else sc = (R)1;
     }

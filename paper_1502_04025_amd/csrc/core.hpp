@@ -76,9 +76,20 @@ template <class S> struct CFieldPtr {
     const float *scale;
 };
 
+// One 16-byte vector load / store. NT = true marks data that is streamed through once
+// (non-temporal cache hint); fields that other workgroups re-read keep the default.
+template <bool NT, class VT> __device__ __forceinline__ VT ld_vec(const VT *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class VT> __device__ __forceinline__ void st_vec(VT *p, const VT &x) {
+    if constexpr (NT) __builtin_nontemporal_store(x, p);
+    else *p = x;
+}
+
 // Reals [K0, K0 + K) of site (bp, s) of an N-real field, through whole 16-byte vectors.
 // With RAW the FP16 site scale is not applied (the caller folds it into a result).
-template <class R, int N, int K0, int K, class S, bool RAW = false>
+template <class R, int N, int K0, int K, class S, bool RAW = false, bool NT = false>
 __device__ __forceinline__ void load_reals(const S *__restrict__ data, const float *__restrict__ scale, int64_t bp,
                                            int s, int Vbh, R out[K]) {
     typedef typename Vec<S>::type VT;
@@ -89,7 +100,7 @@ __device__ __forceinline__ void load_reals(const S *__restrict__ data, const flo
     if constexpr (Storage<S>::scaled && !RAW) sc = (R)scale[bp * Vbh + s];
 #pragma unroll
     for (int v = v0; v <= v1; ++v) {
-        const VT x = p[vec_index<S, N>(bp, v, s, Vbh)];
+        const VT x = ld_vec<NT>(p + vec_index<S, N>(bp, v, s, Vbh));
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const int k = v * W + w - K0;
@@ -109,15 +120,15 @@ __device__ __forceinline__ R site_scale(const float *__restrict__ scale, int64_t
     else return (R)1;
 }
 
-template <class R, int N, class S>
+template <class R, int N, class S, bool NT = false>
 __device__ __forceinline__ void load_site(const S *__restrict__ data, const float *__restrict__ scale,
                                           int64_t bp, int s, int Vbh, R out[N]) {
-    load_reals<R, N, 0, N, S>(data, scale, bp, s, Vbh, out);
+    load_reals<R, N, 0, N, S, false, NT>(data, scale, bp, s, Vbh, out);
 }
 
 // Store N reals of one site; FP16 storage divides by the site's max |value| and rounds
 // to nearest even (scale 0 stores zeros).
-template <class R, int N, class S>
+template <class R, int N, class S, bool NT = false>
 __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restrict__ scale, int64_t bp,
                                            int s, int Vbh, const R in[N]) {
     typedef typename Vec<S>::type VT;
@@ -134,7 +145,7 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
             VT x;
 #pragma unroll
             for (int w = 0; w < W; ++w) x[w] = (half_t)((float)in[v * W + w] * inv);
-            p[vec_index<S, N>(bp, v, s, Vbh)] = x;
+            st_vec<NT>(p + vec_index<S, N>(bp, v, s, Vbh), x);
         }
     } else {
 #pragma unroll
@@ -142,7 +153,7 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
             VT x;
 #pragma unroll
             for (int w = 0; w < W; ++w) x[w] = (S)in[v * W + w];
-            p[vec_index<S, N>(bp, v, s, Vbh)] = x;
+            st_vec<NT>(p + vec_index<S, N>(bp, v, s, Vbh), x);
         }
     }
 }

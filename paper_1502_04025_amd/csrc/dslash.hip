@@ -226,19 +226,23 @@ __global__ __launch_bounds__(BK::NT) void dslash_block_kernel(Geom geo, CF<S> li
     const int64_t ioff = (int64_t)rhs * geo.V * 24, soff = (int64_t)rhs * geo.V;
     // links held in registers between the two half-hops (re-reading them from L1/L2 to
     // reach 4 waves per SIMD measured slower: 3.65 vs 4.53 TB/s in FP16)
+    // Every byte this kernel touches is used by one workgroup only: non-temporal hints
+    // (measured 4.71 -> 5.52 TB/s in FP32, 4.49 -> 4.80 TB/s in FP16 on 32^3x64). Issuing
+    // the clover loads before the hops instead of after measured slower.
+    constexpr bool NT = true;
     SiteLinks<S, R, true> U;
-    U.init(links.data, links.scale, bp, si.s, Vbh);
+    U.template init<NT>(links.data, links.scale, bp, si.s, Vbh);
     R psi[24], hop[24];
-    load_site<R, 24>(in.data + ioff, in.scale ? in.scale + soff : nullptr, bp, si.s, Vbh, psi);
+    load_site<R, 24, S, NT>(in.data + ioff, in.scale ? in.scale + soff : nullptr, bp, si.s, Vbh, psi);
     block_hop<BK>(0, si, U, psi, hop, lds);  // odd sites receive
     block_hop<BK>(1, si, U, psi, hop, lds);  // even sites receive
     R res[24];
     CloverRegs<S, R> cl;
-    cl.load(tclov.data, tclov.scale, bp, si.s, Vbh);
+    cl.template load<NT>(tclov.data, tclov.scale, bp, si.s, Vbh);
     clover_mul(cl, psi, res, kappa);
 #pragma unroll
     for (int c = 0; c < 24; ++c) res[c] = fmac(-kappa, hop[c], res[c]);
-    store_site<R, 24>(out.data + ioff, out.scale ? out.scale + soff : nullptr, bp, si.s, Vbh, res);
+    store_site<R, 24, S, NT>(out.data + ioff, out.scale ? out.scale + soff : nullptr, bp, si.s, Vbh, res);
 }
 
 template <class BK>

