@@ -148,8 +148,8 @@ template <class S, class R> struct CloverRegs {
 
 // out = in + kx * X in for the two packed Hermitian 6x6 blocks of X: X in is accumulated
 // from the stored entries with FMAs and scaled once (kx times the site scale).
-template <class S, class R>
-__device__ __forceinline__ void clover_mul(const CloverRegs<S, R> &X, const R (&in)[24], R (&out)[24], R kx) {
+template <class XR, class R>
+__device__ __forceinline__ void clover_mul(const XR &X, const R (&in)[24], R (&out)[24], R kx) {
     const R f = kx * X.scale();
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {

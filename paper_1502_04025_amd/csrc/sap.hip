@@ -80,6 +80,22 @@ __device__ __forceinline__ void block_sum3(R &a, R &b, R &c, R *red) {
 #define SAPDD_SAP_CACHE_CLOVER 0
 #endif
 
+#ifndef SAPDD_SAP_XLDS
+#define SAPDD_SAP_XLDS 1
+#endif
+
+// The clover of a thread's own site held in LDS (thread-private slots k * Vbh + s).
+template <class S, class R, int Vbh> struct LdsClover {
+    const S *x;
+    int s;
+    R sc;
+    __device__ __forceinline__ R at(int k) const {
+        if constexpr (Storage<S>::scaled) return (R)(float)x[k * Vbh + s];
+        else return (R)x[k * Vbh + s];
+    }
+    __device__ __forceinline__ R scale() const { return sc; }
+};
+
 #ifndef SAPDD_SAP_WAVES_PER_EU
 #define SAPDD_SAP_WAVES_PER_EU 2
 #endif
@@ -141,9 +157,17 @@ void sap_half_kernel(SapArgs<S, P> a) {
     // extra live spinor across the hop costs more registers than the overlap gains
     // (8x4^3 FP32: 84 -> 127 us), so A_e r is formed after the hop there.
     constexpr bool EARLY_AE = Storage<S>::scaled;
-    __shared__ R lds_hop[HopLds<BK, R>::NBUF * HopLds<BK, R>::PER];
+    // XL: on 8x4x4x4 blocks the even sites' clover is copied into LDS once and read from
+    // there in every MR step, and the hop uses one LDS buffer. With FP32 storage the links
+    // and clover of the 16 blocks an XCD works on at once exceed its 4 MB L2 otherwise
+    // (16^3x32, 1 RHS: 83.7 -> 74.6 us per half-sweep). Links in LDS, or the odd sites'
+    // clover as well (FP16), measured slower.
+    constexpr bool XL = SAPDD_SAP_XLDS && sizeof(R) == 4 && BK::Vbh == 256;
+    constexpr int HB = XL ? 1 : 2;
+    __shared__ R lds_hop[HopLds<BK, R, HB>::NBUF * HopLds<BK, R, HB>::PER];
+    __shared__ S xl[XL ? 72 * Vbh : 1];
     __shared__ R red[3 * BK::NW];
-    HopLds<BK, R> lds{lds_hop, 0};
+    HopLds<BK, R, HB> lds{lds_hop, 0};
 
     const Geom &geo = a.geo;
     const SiteInfo si = site_info<BK>(threadIdx.x);
@@ -166,6 +190,22 @@ void sap_half_kernel(SapArgs<S, P> a) {
     U.init(a.links, a.lscale, bp, si.s, Vbh);
     SiteClover<S, R, CACHE_X> Xc;
     Xc.init(a.X[rhs], a.Xsc ? a.Xsc[rhs] : nullptr, bp, si.s, Vbh);
+    LdsClover<S, R, Vbh> Xe{xl, si.s, (R)1};
+    if (XL && even) {
+        CloverRegs<S, R> c;
+        c.load(a.X[rhs], a.Xsc ? a.Xsc[rhs] : nullptr, bp, si.s, Vbh);
+        constexpr int W = Vec<S>::W;
+#pragma unroll
+        for (int v = 0; v < 72 / W; ++v)
+#pragma unroll
+            for (int q = 0; q < W; ++q) xl[(v * W + q) * Vbh + si.s] = c.x[v][q];
+        Xe.sc = c.scale();
+    }
+    // even sites: T = (1 + X) in
+    auto mul_even = [&](const R(&in)[24], R(&out)[24]) {
+        if constexpr (XL) clover_mul(Xe, in, out, (R)1);
+        else Xc.mul(in, out, (R)1);
+    };
 
     S *dlt = a.delta + (int64_t)rhs * V * 24;
     float *dlt_sc = a.delta_sc ? a.delta_sc + (int64_t)rhs * V : nullptr;
@@ -213,12 +253,12 @@ void sap_half_kernel(SapArgs<S, P> a) {
     const R k2 = kappa * kappa;
     for (int it = 0; it < a.nmr; ++it) {
         block_hop<BK>(0, si, U, A, H, lds);  // odd: H = H_oe r
-        if (EARLY_AE && even) Xc.mul(A, T, (R)1);  // even: T = A_e r (needs only r)
-        if (!even) Xc.mul(H, T, (R)1);       // odd: T = A_o^-1 H_oe r
+        if (EARLY_AE && even) mul_even(A, T);  // even: T = A_e r (needs only r)
+        if (!even) Xc.mul(H, T, (R)1);           // odd: T = A_o^-1 H_oe r
         block_hop<BK>(1, si, U, T, H, lds);  // even: H = H_eo T
         R pr_re = 0, pr_im = 0, pp = 0;
         if (even) {
-            if (!EARLY_AE) Xc.mul(A, T, (R)1);  // even: T = p = A_e r - kappa^2 H
+            if (!EARLY_AE) mul_even(A, T);  // even: T = p = A_e r - kappa^2 H
 #pragma unroll
             for (int k = 0; k < 24; ++k) T[k] = fmac(-k2, H[k], T[k]);
 #pragma unroll
