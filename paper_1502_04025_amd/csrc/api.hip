@@ -1196,7 +1196,10 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     } else {
         HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
     }
-    // |b|
+    // |b|. From x0 = 0 the first residual is b itself: it goes straight into basis slot 0
+    // with vscale[0] = 1/|b|, and no operator application is needed for it.
+    double *v0slot = (double *)B->Vb.data + (size_t)r * (B->m + 1) * B->NS;
+    if (!x0) HIPCHK(c, launch_copy(bslot.data, v0slot, (int64_t)B->NS * 8, c->stream));
     std::vector<int> one(1, r);
     int *d_one;
     CHK(upload(B, SEG_CHECK, one, &d_one));
@@ -1210,7 +1213,7 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     a.n = B->ncx;
     KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
     KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, blas_partials(B->ncx, 1), 1, d_one, 1, B->coef + B->noff, B->CST,
-                                         nullptr, 0, 0, nullptr, 0, c->stream));
+                                         nullptr, 0, 0, x0 ? nullptr : B->vscale, B->m + 1, c->stream));
     CHK(fetch_coef(B));
     s.bnorm = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
     if (s.bnorm == 0.0) {
@@ -1220,8 +1223,20 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     } else if (!std::isfinite(s.bnorm)) {
         s.finished = true;
         s.status = SAPDD_ENAN;
+    } else if (x0) {
+        s.dirty = true;  // its first residual b - M x0 is computed by the next step
     } else {
-        s.dirty = true;  // its first residual is computed by the next step
+        s.beta = s.bnorm;  // the residual bookkeeping of batch_residual for r = b
+        s.true_relres = 1.0;
+        if (s.true_relres <= B->p.tol) {
+            s.converged = 1;
+            s.finished = true;
+        } else if (s.iters >= B->p.max_iter) {
+            s.status = SAPDD_ENOCONV;
+            s.finished = true;
+        } else {
+            s.ready = true;
+        }
     }
     *slot_out = r;
     return SAPDD_OK;

@@ -41,8 +41,11 @@ int blas_partials(int64_t n, int nact) {
     return (int)want;
 }
 
+// Partial sums are stored value-major per slot: value k of workgroup q at out[k * nwg]
+// relative to the slot's and workgroup's base, so that the reduction of one value reads
+// contiguous memory.
 template <int NVAL>
-__device__ __forceinline__ void wg_reduce_store(double (&v)[NVAL], double *out) {
+__device__ __forceinline__ void wg_reduce_store(double (&v)[NVAL], double *out, int nwg) {
     __shared__ double red[BLAS_WG / 64][NVAL > 0 ? NVAL : 1];
 #pragma unroll
     for (int k = 0; k < NVAL; ++k)
@@ -56,7 +59,7 @@ __device__ __forceinline__ void wg_reduce_store(double (&v)[NVAL], double *out) 
         double t = 0;
 #pragma unroll
         for (int q = 0; q < BLAS_WG / 64; ++q) t += red[q][threadIdx.x];
-        out[threadIdx.x] = t;
+        out[(int64_t)threadIdx.x * nwg] = t;
     }
 }
 
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
             acc[0] += ww.x * ww.x + ww.y * ww.y;
         }
     }
-    wg_reduce_store<NVAL>(acc, a.part + ((int64_t)slot * gridDim.x + blockIdx.x) * NVAL);
+    wg_reduce_store<NVAL>(acc, a.part + (int64_t)slot * NVAL * gridDim.x + blockIdx.x, (int)gridDim.x);
 }
 
 template <int MODE, int NV>
@@ -135,37 +138,38 @@ hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// One workgroup per (slot, value): out[rhs * ostride + k] = sum over the nwg partial sums
+// of value k, added in a fixed order (times mul[rhs * mstride + v0 + k / 2] if given);
+// for k = 0 also isq[rhs * istride] = 1 / sqrt(sum) if isq is given.
 __global__ __launch_bounds__(BLAS_WG) void reduce_kernel(const double *part, int nwg, int nval, const int *active,
                                                          double *out, int ostride, const double *mul, int mstride,
                                                          int v0, double *isq, int istride) {
     __shared__ double red[BLAS_WG / 64];
     const int slot = blockIdx.x;
+    const int k = blockIdx.y;
     const int rhs = active[slot];
-    const double *p = part + (int64_t)slot * nwg * nval;
-    for (int k = 0; k < nval; ++k) {
-        double t = 0;
-        for (int q = threadIdx.x; q < nwg; q += BLAS_WG) t += p[(int64_t)q * nval + k];
+    const double *p = part + ((int64_t)slot * nval + k) * nwg;
+    double t = 0;
+    for (int q = threadIdx.x; q < nwg; q += BLAS_WG) t += p[q];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0;
-            for (int q = 0; q < BLAS_WG / 64; ++q) s += red[q];
-            if (mul) s *= mul[(int64_t)rhs * mstride + v0 + k / 2];
-            out[(int64_t)rhs * ostride + k] = s;
-            if (isq && k == 0) isq[(int64_t)rhs * istride] = s > 0 ? 1.0 / sqrt(s) : 0.0;
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int q = 0; q < BLAS_WG / 64; ++q) s += red[q];
+        if (mul) s *= mul[(int64_t)rhs * mstride + v0 + k / 2];
+        out[(int64_t)rhs * ostride + k] = s;
+        if (isq && k == 0) isq[(int64_t)rhs * istride] = s > 0 ? 1.0 / sqrt(s) : 0.0;
     }
 }
 
 hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
                          int ostride, const double *mul, int mstride, int v0, double *isq, int istride,
                          hipStream_t st) {
-    if (nact <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(nact), dim3(BLAS_WG), 0, st, part, nwg, nval, active, out, ostride, mul,
-                       mstride, v0, isq, istride);
+    if (nact <= 0 || nval <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(nact, nval), dim3(BLAS_WG), 0, st, part, nwg, nval, active, out, ostride,
+                       mul, mstride, v0, isq, istride);
     return hipGetLastError();
 }
 

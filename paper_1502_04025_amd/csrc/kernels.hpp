@@ -108,7 +108,7 @@ int blas_partials(int64_t n, int nact);
 // mode 2: w -= sum_i coef_i s_i v_i, then partial |w|^2. Coefficient i of the pass is
 // coef[2 (v0 + i)] (re, im).
 hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st);
-// For every slot: v_k = sum over wg of part[slot][wg][k] (fixed order), times
+// For every slot: v_k = sum over wg of part[slot][k][wg] (fixed order), times
 // mul[rhs * mstride + v0 + k / 2] if mul is set; written to out[rhs * ostride + k].
 // If isq is set, isq[rhs * istride] = 1 / sqrt(v_0) (0 if v_0 <= 0).
 hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
