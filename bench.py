@@ -33,9 +33,11 @@ WORKLOADS = {
     "c2_f64": ("c2_16x16x16x32_f32", "f64", {}),
     "c3": ("c3_32x32x32x64_f16", "f16", {}),
     "c3_f64_1rhs": ("c3_32x32x32x64_f16", "f64", {"nrhs": 1, "source": "gaussian"}),
-    # 12 RHS of FGMRES(3) on 48^3x96 need ~213 GB of Krylov state: b and x stay in host
-    # memory (staged over PCIe one right-hand side at a time, inside the timed region)
-    "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 3, "host_io": True}),
+    # 12 RHS of FGMRES(3) on 48^3x96 need ~213 GB of Krylov state; b and x (6 GB) stay
+    # resident in HBM beside it. c5_host_io keeps them in host memory instead (staged over
+    # PCIe one right-hand side at a time, inside the timed region).
+    "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 3}),
+    "c5_host_io": ("c5_48x48x48x96_f16", "f16", {"restart": 3, "host_io": True}),
 }
 
 
