@@ -48,12 +48,8 @@ constexpr int DSLASH_WG = 256;
 
 
 
-#ifndef SAPDD_FULL_WAVES_PER_EU
-#define SAPDD_FULL_WAVES_PER_EU 2
-#endif
-
 template <class BK, class S, class TI, class TO, class R>
-__global__ __launch_bounds__(DSLASH_WG) __attribute__((amdgpu_waves_per_eu(SAPDD_FULL_WAVES_PER_EU))) void dslash_full_kernel(Geom geo, CF<S> links, CF<S> tclov, R kappa,
+__global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> links, CF<S> tclov, R kappa,
                                                                  CF<TI> in, MF<TO> out, const double *sub,
                                                                  double *part, const int *active, int nact,
                                                                  int nchunk, int ins_, int outs_, int subs_,
