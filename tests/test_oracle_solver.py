@@ -213,3 +213,62 @@ def test_dense_lu_4444_sap_fgmres(system, eta):
     # SAP is a strong preconditioner: far fewer iterations than unpreconditioned GMRES
     _, info_id = fg.fgmres(mfun, lambda v: v, eta, m=16, tol=1e-10)
     assert info["iters"] < info_id["iters"]
+
+
+# ---- flexible GMRES with deflated restarts
+
+def _normal_matrix_with_small_eigenvalues(n=160, small=(1e-3, 2e-3 + 1e-3j, 3e-3, 4e-3 - 5e-4j), seed=5):
+    """A = Q diag(lambda) Q^H with a few eigenvalues near 0 and the rest in [1, 3]: restarted
+    GMRES stalls on the small ones, deflation removes them."""
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.concatenate([np.array(small, dtype=np.complex128), rng.uniform(1.0, 3.0, n - len(small))])
+    return (q * lam) @ q.conj().T, lam
+
+
+def test_fgmres_dr_without_deflation_is_restarted_fgmres(system, eta):
+    """k = 0 restarts from the recursive residual V s instead of the recomputed true
+    residual: in exact arithmetic the same vector, so the iterates agree to rounding."""
+    mfun = _ops(system)
+    prec = lambda v: sap.sap(system, v, 2, 1)  # noqa: E731
+    x0, i0 = fg.fgmres(mfun, prec, eta, m=3, tol=1e-9, max_iter=60)
+    x1, i1 = fg.fgmres_dr(mfun, prec, eta, m=3, k=0, tol=1e-9, max_iter=60)
+    assert i0["converged"] and i1["converged"] and i0["restarts"] > 2
+    assert i1["iters"] == i0["iters"]
+    assert np.linalg.norm(x1 - x0) <= 1e-7 * np.linalg.norm(x0)
+
+
+def test_fgmres_dr_arnoldi_relation_after_deflated_restart(system, eta):
+    """After deflated restarts the cycle still satisfies M Z = V Hbar with orthonormal V,
+    and c holds the residual's coordinates: V c = b - M x at the cycle start."""
+    mfun = _ops(system)
+    prec = lambda v: sap.sap(system, v, 2, 1)  # noqa: E731
+    rec = {}
+    x, info = fg.fgmres_dr(mfun, prec, eta, m=4, k=2, tol=1e-30, max_iter=10, record=rec)
+    assert info["restarts"] >= 3 and len(rec["theta"]) >= 2
+    v = np.array([a.reshape(-1) for a in rec["V"]]).T
+    z = np.array([a.reshape(-1) for a in rec["Z"]]).T
+    h = rec["H"]
+    assert np.max(np.abs(v.conj().T @ v - np.eye(v.shape[1]))) < 1e-9
+    mz = np.array([mfun(a).reshape(-1) for a in rec["Z"]]).T
+    assert np.linalg.norm(mz - v @ h) < 1e-11 * np.linalg.norm(mz)
+    assert np.abs(h[2, 0]) > 0 and np.abs(h[2, 1]) > 0 or h.shape[1] < 2  # dense leading block
+
+
+def test_fgmres_dr_deflation_finds_small_eigenvalues_and_accelerates():
+    """On A = Q diag(lambda) Q^H (identity preconditioner), GMRES-DR(10, 4) converges in a
+    fraction of the iterations restarted GMRES(10) needs, and its harmonic Ritz values
+    converge to the four small eigenvalues."""
+    a, lam = _normal_matrix_with_small_eigenvalues()
+    b = np.random.default_rng(6).standard_normal(a.shape[0]) + 0j
+    mfun = lambda v: a @ v  # noqa: E731
+    ident = lambda v: v  # noqa: E731
+    _, plain = fg.fgmres(mfun, ident, b, m=10, tol=1e-10, max_iter=1500)
+    rec = {}
+    x, dr = fg.fgmres_dr(mfun, ident, b, m=10, k=4, tol=1e-10, max_iter=1500, record=rec)
+    assert dr["converged"]
+    assert np.linalg.norm(b - a @ x) <= 1e-10 * np.linalg.norm(b) * 1.0001
+    assert dr["iters"] * 4 < (plain["iters"] if plain["converged"] else 1500)
+    got = np.sort_complex(rec["theta"][-1])
+    want = np.sort_complex(lam[:4])
+    assert np.max(np.abs(got - want)) < 1e-6
