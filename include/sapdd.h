@@ -80,6 +80,11 @@ typedef struct {
     double tol;     /* target true relative residual |b - M x| / |b|               */
     int sap_prec;   /* storage precision inside SAP: SAPDD_F64, SAPDD_F32, SAPDD_F16 */
     int flags;      /* SAPDD_DEVICE_PTRS | SAPDD_USE_X0 | SAPDD_NO_GRAPH          */
+    int deflate;    /* deflated restarts (Sec. 3.1, flexible GMRES with deflated
+                     * restarts): k harmonic Ritz vectors of the cycle's Hessenberg
+                     * matrix, those of smallest modulus, are kept across each full
+                     * restart (0 = plain restarts; 0 <= k < restart). With k > 0 the
+                     * preconditioned vectors Z are held in FP64 whatever sap_prec is.  */
 } sapdd_params;
 
 /* Per right-hand-side result of sapdd_solve. Times are seconds of device time

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/sapdd.h"
+#include "dense.hpp"
 #include "kernels.hpp"
 
 using namespace sapdd;
@@ -653,7 +654,7 @@ long long sapdd_solve_footprint(const sapdd_field *f, const sapdd_params *p, int
     const int m = std::max(1, p->restart);
     const int prec = p->sap_prec;
     const long long sb = prec == P64 ? 8 : prec == P32 ? 4 : 2;
-    const long long zb = prec == P64 ? 8 : 4;
+    const long long zb = prec == P64 || p->deflate > 0 ? 8 : 4;
     long long per_rhs = (m + 1) * V * 24 * 8     // Krylov basis V
                         + (long long)m * V * 24 * zb  // preconditioned vectors Z
                         + 2 * V * 24 * 8              // b and x in the device layout
@@ -711,10 +712,17 @@ struct Slot {
     bool used = false, finished = false, ready = false, dirty = false, in_cycle = false;
     double kappa = 0, bnorm = 0, beta = 0, est = 0, true_relres = 0;
     int iters = 0, restarts = 0, converged = 0, nz = 0, status = SAPDD_OK;
-    std::vector<cd> H, cs, sn, gv;
+    std::vector<cd> H, cs, sn, gv;  // Hessenberg matrix as the Givens rotations leave it
+    // Deflated restarts: Hr is the cycle's Hbar as built ((m+1) x m, column-major), c0 the
+    // coordinates of the residual in the basis at the cycle start, j0 the first Arnoldi
+    // step of the cycle, y the last least-squares solution; `deflated` marks a cycle that
+    // continues a deflated basis (dense leading block, solved without the Givens update).
+    std::vector<cd> Hr, c0, y;
+    int j0 = 0;
+    bool deflated = false;
 };
 
-enum { SEG_CHECK = 0, SEG_CYCLE = 1, SEG_GROUP = 2, NSEG = 8 };
+enum { SEG_CHECK = 0, SEG_CHECK2 = 1, SEG_CYCLE = 2, SEG_DEFL = 3, SEG_GROUP = 4, NSEG = 10 };
 
 }  // namespace
 
@@ -722,12 +730,13 @@ struct sapdd_batch {
     sapdd_ctx *c = nullptr;
     sapdd_field *f = nullptr;
     sapdd_params p{};
-    int cap = 0, m = 0, prec = 0, zprec = 0;
+    int cap = 0, m = 0, k = 0, prec = 0, zprec = 0;
     Geom g{};
     int64_t NS = 0, ncx = 0;
     Fld Vb{}, Zb{}, Bb{}, Xb{};
     SapState ss{};
     double *coef = nullptr, *vscale = nullptr, *part = nullptr, *ydev = nullptr;
+    double *pdev = nullptr, *hp = nullptr;  // deflation bases per slot, (m+1) x (k+1) complex (device, pinned host)
     int *dlists = nullptr;
     char *pin = nullptr;
     int *hlists = nullptr;
@@ -789,23 +798,32 @@ int fetch_coef(sapdd_batch *B) {
 int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
     if (list.empty()) return SAPDD_OK;
     sapdd_ctx *c = B->c;
-    int *d_list;
-    CHK(upload(B, SEG_CHECK, list, &d_list));
+    // Slots that continue a deflated basis keep basis vectors 0..k: their true residual
+    // goes to the spare vector m and only its norm is used.
+    std::vector<int> plain, defl;
+    for (int r : list) (B->slots[r].deflated ? defl : plain).push_back(r);
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    DslashIO io{};
-    io.in = B->Xb;
-    io.out = Fld{B->Vb.data, nullptr, P64};
-    io.sub = (const double *)B->Bb.data;
-    io.part = B->part;
-    io.active = d_list;
-    io.nact = (int)list.size();
-    io.in_stride = 1;
-    io.out_stride = B->m + 1;
-    io.sub_stride = 1;
-    io.kappa = B->ss.kappa;
-    KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(B->g, links_of(B->f, P64), tclov_of(B->f, P64), 0.0, io, c->stream));
-    KLAUNCH(c, SAPDD_K_DSLASH, launch_reduce(B->part, B->nwg_d, 1, d_list, io.nact, B->coef + B->noff, B->CST, nullptr,
-                                             0, 0, B->vscale, B->m + 1, c->stream));
+    for (int g = 0; g < 2; ++g) {
+        const std::vector<int> &l = g == 0 ? plain : defl;
+        if (l.empty()) continue;
+        int *d_list;
+        CHK(upload(B, g == 0 ? SEG_CHECK : SEG_CHECK2, l, &d_list));
+        DslashIO io{};
+        io.in = B->Xb;
+        io.out = Fld{(double *)B->Vb.data + (g == 0 ? 0 : (size_t)B->m * B->NS), nullptr, P64};
+        io.sub = (const double *)B->Bb.data;
+        io.part = B->part;
+        io.active = d_list;
+        io.nact = (int)l.size();
+        io.in_stride = 1;
+        io.out_stride = B->m + 1;
+        io.sub_stride = 1;
+        io.kappa = B->ss.kappa;
+        KLAUNCH(c, SAPDD_K_DSLASH,
+                launch_dslash_full(B->g, links_of(B->f, P64), tclov_of(B->f, P64), 0.0, io, c->stream));
+        KLAUNCH(c, SAPDD_K_DSLASH, launch_reduce(B->part, B->nwg_d, 1, d_list, io.nact, B->coef + B->noff, B->CST,
+                                                 nullptr, 0, 0, g == 0 ? B->vscale : nullptr, B->m + 1, c->stream));
+    }
     HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
     CHK(fetch_coef(B));
     float ms = 0;
@@ -869,29 +887,125 @@ int batch_sap(sapdd_batch *B, int j, const int *d_cyc, int ncyc) {
     return SAPDD_OK;
 }
 
-// One FGMRES(m) restart cycle over every ready slot.
+// Deflated restart of slot r after a full cycle (flexible GMRES with deflated restarts,
+// Sec. 3.1, in the form of Morgan's GMRES-DR): with Hbar = Hr ((m+1) x m), y the
+// cycle's least-squares solution and s = c0 - Hbar y the residual's coordinates,
+//   harmonic Ritz: (H_m + H_m^-H h^H h) g = theta g  (H_m = first m rows, h = last row);
+//   P_k = the Schur vectors of the k values of smallest modulus (orthonormal, m x k);
+//   P_{k+1} = [[P_k; 0], s orthogonalised against them and normalised];
+//   next cycle: V <- V P_{k+1}, Z <- Z P_k, Hbar <- P_{k+1}^H Hbar P_k, c0 <- P_{k+1}^H s,
+//   first step k. P_{k+1} goes to the slot's block of the pinned staging area (column-major,
+//   leading dimension m+1). Returns false (plain restart) if H_m is singular, the Schur
+//   iteration fails or s vanishes.
+bool deflate_basis(sapdd_batch *B, int r) {
+    Slot &s = B->slots[r];
+    const int m = B->m, k = B->k, M1 = m + 1;
+    if ((int)s.y.size() != m) return false;
+    std::vector<cd> sres(M1);
+    for (int i = 0; i < M1; ++i) {
+        cd t = s.c0[i];
+        for (int q = 0; q < m; ++q) t -= s.Hr[i + (size_t)M1 * q] * s.y[q];
+        sres[i] = t;
+    }
+    std::vector<cd> hmh((size_t)m * m), f(m), a((size_t)m * m), q;
+    for (int i = 0; i < m; ++i) {
+        f[i] = std::conj(s.Hr[m + (size_t)M1 * i]);
+        for (int j = 0; j < m; ++j) {
+            hmh[i + (size_t)m * j] = std::conj(s.Hr[j + (size_t)M1 * i]);
+            a[i + (size_t)m * j] = s.Hr[i + (size_t)M1 * j];
+        }
+    }
+    if (!dense::solve(m, hmh, f)) return false;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) a[i + (size_t)m * j] += f[i] * s.Hr[m + (size_t)M1 * j];
+    if (!dense::schur_sorted(m, a, q)) return false;
+    std::vector<cd> P((size_t)M1 * (k + 1), 0.0);
+    for (int l = 0; l < k; ++l)
+        for (int i = 0; i < m; ++i) P[i + (size_t)M1 * l] = q[i + (size_t)m * l];
+    std::vector<cd> v = sres;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int l = 0; l < k; ++l) {
+            cd d = 0;
+            for (int i = 0; i < M1; ++i) d += std::conj(P[i + (size_t)M1 * l]) * v[i];
+            for (int i = 0; i < M1; ++i) v[i] -= d * P[i + (size_t)M1 * l];
+        }
+    double nv = 0;
+    for (const cd &x : v) nv += std::norm(x);
+    nv = std::sqrt(nv);
+    if (!(nv > 0) || !std::isfinite(nv)) return false;
+    for (int i = 0; i < M1; ++i) P[i + (size_t)M1 * k] = v[i] / nv;
+    // Hbar_new = P^H Hbar P_k, c0_new = P^H s
+    std::vector<cd> hp_((size_t)M1 * k);  // Hbar P_k, (m+1) x k
+    for (int b = 0; b < k; ++b)
+        for (int i = 0; i < M1; ++i) {
+            cd t = 0;
+            for (int qq = 0; qq < m; ++qq) t += s.Hr[i + (size_t)M1 * qq] * P[qq + (size_t)M1 * b];
+            hp_[i + (size_t)M1 * b] = t;
+        }
+    std::vector<cd> hn((size_t)M1 * m, 0.0), cn(M1, 0.0);
+    for (int a2 = 0; a2 <= k; ++a2) {
+        for (int b = 0; b < k; ++b) {
+            cd t = 0;
+            for (int i = 0; i < M1; ++i) t += std::conj(P[i + (size_t)M1 * a2]) * hp_[i + (size_t)M1 * b];
+            hn[a2 + (size_t)M1 * b] = t;
+        }
+        cd t = 0;
+        for (int i = 0; i < M1; ++i) t += std::conj(P[i + (size_t)M1 * a2]) * sres[i];
+        cn[a2] = t;
+    }
+    double *hp = B->hp + (size_t)r * M1 * (k + 1) * 2;
+    for (size_t i = 0; i < P.size(); ++i) {
+        hp[2 * i] = P[i].real();
+        hp[2 * i + 1] = P[i].imag();
+    }
+    s.Hr = hn;
+    s.c0 = cn;
+    s.j0 = k;
+    return true;
+}
+
+// One FGMRES(m) restart cycle over every ready slot. A slot that continues a deflated
+// basis starts at Arnoldi step k; with deflation (k > 0) every full cycle ends with the
+// deflated restart of the next (deflate_basis).
 int batch_cycle(sapdd_batch *B) {
     sapdd_ctx *c = B->c;
     const int m = B->m;
-    std::vector<int> cycle;
+    std::vector<int> running;
     for (int r = 0; r < B->cap; ++r)
-        if (B->slots[r].used && !B->slots[r].finished && B->slots[r].ready) cycle.push_back(r);
-    if (cycle.empty()) return SAPDD_OK;
-    for (int r : cycle) {
+        if (B->slots[r].used && !B->slots[r].finished && B->slots[r].ready) running.push_back(r);
+    if (running.empty()) return SAPDD_OK;
+    int jmin = m;
+    for (int r : running) {
         Slot &s = B->slots[r];
-        std::fill(s.H.begin(), s.H.end(), 0.0);
-        std::fill(s.gv.begin(), s.gv.end(), 0.0);
-        s.gv[0] = s.beta;
         s.in_cycle = true;
         s.nz = 0;
+        if (!s.deflated) {
+            std::fill(s.H.begin(), s.H.end(), 0.0);
+            std::fill(s.gv.begin(), s.gv.end(), 0.0);
+            s.gv[0] = s.beta;
+            s.Hr.assign((size_t)(m + 1) * m, 0.0);
+            s.c0.assign(m + 1, 0.0);
+            s.c0[0] = s.beta;
+            s.j0 = 0;
+        }
+        jmin = std::min(jmin, s.j0);
     }
-    const std::vector<int> members = cycle;
-    int *d_cyc;
-    CHK(upload(B, SEG_CYCLE, cycle, &d_cyc));
-    int ncyc = (int)cycle.size();
+    const std::vector<int> members = running;
+    std::vector<int> cycle;  // the slots of the current step, as uploaded
+    int *d_cyc = nullptr;
+    int ncyc = 0;
     double *Vd = (double *)B->Vb.data;
-    const int nwg = blas_partials(B->ncx, ncyc);
-    for (int j = 0; j < m && ncyc > 0; ++j) {
+    const int nwg = blas_partials(B->ncx, 1);
+    for (int j = jmin; j < m && !running.empty(); ++j) {
+        std::vector<int> act;
+        for (int r : running)
+            if (B->slots[r].j0 <= j) act.push_back(r);
+        if (act.empty()) continue;
+        if (act != cycle) {
+            cycle = act;
+            ncyc = (int)cycle.size();
+            CHK(upload(B, SEG_CYCLE, cycle, &d_cyc));
+        }
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         CHK(batch_sap(B, j, d_cyc, ncyc));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
@@ -948,15 +1062,37 @@ int batch_cycle(sapdd_batch *B) {
             B->t_gs += ms * 1e-3;
         }
         // host: Hessenberg column, Givens rotations, least-squares residual estimate
-        std::vector<int> still;
+        std::vector<int> stopped;
         for (int r : cycle) {
             Slot &s = B->slots[r];
             const double *hc = B->hcoef + (size_t)r * B->CST;
-            cd *col = &s.H[(size_t)(m + 1) * j];
+            cd *hr = &s.Hr[(size_t)(m + 1) * j];
             for (int i = 0; i <= j; ++i)
-                col[i] = cd(hc[B->hoff + 2 * i] + hc[B->coff + 2 * i], hc[B->hoff + 2 * i + 1] + hc[B->coff + 2 * i + 1]);
+                hr[i] = cd(hc[B->hoff + 2 * i] + hc[B->coff + 2 * i], hc[B->hoff + 2 * i + 1] + hc[B->coff + 2 * i + 1]);
             const double hn = std::sqrt(std::max(0.0, hc[B->noff]));
-            col[j + 1] = hn;
+            hr[j + 1] = hn;
+            if (s.deflated) {  // dense leading block: least squares from scratch
+                std::vector<cd> hsub((size_t)(j + 2) * (j + 1));
+                for (int q = 0; q <= j; ++q)
+                    for (int i = 0; i < j + 2; ++i) hsub[i + (size_t)(j + 2) * q] = s.Hr[i + (size_t)(m + 1) * q];
+                const double res = dense::lstsq(j + 2, j + 1, hsub, std::vector<cd>(s.c0.begin(), s.c0.begin() + j + 2),
+                                                s.y);
+                s.est = res / s.bnorm;
+                s.iters += 1;
+                s.nz = j + 1;
+                if (!std::isfinite(s.est)) {
+                    s.status = SAPDD_ENAN;
+                    s.in_cycle = false;
+                    s.nz = 0;
+                    stopped.push_back(r);
+                } else if (s.est <= B->p.tol || hn == 0.0 || s.iters >= B->p.max_iter) {
+                    s.in_cycle = false;
+                    stopped.push_back(r);
+                }
+                continue;
+            }
+            cd *col = &s.H[(size_t)(m + 1) * j];
+            for (int i = 0; i <= j + 1; ++i) col[i] = hr[i];
             for (int i = 0; i < j; ++i) {
                 const cd t = std::conj(s.cs[i]) * col[i] + std::conj(s.sn[i]) * col[i + 1];
                 col[i + 1] = -s.sn[i] * col[i] + s.cs[i] * col[i + 1];
@@ -981,19 +1117,21 @@ int batch_cycle(sapdd_batch *B) {
                 if (!std::isfinite(s.est)) s.status = SAPDD_ENAN;
                 s.in_cycle = false;
                 if (!std::isfinite(s.est)) s.nz = 0;
+                stopped.push_back(r);
                 continue;
             }
             if (s.est <= B->p.tol || hn == 0.0 || s.iters >= B->p.max_iter) {
                 s.in_cycle = false;
+                stopped.push_back(r);
                 continue;
             }
-            still.push_back(r);
         }
         B->t_host += now_s() - th;
-        if (still.size() != (size_t)ncyc) {
-            cycle = still;
-            ncyc = (int)cycle.size();
-            if (ncyc) CHK(upload(B, SEG_CYCLE, cycle, &d_cyc));
+        if (!stopped.empty()) {
+            std::vector<int> keep;
+            for (int r : running)
+                if (std::find(stopped.begin(), stopped.end(), r) == stopped.end()) keep.push_back(r);
+            running = keep;
         }
     }
     // x += Z y, one launch per basis size
@@ -1004,13 +1142,16 @@ int batch_cycle(sapdd_batch *B) {
         const int nz = kv.first;
         for (int r : kv.second) {
             Slot &s = B->slots[r];
-            std::vector<cd> y(nz);
-            for (int i = nz - 1; i >= 0; --i) {  // back substitution R y = g
-                cd t = s.gv[i];
-                for (int k = i + 1; k < nz; ++k) t -= s.H[(size_t)(m + 1) * k + i] * y[k];
-                const cd d = s.H[(size_t)(m + 1) * i + i];
-                y[i] = d != 0.0 ? t / d : 0.0;
+            if (!s.deflated) {
+                s.y.assign(nz, 0.0);
+                for (int i = nz - 1; i >= 0; --i) {  // back substitution R y = g
+                    cd t = s.gv[i];
+                    for (int k = i + 1; k < nz; ++k) t -= s.H[(size_t)(m + 1) * k + i] * s.y[k];
+                    const cd d = s.H[(size_t)(m + 1) * i + i];
+                    s.y[i] = d != 0.0 ? t / d : 0.0;
+                }
             }
+            const std::vector<cd> &y = s.y;
             for (int i = 0; i < nz; ++i) {
                 B->hy[(size_t)r * 2 * m + 2 * i] = y[i].real();
                 B->hy[(size_t)r * 2 * m + 2 * i + 1] = y[i].imag();
@@ -1029,6 +1170,29 @@ int batch_cycle(sapdd_batch *B) {
         KLAUNCH(c, SAPDD_K_UPDATE, launch_zupdate((double *)B->Xb.data, B->NS, B->Zb.data, B->zprec, B->NS,
                                                   (int64_t)m * B->NS, B->ydev, 2 * m, kv.first, d_grp,
                                                   (int)kv.second.size(), B->ncx, B->g.Vbh, c->stream));
+    }
+    // deflated restarts: the next cycle of every slot that ran all m steps continues from
+    // the recombined basis; the others restart plainly from their true residual
+    if (B->k > 0) {
+        std::vector<int> dr;
+        for (int r : members) {
+            Slot &s = B->slots[r];
+            const bool full = s.nz == m && s.status == SAPDD_OK;
+            s.deflated = full && deflate_basis(B, r);
+            if (s.deflated) dr.push_back(r);
+        }
+        if (!dr.empty()) {
+            const int M1 = m + 1;
+            const int64_t pstride = (int64_t)M1 * (B->k + 1) * 2;
+            HIPCHK(c, hipMemcpyAsync(B->pdev, B->hp, (size_t)B->cap * pstride * 8, hipMemcpyHostToDevice, c->stream));
+            int *d_dr;
+            CHK(upload(B, SEG_DEFL, dr, &d_dr));
+            KLAUNCH(c, SAPDD_K_GS, launch_recombine(Vd, (int64_t)M1 * B->NS, B->NS, B->vscale, M1, B->pdev, pstride, M1,
+                                                    M1, B->k + 1, d_dr, (int)dr.size(), B->ncx, c->stream));
+            KLAUNCH(c, SAPDD_K_GS, launch_recombine((double *)B->Zb.data, (int64_t)m * B->NS, B->NS, nullptr, 0,
+                                                    B->pdev, pstride, M1, m, B->k, d_dr, (int)dr.size(), B->ncx,
+                                                    c->stream));
+        }
     }
     std::vector<int> check;
     for (int r : members) {
@@ -1071,6 +1235,8 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     CHK(check_params(c, f, p));
     // the fused correct-and-dot Gram-Schmidt pass holds all basis vectors of a step at once
     if (p->restart < 1 || p->restart > 16) return fail(c, SAPDD_EINVAL, "restart must be in 1..16");
+    if (p->deflate < 0 || p->deflate >= p->restart)
+        return fail(c, SAPDD_EINVAL, "deflate must be in 0..restart-1");
     if (!(p->tol > 0) || p->max_iter < 1) return fail(c, SAPDD_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (cap < 1) return fail(c, SAPDD_EINVAL, "a batch needs at least one slot");
     sapdd_batch *B = new sapdd_batch;
@@ -1080,7 +1246,9 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     B->cap = cap;
     B->m = p->restart;
     B->prec = p->sap_prec;
-    B->zprec = B->prec == P64 ? P64 : P32;
+    B->k = p->deflate;
+    // deflated restarts recombine Z: FP64 keeps M Z = V Hbar exact through the recombination
+    B->zprec = B->prec == P64 || B->k > 0 ? P64 : P32;
     B->g = f->geo;
     B->NS = B->g.V * 24;
     B->ncx = B->g.V * 12;
@@ -1124,8 +1292,11 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
         B->ydev = (double *)q;
         if ((r = balloc(B, (size_t)NSEG * cap * sizeof(int), &q)) != SAPDD_OK) break;
         B->dlists = (int *)q;
-        const size_t pin_bytes =
-            (size_t)NSEG * cap * sizeof(int) + (size_t)cap * B->CST * 8 + (size_t)cap * 2 * B->m * 8 + meta_bytes;
+        const size_t pbytes = (size_t)cap * (B->m + 1) * (B->k + 1) * 16;
+        if ((r = balloc(B, pbytes, &q)) != SAPDD_OK) break;
+        B->pdev = (double *)q;
+        const size_t pin_bytes = (size_t)NSEG * cap * sizeof(int) + (size_t)cap * B->CST * 8 +
+                                 (size_t)cap * 2 * B->m * 8 + meta_bytes + pbytes;
         if (hipHostMalloc((void **)&B->pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             r = fail(c, SAPDD_ENOMEM, "pinned staging allocation failed");
@@ -1135,6 +1306,7 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
         B->hcoef = (double *)(B->pin + (size_t)NSEG * cap * sizeof(int));
         B->hy = B->hcoef + (size_t)cap * B->CST;
         B->hmeta = (char *)(B->hy + (size_t)cap * 2 * B->m);
+        B->hp = (double *)(B->hmeta + meta_bytes);
         memset(B->hy, 0, (size_t)cap * 2 * B->m * 8);
     } while (false);
     if (r != SAPDD_OK) {

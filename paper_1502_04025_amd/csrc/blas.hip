@@ -173,6 +173,72 @@ hipError_t launch_reduce(const double *part, int nwg, int nval, const int *activ
     return hipGetLastError();
 }
 
+// In place, for every listed slot: v_l <- sum_{i < NIN} s_i v_i P_il for l < nout (FP64
+// complex vectors of n entries), with s_i = vscale[rhs * vsstride + i] (1 without
+// vscale) and P column-major with leading dimension ld at P + rhs * pstride (complex).
+// Each thread holds all NIN entries of its element before writing any, so outputs may
+// overwrite inputs.
+template <int NIN>
+__global__ __launch_bounds__(BLAS_WG) void recombine_kernel(double *base, int64_t rstride, int64_t vstride,
+                                                            const double *vscale, int vsstride, const double *P,
+                                                            int64_t pstride, int ld, int nout, const int *active,
+                                                            int64_t n) {
+    const int rhs = active[blockIdx.y];
+    double2 *b = (double2 *)(base + rhs * rstride);
+    const int64_t vs = vstride / 2;
+    const double *pm = P + rhs * pstride;
+    double sc[NIN];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) sc[i] = vscale ? vscale[(int64_t)rhs * vsstride + i] : 1.0;
+    const int64_t stride = (int64_t)gridDim.x * BLAS_WG;
+    for (int64_t e = (int64_t)blockIdx.x * BLAS_WG + threadIdx.x; e < n; e += stride) {
+        double2 v[NIN];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            v[i] = b[i * vs + e];
+            v[i].x *= sc[i];
+            v[i].y *= sc[i];
+        }
+        for (int l = 0; l < nout; ++l) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+                const double pr = pm[2 * (i + ld * l)], pi = pm[2 * (i + ld * l) + 1];
+                re = __builtin_fma(v[i].x, pr, __builtin_fma(-v[i].y, pi, re));
+                im = __builtin_fma(v[i].x, pi, __builtin_fma(v[i].y, pr, im));
+            }
+            b[l * vs + e] = make_double2(re, im);
+        }
+    }
+}
+
+__global__ void set_scales_kernel(double *vscale, int vsstride, int count, const int *active) {
+    const int rhs = active[blockIdx.x];
+    if ((int)threadIdx.x < count) vscale[(int64_t)rhs * vsstride + threadIdx.x] = 1.0;
+}
+
+hipError_t launch_recombine(double *base, int64_t rstride, int64_t vstride, const double *vscale, int vsstride,
+                            const double *P, int64_t pstride, int ld, int nin, int nout, const int *active, int nact,
+                            int64_t n, hipStream_t st) {
+    if (nact <= 0 || nout <= 0) return hipSuccess;
+    if (nout > nin) return hipErrorInvalidValue;
+    const dim3 grid(blas_partials(n, nact), nact);
+    switch (nin) {
+#define C(N)                                                                                                     \
+    case N:                                                                                                      \
+        hipLaunchKernelGGL(recombine_kernel<N>, grid, dim3(BLAS_WG), 0, st, base, rstride, vstride, vscale,      \
+                           vsstride, P, pstride, ld, nout, active, n);                                            \
+        break;
+        C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14) C(15) C(16) C(17)
+#undef C
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !vscale) return e;
+    hipLaunchKernelGGL(set_scales_kernel, dim3(nact), dim3(64), 0, st, (double *)vscale, vsstride, nout, active);
+    return hipGetLastError();
+}
+
 // x += sum_j y_j z_j. FP64 z shares x's element order; an FP32 z holds the complex
 // components 2v and 2v + 1 of site (bp, s) in its float4 number (bp * 6 + v) * Vbh + s,
 // which map to the double2 numbers (bp * 12 + 2v) * Vbh + s and the one Vbh later.

@@ -114,6 +114,14 @@ hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st);
 hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
                          int ostride, const double *mul, int mstride, int v0, double *isq, int istride,
                          hipStream_t st);
+// In place v_l <- sum_{i < nin} s_i v_i P_il (l < nout <= nin) for the FP64 vectors of
+// every listed slot (n complex entries; slot rhs at base + rhs * rstride, vector i at
+// + i * vstride doubles); s_i = vscale[rhs * vsstride + i] (1 if vscale is null), which
+// is then set to 1 for i < nout. P: column-major, leading dimension ld, complex, at
+// P + rhs * pstride doubles. nin <= 17.
+hipError_t launch_recombine(double *base, int64_t rstride, int64_t vstride, const double *vscale, int vsstride,
+                            const double *P, int64_t pstride, int ld, int nin, int nout, const int *active, int nact,
+                            int64_t n, hipStream_t st);
 // x[rhs] += sum_j y[rhs][j] z_j[rhs]: y complex at y + rhs * ystride, z in P32 or P64 at
 // z + (rhs * zstride_rhs + j * zstride_j) elements.
 hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, int64_t zstride_j,

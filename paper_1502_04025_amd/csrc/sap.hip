@@ -356,6 +356,9 @@ static hipError_t sap_shape(const Geom &geo, const SapArgsHost &h, int colour, i
     if (sp == P64 && h.psi_prec == P64) return sap_typed<BK, double, double, double>(geo, h, colour, mode, ws, st);
     if (sp == P32 && h.psi_prec == P32) return sap_typed<BK, float, float, float>(geo, h, colour, mode, ws, st);
     if (sp == P16 && h.psi_prec == P32) return sap_typed<BK, half_t, float, float>(geo, h, colour, mode, ws, st);
+    // FP64 output: the preconditioned vectors of deflated restarts
+    if (sp == P32 && h.psi_prec == P64) return sap_typed<BK, float, float, double>(geo, h, colour, mode, ws, st);
+    if (sp == P16 && h.psi_prec == P64) return sap_typed<BK, half_t, float, double>(geo, h, colour, mode, ws, st);
     return hipErrorInvalidValue;
 }
 

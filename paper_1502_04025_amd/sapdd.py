@@ -44,7 +44,8 @@ class SapddError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("nmr", C.c_int), ("ncy", C.c_int), ("restart", C.c_int),
-                ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int)]
+                ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int),
+                ("deflate", C.c_int)]
 
 
 class KernelProfile(C.Structure):
@@ -247,13 +248,15 @@ class Field:
     def apply_block_D(self, kappa, psi, prec="f64", out=None):
         return self._apply(self.ctx.lib.sapdd_apply_block_D, kappa, psi, prec, out)
 
-    def params(self, nmr=4, ncy=5, restart=16, max_iter=1000, tol=1e-10, prec="f64", flags=0) -> Params:
+    def params(self, nmr=4, ncy=5, restart=16, max_iter=1000, tol=1e-10, prec="f64", flags=0,
+               deflate=0) -> Params:
         p = Params()
         for i in range(4):
             p.block[i] = self.block[i]
         p.nmr, p.ncy, p.restart, p.max_iter, p.tol = nmr, ncy, restart, max_iter, tol
         p.sap_prec = PRECS[prec] if isinstance(prec, str) else int(prec)
         p.flags = flags
+        p.deflate = deflate
         return p
 
     def sap(self, kappa, psi, out=None, **kw):

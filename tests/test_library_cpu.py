@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -29,10 +30,25 @@ def test_library_loads_and_exports_every_header_symbol():
     sapdd.load_library()
 
 
-def test_params_struct_matches_header_layout():
-    # int block[4], 4 ints, a double, 2 ints -> 48 bytes with natural alignment
-    assert ctypes.sizeof(sapdd.Params) == 48
-    assert ctypes.sizeof(sapdd.Stats) == 3 * 4 + 4 + 7 * 8
+def test_params_struct_matches_header_layout(tmp_path):
+    """The ctypes mirrors have the size and field offsets the C compiler gives the header's
+    structs."""
+    fields_p = [f for f, _ in sapdd.Params._fields_]
+    fields_s = [f for f, _ in sapdd.Stats._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"sapdd.h\"\nint main(void) {\n"
+                   + f'  printf("%zu %zu\\n", sizeof(sapdd_params), sizeof(sapdd_stats));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(sapdd_params, {f}));\n' for f in fields_p)
+                   + "".join(f'  printf("%zu\\n", offsetof(sapdd_stats, {f}));\n' for f in fields_s)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(sapdd.Params)
+    assert int(out[1]) == ctypes.sizeof(sapdd.Stats)
+    offs = [int(v) for v in out[2:]]
+    assert offs[:len(fields_p)] == [getattr(sapdd.Params, f).offset for f in fields_p]
+    assert offs[len(fields_p):] == [getattr(sapdd.Stats, f).offset for f in fields_s]
 
 
 def test_product_path_does_not_import_the_oracle():
