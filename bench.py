@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--nmr", type=int, default=4, help="MR iterations per block solve")
     ap.add_argument("--ncy", type=int, default=None,
                     help="Schwarz cycles per preconditioner application (default: the workload's)")
+    ap.add_argument("--restart", type=int, default=None, help="FGMRES restart length (default: the workload's)")
+    ap.add_argument("--deflate", type=int, default=0, help="deflated restarts: harmonic Ritz vectors kept")
     ap.add_argument("--sweep", action="store_true", help="time-to-solution sweep over nmr x ncy x domain shape")
     ap.add_argument("--sweep-nmr", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8])
     ap.add_argument("--sweep-ncy", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8, 12, 16])
@@ -328,7 +330,9 @@ def main():
     name, prec, over = WORKLOADS[args.workload]
     cfg = dict(synthetic.CONFIGS[name])
     cfg.update(over)
-    nmr, restart, tol = args.nmr, cfg.get("restart", 16), 1e-10
+    nmr, tol = args.nmr, 1e-10
+    restart = args.restart if args.restart is not None else cfg.get("restart", 16)
+    deflate = args.deflate
     ncy = args.ncy if args.ncy is not None else cfg.get("ncy", 5)
     torch.cuda.init()
     stream = torch.cuda.Stream()  # a real stream: the SAP sweep replays from HIP graphs
@@ -345,7 +349,8 @@ def main():
     cfg["nrhs_active"] = nrhs
 
     def step():
-        return field.solve(cfg["kappa"], b, x=x, nmr=nmr, ncy=ncy, restart=restart, tol=tol, prec=prec)
+        return field.solve(cfg["kappa"], b, x=x, nmr=nmr, ncy=ncy, restart=restart, deflate=deflate, tol=tol,
+                           prec=prec)
 
     for _ in range(args.warmup):
         r = step()
@@ -402,7 +407,7 @@ def main():
         "config": {"workload": f"{name}: {'x'.join(map(str, cfg['dims']))} lattice, {'x'.join(map(str, cfg['block']))} "
                                f"domains, kappa {cfg['kappa']}, c_sw {cfg['csw']}, links exp(i {cfg['eps']} H), "
                                f"{nrhs} {cfg['source']} RHS, SAP {prec} storage (nmr {nmr}, ncy {ncy}), "
-                               f"FP64 FGMRES({restart}) to {tol}",
+                               f"FP64 FGMRES({restart}){f' with {deflate} deflated vectors' if deflate else ''} to {tol}",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(1e3 * percentile(lat, 50), 3), "p99": round(1e3 * percentile(lat, 99), 3)},
         "solve": {"outer_iters": iters, "true_relres": relres, "oracle_relres_rhs0": oracle_relres,
