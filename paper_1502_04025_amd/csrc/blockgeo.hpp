@@ -275,7 +275,9 @@ template <class BK, class R, int WANT = 2> struct HopLds {
     __device__ __forceinline__ R *hb() const { return base + cur * PER + 24 * BK::Vbh; }
 };
 
-template <class BK, class R, class LK, int WANT>
+// TAIL = false (one LDS buffer only): the caller guarantees a barrier between the
+// receivers' reads and the next hop's writes, and the trailing barrier is left out.
+template <class BK, bool TAIL = true, class R, class LK, int WANT>
 __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK &U, const R (&in)[24], R (&out)[24],
                                           HopLds<BK, R, WANT> &lds) {
     constexpr int Vbh = BK::Vbh;
@@ -300,7 +302,7 @@ __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK 
     }
     if constexpr (HopLds<BK, R, WANT>::NBUF == 2) {
         lds.cur ^= 1;
-    } else {
+    } else if constexpr (TAIL) {
         __syncthreads();  // one buffer: the next hop may only overwrite it after every read
     }
 }

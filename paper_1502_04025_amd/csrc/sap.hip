@@ -255,7 +255,9 @@ void sap_half_kernel(SapArgs<S, P> a) {
         block_hop<BK>(0, si, U, A, H, lds);  // odd: H = H_oe r
         if (EARLY_AE && even) mul_even(A, T);  // even: T = A_e r (needs only r)
         if (!even) Xc.mul(H, T, (R)1);           // odd: T = A_o^-1 H_oe r
-        block_hop<BK>(1, si, U, T, H, lds);  // even: H = H_eo T
+        // even: H = H_eo T; the reduction's barrier below separates these reads from the
+        // next hop's writes, so a single-buffer hop needs no barrier of its own at the end
+        block_hop<BK, false>(1, si, U, T, H, lds);
         R pr_re = 0, pr_im = 0, pp = 0;
         if (even) {
             if (!EARLY_AE) mul_even(A, T);  // even: T = p = A_e r - kappa^2 H
