@@ -109,21 +109,25 @@ def roofline_sap(prof, cfg, prec, nmr):
                                f"{prec}") if cfg["nrhs_active"] == 1 else None
     t_alu = flops / (alu_peak * 1e12)
     t_hbm = byts / (pm.HBM_PEAK_GBS * 1e9)
+    tflops, gbs = flops / avg / 1e12, byts / avg / 1e9
+    # both roofs, and whether one SAP cycle's data (both colours) fits the 256 MB
+    # Infinity Cache, in which case the HBM figure is a cache-resident one
+    both = dict(alu_TFLOP_s=round(tflops, 3), alu_frac=round(tflops / alu_peak, 4), hbm_GB_s=round(gbs, 1),
+                hbm_frac=round(gbs / pm.HBM_PEAK_GBS, 4), working_set_bytes=2 * byts,
+                cache_resident=bool(2 * byts < 256e6))
+    common = dict(traffic=traffic, avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
+                  algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts, **both)
     if t_alu >= t_hbm:
-        ach = flops / avg / 1e12
-        return dict(kernel="sap_half_kernel", bound="alu", achieved=round(ach, 3), peak=alu_peak,
-                    unit="TFLOP/s", frac=round(ach / alu_peak, 4), traffic=traffic,
-                    avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
-                    algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts)
-    ach = byts / avg / 1e9
-    return dict(kernel="sap_half_kernel", bound="hbm", achieved=round(ach, 1), peak=pm.HBM_PEAK_GBS,
-                unit="GB/s", frac=round(ach / pm.HBM_PEAK_GBS, 4), traffic=traffic,
-                avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
-                algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts)
+        return dict(kernel="sap_half_kernel", bound="alu", achieved=round(tflops, 3), peak=alu_peak,
+                    unit="TFLOP/s", frac=round(tflops / alu_peak, 4), **common)
+    return dict(kernel="sap_half_kernel", bound="hbm", achieved=round(gbs, 1), peak=pm.HBM_PEAK_GBS,
+                unit="GB/s", frac=round(gbs / pm.HBM_PEAK_GBS, 4), **common)
 
 
-def dslash_bandwidth(ctx, reps=20):
-    """Block Dslash on 32^3 x 64 (4^4 domains), FP16 and FP32 storage, device arrays."""
+def dslash_bandwidth(ctx, warm=10, reps=100):
+    """Block Dslash on 32^3 x 64 (4^4 domains), FP16 and FP32 storage, device arrays:
+    `warm` untimed launches, then `reps` launches each timed by its own HIP-event pair;
+    GB/s at the median launch time, with p10/p90."""
     import torch
 
     import synthetic
@@ -136,16 +140,19 @@ def dslash_bandwidth(ctx, reps=20):
     V = int(np.prod(cfg["dims"]))
     res = {}
     for prec in ("f16", "f32"):
-        f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out)  # warm (builds the low-precision copies)
-        ctx.profile(True)
-        for _ in range(reps):
+        for _ in range(warm):  # the first one builds the low-precision copies
             f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out)
-        p = ctx.profile(False)["block_dslash"]
-        avg = p["seconds"] / p["launches"]
+        ts = []
+        for _ in range(reps):
+            ctx.profile(True, families=["block_dslash"])
+            f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out)
+            ts.append(ctx.profile(False)["block_dslash"]["seconds"])
+        med, p10, p90 = (float(np.percentile(ts, q)) for q in (50, 10, 90))
         byts = pm.block_dslash_bytes(cfg["block"], prec) * V
-        gbs = byts / avg / 1e9
-        res[prec] = dict(GB_s=round(gbs, 1), frac=round(gbs / pm.HBM_PEAK_GBS, 4), avg_launch_us=round(avg * 1e6, 2),
-                         algorithmic_bytes_per_launch=byts,
+        gbs = byts / med / 1e9
+        res[prec] = dict(GB_s=round(gbs, 1), frac=round(gbs / pm.HBM_PEAK_GBS, 4),
+                         median_launch_us=round(med * 1e6, 2), p10_us=round(p10 * 1e6, 2),
+                         p90_us=round(p90 * 1e6, 2), launches=reps, algorithmic_bytes_per_launch=byts,
                          traffic=profiled_traffic(f"dslash_block_kernel 32x32x32x64 4x4x4x4 {prec}"))
     f.free()
     return dict(kernel="dslash_block_kernel", lattice="32x32x32x64", block=list(cfg["block"]), **res)
@@ -186,7 +193,9 @@ def cpu_baseline(cfg, iters, restarts, nmr, ncy):
         t_half = (time.perf_counter() - t0) / 2
     del m
     t_solve = iters * (2 * ncy * t_half + t_m) + (restarts + 1) * t_m
+    model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), None)
     return dict(value=round(1.0 / t_solve, 6), unit="solves/s", cores=1, kind="oracle",
+                host_cores=len(os.sched_getaffinity(0)), cpu_model=model,
                 sample=f"two Schwarz half-sweeps (even-odd MR block solves, nmr {nmr}, plus the residual "
                        f"update) and one operator application on the full {'x'.join(map(str, cfg['dims']))} "
                        f"lattice, NumPy FP64 on one core ({t_half:.1f} s per half-sweep, {t_m:.2f} s per "
@@ -205,7 +214,9 @@ def run_serving(args):
     kw = dict(prec="f16", nmr=4, ncy=NCY, restart=16, tol=1e-10)
     vols = [sv.TorchVolume(f"{'x'.join(map(str, d))}", d, (4, 4, 4, 4), 0.3, 14 + i, 1.0, 0, kw)
             for i, d in enumerate(synthetic.SERVING_VOLUMES)]
-    plans = sv.plan_capacity([v.plan() for v in vols], int(args.hbm_budget_gb * 1e9), max_slots=16)
+    # 16 GB of the budget stay free for kernel scratch, graphs and the caching allocator
+    plans = sv.plan_capacity([v.plan() for v in vols], int(args.hbm_budget_gb * 1e9), max_slots=16,
+                             reserve_bytes=16 * 10 ** 9)
     for v, p in zip(vols, plans):
         v.start(p.capacity)
 
@@ -218,6 +229,9 @@ def run_serving(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out = sv.summarize(done, wall)
+        for r in done:  # release the results (the responses) before the next phase
+            r.x = None
+        torch.cuda.empty_cache()
         out["steps"] = [w.steps for w in workers]
         out["converged"] = all(all(st["converged"] for st in r.stats) for r in done if r.error is None)
         return out
@@ -300,7 +314,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per arrival rate")
-    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: HBM budget for admission")
+    ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="serve: HBM budget for admission")
     ap.add_argument("--nmr", type=int, default=4, help="MR iterations per block solve")
     ap.add_argument("--ncy", type=int, default=None,
                     help="Schwarz cycles per preconditioner application (default: the workload's)")
@@ -421,6 +435,9 @@ def main():
         except Exception as e:  # report, do not hide the main number
             line["dslash"] = {"error": str(e)}
         line["copy_GB_s"] = copy_bandwidth(ctx)
+        for prec in ("f16", "f32"):  # also as a fraction of the measured copy bandwidth
+            if isinstance(line["dslash"].get(prec), dict):
+                line["dslash"][prec]["frac_of_copy"] = round(line["dslash"][prec]["GB_s"] / line["copy_GB_s"], 4)
         if prec != "f64":
             t0 = time.perf_counter()
             n64 = 3

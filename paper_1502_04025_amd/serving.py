@@ -54,14 +54,15 @@ class VolumePlan:
     capacity: int = 0
 
 
-def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: int = 16):
+def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: int = 16, reserve_bytes: int = 0):
     """Split an HBM budget into batch capacities (slots) per volume.
 
-    The fields and a cache of `kappa_cache` clover inverses per volume are reserved
-    first; the rest buys the same number of slots in every volume (a slot of a large
-    volume costs more bytes), at most max_slots. Raises if not even one slot fits.
+    `reserve_bytes` (kernel scratch, graphs, allocator slack), the fields and a cache of
+    `kappa_cache` clover inverses per volume are reserved first; the rest buys the same
+    number of slots in every volume (a slot of a large volume costs more bytes), at most
+    max_slots. Raises if not even one slot fits.
     """
-    fixed = sum(p.field_bytes + kappa_cache * p.kappa_bytes for p in plans)
+    fixed = reserve_bytes + sum(p.field_bytes + kappa_cache * p.kappa_bytes for p in plans)
     if fixed >= budget_bytes:
         raise MemoryError(f"budget {budget_bytes} B cannot hold the resident fields ({fixed} B)")
     cap = int(min(max_slots, (budget_bytes - fixed) // sum(p.per_rhs_bytes for p in plans)))
@@ -255,10 +256,12 @@ class TorchVolume:
             self.start(capacity)
 
     def plan(self) -> VolumePlan:
-        """Memory plan of this volume: resident field, bytes per slot, per-kappa clover."""
+        """Memory plan of this volume: resident field, bytes per slot (the solver's state plus
+        this backend's canonical b and x of one right-hand side), per-kappa clover."""
         lx, ly, lz, lt = self.dims
         v = lx * ly * lz * lt
         per_rhs = self.field.footprint(2, **self.solver_kw) - self.field.footprint(1, **self.solver_kw)
+        per_rhs += 2 * v * 12 * 16  # complex128 b and x
         lo = self.field.footprint(1, **self.solver_kw) - per_rhs
         prec_b = {"f64": 8, "f32": 4, "f16": 2}[self.solver_kw.get("prec", "f64")]
         return VolumePlan(self.name, 2 * v * 72 * 8 + lo, per_rhs, v * 72 * prec_b + v * 4)

@@ -58,6 +58,8 @@ def test_plan_capacity_and_budget_errors():
     plans = [sv.VolumePlan("a", 100, 10, 1), sv.VolumePlan("b", 300, 40, 2)]
     sv.plan_capacity(plans, 400 + 16 * 3 + 5 * 50, max_slots=24)
     assert [p.capacity for p in plans] == [5, 5]
+    sv.plan_capacity(plans, 400 + 16 * 3 + 5 * 50, max_slots=24, reserve_bytes=50)
+    assert [p.capacity for p in plans] == [4, 4]  # the reserve buys one slot per volume less
     sv.plan_capacity(plans, 10 ** 9, max_slots=24)
     assert plans[0].capacity == 24
     with pytest.raises(MemoryError):
