@@ -166,7 +166,8 @@ int sapdd_batch_step(sapdd_batch *batch, int *running);
  * fills stats when not NULL. */
 int sapdd_batch_poll(const sapdd_batch *batch, int slot, sapdd_stats *stats);
 /* Copy the slot's solution to x (canonical; flags: SAPDD_DEVICE_PTRS), fill stats and
- * free the slot. */
+ * free the slot. Taking an unfinished slot cancels it: x is then the iterate of its last
+ * completed restart cycle, a resume point to pass back later as x0 (SAPDD_USE_X0). */
 int sapdd_batch_take(sapdd_batch *batch, int slot, double *x, int flags, sapdd_stats *stats);
 
 /* Bytes of device memory a solve of nrhs RHS with these parameters allocates on top of

@@ -115,6 +115,7 @@ class VolumeWorker(threading.Thread):
         self.cv = threading.Condition()
         self.stop_when_idle = False
         self.active = []
+        self.cancels = set()
         self.error = None
         self.steps = 0
 
@@ -127,6 +128,40 @@ class VolumeWorker(threading.Thread):
                 return
             self.queue.append(req)
             self.cv.notify()
+
+    def cancel(self, req_id) -> bool:
+        """Cancel a request. A waiting one leaves the queue at once; an admitted one gives
+        its slots back before the next batch step, its outputs holding the iterate of the
+        last completed restart cycle (a resume point: resubmit it as the start vector).
+        Returns False if the request is not waiting (admitted, finished or unknown)."""
+        with self.cv:
+            for q in list(self.queue):
+                if q.id == req_id:
+                    self.queue.remove(q)
+                    q.error = "cancelled"
+                    q.t_done = self.clock()
+                    self.on_done(q)
+                    return True
+            self.cancels.add(req_id)
+            self.cv.notify()
+        return False
+
+    def _cancel_active(self):
+        with self.cv:
+            ids, self.cancels = self.cancels, set()
+        if not ids:
+            return
+        still = []
+        for req in self.active:
+            if req.id not in ids:
+                still.append(req)
+                continue
+            req.stats = [self.batch.take(s, out) for s, out in zip(req.slots, req.x)]
+            self.adm.give_back(req.nrhs)
+            req.error = "cancelled"
+            req.t_done = self.clock()
+            self.on_done(req)
+        self.active = still
 
     def finish(self):
         with self.cv:
@@ -167,6 +202,7 @@ class VolumeWorker(threading.Thread):
 
     def _loop(self):
         while True:
+            self._cancel_active()
             self._admit()
             if self.active:
                 self.batch.step()

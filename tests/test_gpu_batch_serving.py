@@ -105,3 +105,29 @@ def test_serving_loop_results_equal_alone(env):
     assert s["requests"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0
     for v in vols:
         v.close()
+
+
+def test_cancel_and_resume_from_the_taken_iterate(env):
+    """Taking an unfinished slot returns the iterate of its last restart cycle; adding it
+    back as the start vector finishes the solve (checkpoint and resume)."""
+    from paper_1502_04025_amd import Batch
+    torch, f = env["torch"], env["f"]
+    b = synthetic.gaussian_source(env["dims"], 1, 34)[0]
+    with torch.cuda.stream(env["stream"]):
+        batch = Batch(f, 1, prec="f32", restart=2)
+        s = batch.add(0.124, b)
+        batch.step()
+        finished, st = batch.poll(s)
+        assert not finished and st["iters"] == 2
+        x1 = np.empty_like(b)
+        batch.take(s, x1)  # cancels the slot
+        r1 = oracle_relres(env["u"], env["t"], 0.124, x1, b)
+        assert 1e-10 < r1 < 1.0  # a partial solution
+        s = batch.add(0.124, b, x0=x1)  # resume
+        while batch.step():
+            pass
+        x2 = np.empty_like(b)
+        st2 = batch.take(s, x2)
+        batch.close()
+    assert st2["converged"]
+    assert oracle_relres(env["u"], env["t"], 0.124, x2, b) <= 1e-10

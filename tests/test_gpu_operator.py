@@ -121,3 +121,23 @@ def test_operator_deterministic(ctx):
     a = f.apply_D(0.12, psi, prec="f32")
     b = f.apply_D(0.12, psi, prec="f32")
     assert np.array_equal(a, b)
+
+
+def test_layout_round_trip_all_precisions(ctx):
+    """canonical -> device layout -> canonical through M = 1 (kappa = 0): FP64 exact, FP32
+    exactly the float32 rounding of every real, FP16 within 2^-11 of each site's max |value|
+    (one scale per site, nearest-even halves)."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f = setup_case(ctx, dims, block)
+    psi = synthetic.gaussian_source(dims, 2, 13)
+    psi[0, 1, 2, 3, 4] *= 1e-30  # a site far below the others: its own scale keeps it
+    assert np.array_equal(f.apply_D(0.0, psi, prec="f64"), psi)
+    r32 = f.apply_D(0.0, psi, prec="f32")
+    want = psi.real.astype(np.float32).astype(np.float64) + 1j * psi.imag.astype(np.float32).astype(np.float64)
+    assert np.array_equal(r32, want)
+    r16 = f.apply_D(0.0, psi, prec="f16")
+    re = np.stack([psi.real, psi.imag], axis=-1).reshape(psi.shape[:5] + (24,))
+    err = np.stack([(r16 - psi).real, (r16 - psi).imag], axis=-1).reshape(psi.shape[:5] + (24,))
+    scale = np.abs(re).max(axis=-1, keepdims=True)
+    assert np.all(np.abs(err) <= 2.0 ** -11 * scale)
+    assert np.max(np.abs(err) / scale) > 2.0 ** -14  # the bound is not slack: halves are used

@@ -105,3 +105,27 @@ def test_oversized_request_is_rejected_not_stuck():
     assert len(bad) == 1 and bad[0].id == 0
     s = sv.summarize(done, wall=1.0)
     assert s["requests"] == 1 and s["rejected"] == 1 and s["rhs_solves"] == 2
+
+
+def test_cancel_waiting_and_admitted_requests():
+    """A waiting request leaves the queue; an admitted one gives its slots back between
+    steps and returns its current iterates; the others still complete."""
+    batch = FakeBatch(2)
+    done = []
+    w = sv.VolumeWorker("v", batch, FakeBackend(), sv.Admission(2), lambda: 0.0, done.append)
+    reqs = [sv.Request(i, 0.0, 0, 0.12, n, seed=i) for i, n in enumerate([2, 2, 1])]
+    for r in reqs:
+        w.submit(r)
+    assert w.cancel(2)  # still waiting: removed at once
+    assert done[-1].id == 2 and done[-1].error == "cancelled"
+    w._admit()  # request 0 takes both slots, request 1 waits
+    assert [r.id for r in w.active] == [0] and [q.id for q in w.queue] == [1]
+    w.batch.step()
+    assert not w.cancel(0)  # admitted: cancelled before the next step
+    w._cancel_active()
+    assert done[-1].id == 0 and done[-1].error == "cancelled" and len(done[-1].stats) == 2
+    assert w.adm.free == 2 and not batch.slots
+    w.finish()
+    w._loop()  # request 1 now runs to completion
+    assert done[-1].id == 1 and done[-1].error is None
+    assert not w.cancel(99)  # unknown ids are ignored
