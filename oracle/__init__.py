@@ -18,7 +18,8 @@ formula, so the standard definitions are spelled out in each module):
   wilson   Wilson-clover operator, clover term, block-restricted operator, dense matrix
   sap      even-odd block operator, minimal residual, Schwarz alternating procedure
   fgmres   flexible GMRES(m) with restarts and a true-residual check
+  mg       two-level aggregation multigrid with the Schwarz procedure as smoother
 
 Parity pins (closed forms, invariants, library special cases) live in tests/test_oracle*.py.
 """
-from . import gamma, lattice, wilson, sap, fgmres  # noqa: F401
+from . import gamma, lattice, wilson, sap, fgmres, mg  # noqa: F401
