@@ -48,6 +48,7 @@ extern "C" {
 typedef struct sapdd_ctx sapdd_ctx;     /* device, stream, workspaces, last error      */
 typedef struct sapdd_field sapdd_field; /* one resident gauge field and its clover term */
 typedef struct sapdd_batch sapdd_batch; /* continuous-batching solver state (slots)    */
+typedef struct sapdd_mg sapdd_mg;       /* two-level multigrid preconditioner          */
 
 enum {
     SAPDD_OK = 0,
@@ -170,6 +171,61 @@ int sapdd_batch_poll(const sapdd_batch *batch, int slot, sapdd_stats *stats);
  * completed restart cycle, a resume point to pass back later as x0 (SAPDD_USE_X0). */
 int sapdd_batch_take(sapdd_batch *batch, int slot, double *x, int flags, sapdd_stats *stats);
 
+/* Two-level multigrid with the Schwarz procedure as smoother (Sec. 2.6: the group's
+ * multigrid solver is a Krylov method preconditioned by a multigrid cycle whose smoother
+ * is the domain-decomposition preconditioner of Sec. 3.1; the rest follows the adaptive
+ * aggregation method the paper cites).
+ *   Aggregates: the field's Schwarz blocks, each split into its two chiralities (spins
+ *     0-1 and 2-3, gamma_5 = +1 and -1).
+ *   Test vectors: nvec fields given by the caller (random numbers are inputs, not drawn
+ *     here), each smoothed setup_iters times by v <- v - SAP(M v).
+ *   Interpolation P: on every aggregate and chirality the test vectors orthonormalised
+ *     by Gram-Schmidt in index order; coarse index k = s * nvec + j (chirality s, vector
+ *     j), K = 2 nvec coarse dofs per aggregate. Stored in FP32.
+ *   Coarse operator: D_c = P^H M P (Galerkin), nine K x K blocks per aggregate (itself
+ *     and its forward and backward neighbour in each direction), FP32, built on the
+ *     device by applying the FP64 operator to interpolated unit vectors.
+ *   Preconditioner B(r) = e + SAP(r - M e), e = P GMRES_k(D_c, P^H r): coarse_iters
+ *     GMRES steps from zero, run on the device, then one SAP application (smoother
+ *     params: nmr, ncy, sap_prec) on the remaining residual.
+ * Coarse vectors in the canonical form are complex [aggregate][K], aggregates in block
+ * order (x fastest), as complex128. A multigrid object belongs to its field and kappa
+ * and must be destroyed before the field is freed. */
+typedef struct {
+    int nvec;         /* test vectors per aggregate and chirality: even, 2..16          */
+    int setup_iters;  /* smoothing passes per test vector before P is built (>= 0)     */
+    int coarse_iters; /* GMRES steps of every coarse solve (1..24)                     */
+    int reserved;     /* must be 0                                                     */
+} sapdd_mg_params;
+/* Build P and D_c for (field, kappa). vecs: nvec canonical spinors (flags:
+ * SAPDD_DEVICE_PTRS). smoother supplies nmr, ncy and sap_prec of the smoothing passes
+ * and of sapdd_mg_precond. Blocks must have at most 512 sites. */
+int sapdd_mg_setup(sapdd_ctx *ctx, sapdd_field *field, double kappa, const sapdd_params *smoother,
+                   const sapdd_mg_params *mgp, const double *vecs, int flags, sapdd_mg **out);
+int sapdd_mg_destroy(sapdd_mg *mg);
+/* The nvec interpolation fields (FP32 values widened to FP64) as canonical spinors:
+ * column s * nvec + j of P is the chirality-s half of field j on every aggregate. */
+int sapdd_mg_prolongator(sapdd_mg *mg, double *fields, int flags);
+/* D_c in canonical form: [aggregate][d][row][col] complex128, d = 0 the aggregate itself,
+ * d = 1 + 2 mu its forward and d = 2 + 2 mu its backward neighbour in direction mu. On a
+ * block grid of extent 2 in direction mu both neighbours are one aggregate and the
+ * forward block holds the whole coupling (the backward block is zero). */
+int sapdd_mg_coarse_operator(sapdd_mg *mg, double *stencil, int flags);
+/* out = GMRES_k(D_c, rhs) for n canonical coarse vectors (k = coarse_iters, from zero;
+ * rhs rounded to FP32). */
+int sapdd_mg_coarse_solve(sapdd_mg *mg, int n, const double *rhs, double *out, int flags);
+/* out = B(in) for nrhs canonical spinors. */
+int sapdd_mg_precond(sapdd_mg *mg, int nrhs, const double *in, double *out, int flags);
+/* Solve M x = b (the multigrid's kappa) with FGMRES(params->restart) preconditioned by B:
+ * the batch solver with the multigrid cycle in place of the plain SAP application, its
+ * smoother set by params (nmr, ncy, sap_prec). Same arguments and results as
+ * sapdd_solve; the multigrid object keeps the batch for later calls. */
+int sapdd_mg_solve(sapdd_mg *mg, const sapdd_params *params, int nrhs, const double *b, double *x,
+                   sapdd_stats *stats);
+/* Make a batch (no slot in use) precondition with mg instead of SAP; every RHS added
+ * later must use mg's kappa. mg must outlive the batch's use of it. */
+int sapdd_batch_set_mg(sapdd_batch *batch, sapdd_mg *mg);
+
 /* Bytes of device memory a solve of nrhs RHS with these parameters allocates on top of
  * the resident field (Krylov bases, SAP state, operator copies), for admission control. */
 long long sapdd_solve_footprint(const sapdd_field *field, const sapdd_params *params, int nrhs);
@@ -187,6 +243,8 @@ enum {
     SAPDD_K_BLOCK_DSLASH = 3, /* block-diagonal operator M_B                        */
     SAPDD_K_UPDATE = 4,       /* solution update x += Z y                            */
     SAPDD_K_COPY = 5,         /* bandwidth-probe copy                                */
+    SAPDD_K_MG_FINE = 6,      /* multigrid restriction, interpolation and update     */
+    SAPDD_K_MG_COARSE = 7,    /* multigrid coarse GMRES                              */
     SAPDD_K_COUNT = 8
 };
 typedef struct {

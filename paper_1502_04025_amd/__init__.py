@@ -4,6 +4,6 @@ The compute path is the HIP library libsapdd.so (C ABI in include/sapdd.h); the 
 module `sapdd` only marshals arguments into it.
 """
 from .sapdd import (  # noqa: F401
-    Batch, Context, Field, Params, SapddError, Stats, load_library,
+    Batch, Context, Field, MgParams, Multigrid, Params, SapddError, Stats, load_library,
     F16, F32, F64, OK, EINVAL, EFULL, ENOCONV, ESINGULAR, ENAN, DEVICE_PTRS, USE_X0, NO_GRAPH,
 )

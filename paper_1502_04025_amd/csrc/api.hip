@@ -694,6 +694,119 @@ int sapdd_copy(sapdd_ctx *c, const void *src, void *dst, long long n) {
 }  // extern "C"
 
 
+// ====================================================================== multigrid state
+// The two-level preconditioner (Sec. 2.6: a Krylov solver preconditioned by a multigrid
+// cycle whose smoother is the Schwarz procedure). P and D_c are resident; every
+// application runs restriction, the coarse GMRES, interpolation, the FP64 residual, the
+// SAP smoother and the update as one launch sequence over the listed systems.
+struct sapdd_mg {
+    sapdd_ctx *c = nullptr;
+    sapdd_field *f = nullptr;
+    double kappa = 0;
+    sapdd_params sp{};     // smoother of the set-up and of sapdd_mg_precond
+    sapdd_mg_params mp{};
+    int nvec = 0, K = 0;
+    MgColouring cl{};
+    float *P = nullptr;    // nvec FP32 fields
+    float2 *Dc = nullptr;  // coarse operator, Nd * 9 * K * K
+    sapdd_batch *batch = nullptr;  // kept by sapdd_mg_solve
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+// Workspace of one multigrid application for `cap` systems (indexed by rhs).
+struct MgWork {
+    int cap = 0, nwg = 0;
+    double *t1 = nullptr, *t2 = nullptr;  // FP64 fields: interpolated coarse solution, residual
+    float2 *cb = nullptr;                 // coarse Krylov bases
+    double *pn = nullptr, *pd = nullptr, *H = nullptr, *sc = nullptr, *beta = nullptr, *coef = nullptr;
+};
+
+template <class Alloc>
+int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
+    const Geom &g = mg->f->geo;
+    const size_t nc = (size_t)g.Nd * mg->K;
+    w->cap = cap;
+    w->nwg = mg_coarse_wgs(g, mg->K);
+    void *q;
+    CHK(alloc("mg_t1", (size_t)cap * g.V * 24 * 8, &q));
+    w->t1 = (double *)q;
+    CHK(alloc("mg_t2", (size_t)cap * g.V * 24 * 8, &q));
+    w->t2 = (double *)q;
+    CHK(alloc("mg_cb", (size_t)cap * (MG_IMAX + 1) * nc * sizeof(float2), &q));
+    w->cb = (float2 *)q;
+    CHK(alloc("mg_pn", (size_t)cap * (MG_IMAX + 1) * w->nwg * 8, &q));
+    w->pn = (double *)q;
+    CHK(alloc("mg_pd", (size_t)cap * 4 * MG_IMAX * w->nwg * 8, &q));
+    w->pd = (double *)q;
+    CHK(alloc("mg_H", (size_t)cap * (MG_IMAX + 1) * MG_IMAX * 16, &q));
+    w->H = (double *)q;
+    CHK(alloc("mg_sc", (size_t)cap * (MG_IMAX + 1) * 8, &q));
+    w->sc = (double *)q;
+    CHK(alloc("mg_beta", (size_t)cap * 8, &q));
+    w->beta = (double *)q;
+    CHK(alloc("mg_coef", (size_t)cap * MG_IMAX * 16, &q));
+    w->coef = (double *)q;
+    return SAPDD_OK;
+}
+
+MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
+    const Geom &g = mg->f->geo;
+    MgGmres G{};
+    G.Dc = mg->Dc;
+    G.K = mg->K;
+    for (int mu = 0; mu < 4; ++mu) G.grid[mu] = g.G[mu];
+    G.Nd = g.Nd;
+    G.nwg = w.nwg;
+    G.basis = w.cb;
+    G.vstride = g.Nd * mg->K;
+    G.bstride = (MG_IMAX + 1) * G.vstride;
+    G.pn = w.pn;
+    G.pd = w.pd;
+    G.H = w.H;
+    G.sc = w.sc;
+    G.beta = w.beta;
+    G.coef = w.coef;
+    G.active = active;
+    return G;
+}
+
+// psi = B(s eta) for the listed systems (s = eta_scale[rhs * eta_sstride], 1 if null):
+// e = P GMRES_k(D_c, P^H eta) (the coarse solve is homogeneous, so it runs on the
+// unscaled eta), t2 = eta - M e, psi = SAP(s t2) + s e. eta: FP64 fields with stride
+// eta_stride fields per rhs; psi in psi_prec with stride psi_stride fields; per-rhs kappa
+// and clover from ss.
+int mg_run(sapdd_ctx *c, const sapdd_mg *mg, const MgWork &w, const SapState &ss, const sapdd_params *p,
+           const double *eta, int eta_stride, const double *eta_scale, int eta_sstride, void *psi, int psi_prec,
+           int psi_stride, const int *active, int nact) {
+    const Geom &g = mg->f->geo;
+    const int64_t NS = g.V * 24;
+    const MgGmres G = mg_gmres(mg, w, active);
+    const int k = mg->mp.coarse_iters;
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_restrict(g, mg->nvec, eta, eta_stride * NS, mg->P, w.cb, G.bstride, active,
+                                                   nact, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, nact, k, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_prolong_basis(g, mg->nvec, mg->P, w.cb, G.bstride, G.vstride, w.coef,
+                                                        2 * MG_IMAX, k, w.t1, NS, active, nact, c->stream));
+    DslashIO io{};
+    io.in = Fld{w.t1, nullptr, P64};
+    io.out = Fld{w.t2, nullptr, P64};
+    io.sub = eta;
+    io.active = active;
+    io.nact = nact;
+    io.in_stride = io.out_stride = 1;
+    io.sub_stride = eta_stride;
+    io.kappa = ss.kappa;
+    KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(mg->f, P64), tclov_of(mg->f, P64), 0.0, io, c->stream));
+    CHK(sap_run(c, g, ss, p, w.t2, 1, eta_scale, eta_sstride, psi, psi_prec, psi_stride, active, nact));
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_axpy(g, Fld{psi, nullptr, psi_prec}, psi_stride * NS, w.t1, NS, 1.0,
+                                               eta_scale, eta_sstride, active, nact, c->stream));
+    return SAPDD_OK;
+}
+
+}  // namespace
+
 // ====================================================================== FGMRES batch
 // A batch holds up to `cap` right-hand sides (slots) on one field, each with its own
 // kappa and Krylov state. One step is one FGMRES(m) restart cycle for every active slot:
@@ -748,6 +861,8 @@ struct sapdd_batch {
     std::vector<void *> allocs;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     double t_sap = 0, t_d = 0, t_gs = 0, t_host = 0;
+    sapdd_mg *mg = nullptr;  // multigrid preconditioner in place of SAP (sapdd_batch_set_mg)
+    MgWork mw{};
 };
 
 namespace {
@@ -851,22 +966,28 @@ int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
     return SAPDD_OK;
 }
 
-// z_j = SAP(v_j) for the cycle list (device list in segment SEG_CYCLE, ncyc slots),
+// z_j = SAP(v_j), or the multigrid cycle B(v_j) when the batch has one, for the cycle
+// list (device list in segment SEG_CYCLE, ncyc slots),
 // replayed from a graph captured once per (ncyc, j) when graphs are enabled.
 int batch_sap(sapdd_batch *B, int j, const int *d_cyc, int ncyc) {
     sapdd_ctx *c = B->c;
     const double *eta = (const double *)B->Vb.data + (size_t)j * B->NS;
     void *psi = (char *)B->Zb.data + (size_t)j * B->NS * prec_bytes(B->zprec);
-    if (!B->use_graph)
-        return sap_run(c, B->g, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m, d_cyc, ncyc);
+    auto run = [&]() {
+        if (B->mg)
+            return mg_run(c, B->mg, B->mw, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m,
+                          d_cyc, ncyc);
+        return sap_run(c, B->g, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m, d_cyc,
+                       ncyc);
+    };
+    if (!B->use_graph) return run();
     auto key = std::make_pair(ncyc, j);
     auto it = B->graphs.find(key);
     if (it == B->graphs.end()) {
         const bool prof = c->prof;
         c->prof = false;  // no event records inside the captured sequence
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        int r = sap_run(c, B->g, B->ss, &B->p, eta, B->m + 1, B->vscale + j, B->m + 1, psi, B->zprec, B->m, d_cyc,
-                        ncyc);
+        int r = run();
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &graph);
         c->prof = prof;
@@ -1222,6 +1343,27 @@ void batch_free(sapdd_batch *B) {
     delete B;
 }
 
+// A batch kept between solve calls serves a new call with the same field, shape and
+// solver parameters (tolerance and iteration cap are per call).
+bool batch_reusable(const sapdd_batch *B, const sapdd_field *f, const sapdd_params *p, int nrhs) {
+    return B && B->f == f && B->cap >= nrhs && B->p.restart == p->restart && B->p.nmr == p->nmr &&
+           B->p.ncy == p->ncy && B->p.sap_prec == p->sap_prec && B->p.deflate == p->deflate &&
+           ((B->p.flags ^ p->flags) & SAPDD_NO_GRAPH) == 0;
+}
+
+// Free the slots a call that failed half way may have left behind.
+int batch_release_slots(sapdd_batch *B) {
+    for (int r = 0; r < B->cap; ++r)
+        if (B->slots[r].used) {
+            sap_clover_release(B->f, B->slots[r].kappa, B->prec);
+            B->slots[r].used = false;
+        }
+    return SAPDD_OK;
+}
+
+int batch_solve_all(sapdd_batch *B, const double *kappa, const sapdd_params *p, int nrhs, const double *b, double *x,
+                    sapdd_stats *stats, double t0);
+
 }  // namespace
 
 extern "C" {
@@ -1328,6 +1470,8 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     c->err.clear();
     HIPCHK(c, hipSetDevice(c->device));
     if (!(kappa > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
+    if (B->mg && kappa != B->mg->kappa)
+        return fail(c, SAPDD_EINVAL, "the batch's multigrid preconditioner was built for kappa = %.17g", B->mg->kappa);
     int r = -1;
     for (int q = 0; q < B->cap; ++q)
         if (!B->slots[q].used) {
@@ -1488,15 +1632,8 @@ int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const 
     c->err.clear();
     HIPCHK(c, hipSetDevice(c->device));
     sapdd_batch *B = c->solve_batch;
-    const bool reuse = B && B->f == fc && B->cap >= nrhs && B->p.restart == p->restart && B->p.nmr == p->nmr &&
-                       B->p.ncy == p->ncy && B->p.sap_prec == p->sap_prec &&
-                       ((B->p.flags ^ p->flags) & SAPDD_NO_GRAPH) == 0;
-    if (reuse) {  // a call that failed half way may have left slots behind
-        for (int r = 0; r < B->cap; ++r)
-            if (B->slots[r].used) {
-                sap_clover_release(B->f, B->slots[r].kappa, B->prec);
-                B->slots[r].used = false;
-            }
+    if (batch_reusable(B, fc, p, nrhs)) {
+        CHK(batch_release_slots(B));
     } else {
         if (B) batch_free(B);
         c->solve_batch = nullptr;
@@ -1504,6 +1641,17 @@ int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const 
         CHK(sapdd_batch_create(c, fc, &q, nrhs, &B));
         c->solve_batch = B;
     }
+    return batch_solve_all(B, kappa, p, nrhs, b, x, stats, t0);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Add nrhs right-hand sides, step the batch until all finish and take the solutions.
+int batch_solve_all(sapdd_batch *B, const double *kappa, const sapdd_params *p, int nrhs, const double *b, double *x,
+                    sapdd_stats *stats, double t0) {
+    sapdd_ctx *c = B->c;
     B->p.tol = p->tol;
     B->p.max_iter = p->max_iter;
     B->t_sap = B->t_d = B->t_gs = B->t_host = 0;
@@ -1527,6 +1675,307 @@ int sapdd_solve(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const 
     }
     if (status == SAPDD_ENOCONV) return fail(c, SAPDD_ENOCONV, "not converged within max_iter = %d", p->max_iter);
     return status;
+}
+
+// Colouring for probing D_c: m_mu = the smallest divisor >= 3 of the block-grid extent
+// G_mu (G_mu itself if there is none), so two aggregates of one colour are never both
+// among an aggregate and its neighbours unless they coincide.
+MgColouring mg_colouring(const Geom &g) {
+    MgColouring cl{};
+    cl.n = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        int m = g.G[mu];
+        for (int d = 3; d < g.G[mu]; ++d)
+            if (g.G[mu] % d == 0) {
+                m = d;
+                break;
+            }
+        cl.m[mu] = m;
+        cl.n *= m;
+    }
+    return cl;
+}
+
+int mg_alloc(sapdd_mg *mg, size_t bytes, void **out) {
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(mg->c, SAPDD_ENOMEM, "hipMalloc of %zu bytes for the multigrid failed", bytes);
+    }
+    mg->allocs.push_back(q);
+    *out = q;
+    return SAPDD_OK;
+}
+
+void mg_free(sapdd_mg *mg) {
+    if (!mg) return;
+    if (mg->c) (void)hipStreamSynchronize(mg->c->stream);
+    if (mg->batch) batch_free(mg->batch);
+    for (void *q : mg->allocs) (void)hipFree(q);
+    delete mg;
+}
+
+// Copy n doubles from a device buffer to the caller's array (host or device per flags).
+int copy_out(sapdd_ctx *c, const void *src, double *dst, size_t n, int flags) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, n * 8,
+                             (flags & SAPDD_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SAPDD_OK;
+}
+
+int mg_setup_body(sapdd_mg *mg, const double *vecs, int flags) {
+    sapdd_ctx *c = mg->c;
+    sapdd_field *f = mg->f;
+    const Geom &g = f->geo;
+    const int nvec = mg->nvec, K = mg->K;
+    const size_t NS = (size_t)g.V * 24;
+    void *q;
+    CHK(mg_alloc(mg, (size_t)nvec * NS * sizeof(float), &q));
+    mg->P = (float *)q;
+    CHK(mg_alloc(mg, (size_t)g.Nd * 9 * K * K * sizeof(float2), &q));
+    mg->Dc = (float2 *)q;
+    // test vectors into the device layout (FP64)
+    const double *src;
+    CHK(stage_in(c, "stage_in", vecs, (size_t)nvec * NS, flags, &src));
+    CHK(buf(c, "mg_w", (size_t)nvec * NS * 8, &q));
+    double *w = (double *)q;
+    HIPCHK(c, launch_pack(g, 24, nvec, src, Fld{w, nullptr, P64}, c->stream));
+    int *ident;
+    CHK(identity_list(c, std::max(nvec, K), &ident));
+    if (mg->mp.setup_iters > 0) {  // v <- v - SAP(M v)
+        std::vector<double> kap(nvec, mg->kappa);
+        SapState s;
+        CHK(sap_prepare(c, f, kap.data(), nvec, mg->sp.sap_prec, &s));
+        CHK(buf(c, "mg_sm_t", (size_t)nvec * NS * 8, &q));
+        double *t = (double *)q;
+        CHK(buf(c, "mg_sm_psi", (size_t)nvec * NS * 8, &q));
+        double *psi = (double *)q;
+        for (int it = 0; it < mg->mp.setup_iters; ++it) {
+            DslashIO io{};
+            io.in = Fld{w, nullptr, P64};
+            io.out = Fld{t, nullptr, P64};
+            io.active = ident;
+            io.nact = nvec;
+            io.in_stride = io.out_stride = io.sub_stride = 1;
+            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), mg->kappa, io,
+                                                          c->stream));
+            CHK(sap_run(c, g, s, &mg->sp, t, 1, nullptr, 0, psi, P64, 1, ident, nvec));
+            KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_axpy(g, Fld{w, nullptr, P64}, NS, psi, NS, -1.0, nullptr, 0, ident,
+                                                       nvec, c->stream));
+        }
+    }
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_orth(g, w, nvec, c->stream));
+    HIPCHK(c, launch_convert(g, 24, nvec, w, Fld{mg->P, nullptr, P32}, c->stream));
+    // D_c column by column: for every colour and chunk of coarse columns, interpolate the
+    // unit vectors, apply the FP64 operator, restrict and scatter into the stencil.
+    HIPCHK(c, hipMemsetAsync(mg->Dc, 0, (size_t)g.Nd * 9 * K * K * sizeof(float2), c->stream));
+    const int chunk = std::min(K, 16);
+    CHK(buf(c, "mg_pr_in", (size_t)chunk * NS * 8, &q));
+    double *pin = (double *)q;
+    CHK(buf(c, "mg_pr_out", (size_t)chunk * NS * 8, &q));
+    double *pout = (double *)q;
+    CHK(buf(c, "mg_pr_r", (size_t)chunk * g.Nd * K * sizeof(float2), &q));
+    float2 *R = (float2 *)q;
+    for (int col = 0; col < mg->cl.n; ++col)
+        for (int k0 = 0; k0 < K; k0 += chunk) {
+            const int nk = std::min(chunk, K - k0);
+            KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_prolong_probe(g, mg->nvec, mg->P, col, mg->cl, k0, nk, pin,
+                                                                c->stream));
+            DslashIO io{};
+            io.in = Fld{pin, nullptr, P64};
+            io.out = Fld{pout, nullptr, P64};
+            io.active = ident;
+            io.nact = nk;
+            io.in_stride = io.out_stride = io.sub_stride = 1;
+            KLAUNCH(c, SAPDD_K_DSLASH, launch_dslash_full(g, links_of(f, P64), tclov_of(f, P64), mg->kappa, io,
+                                                          c->stream));
+            KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_restrict(g, mg->nvec, pout, (int64_t)NS, mg->P, R,
+                                                           (int64_t)g.Nd * K, nullptr, nk, c->stream));
+            KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_scatter(g, R, nk, k0, K, col, mg->cl, mg->Dc, c->stream));
+        }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SAPDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sapdd_mg_setup(sapdd_ctx *c, sapdd_field *f, double kappa, const sapdd_params *smoother,
+                   const sapdd_mg_params *mgp, const double *vecs, int flags, sapdd_mg **out) {
+    if (!c || !f || !smoother || !mgp || !vecs || !out) return fail(c, SAPDD_EINVAL, "null argument");
+    *out = nullptr;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    CHK(check_params(c, f, smoother));
+    if (!(kappa > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
+    if (mgp->nvec < 2 || mgp->nvec > MG_NVEC_MAX || mgp->nvec % 2)
+        return fail(c, SAPDD_EINVAL, "nvec must be even and in 2..%d", MG_NVEC_MAX);
+    if (mgp->coarse_iters < 1 || mgp->coarse_iters > MG_IMAX)
+        return fail(c, SAPDD_EINVAL, "coarse_iters must be in 1..%d", MG_IMAX);
+    if (mgp->setup_iters < 0 || mgp->reserved != 0) return fail(c, SAPDD_EINVAL, "bad multigrid parameters");
+    const Geom &g = f->geo;
+    if (g.Vb > 512) return fail(c, SAPDD_EINVAL, "multigrid aggregates (Schwarz blocks) must have <= 512 sites");
+    if ((int64_t)mgp->coarse_iters > g.Nd * 2 * mgp->nvec)
+        return fail(c, SAPDD_EINVAL, "coarse_iters exceeds the coarse dimension");
+    sapdd_mg *mg = new sapdd_mg;
+    mg->c = c;
+    mg->f = f;
+    mg->kappa = kappa;
+    mg->sp = *smoother;
+    mg->mp = *mgp;
+    mg->nvec = mgp->nvec;
+    mg->K = 2 * mgp->nvec;
+    mg->cl = mg_colouring(g);
+    const int r = mg_setup_body(mg, vecs, flags);
+    if (r != SAPDD_OK) {
+        mg_free(mg);
+        return r;
+    }
+    *out = mg;
+    return SAPDD_OK;
+}
+
+int sapdd_mg_destroy(sapdd_mg *mg) {
+    mg_free(mg);
+    return SAPDD_OK;
+}
+
+int sapdd_mg_prolongator(sapdd_mg *mg, double *fields, int flags) {
+    if (!mg || !fields) return SAPDD_EINVAL;
+    sapdd_ctx *c = mg->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    const Geom &g = mg->f->geo;
+    const size_t n = (size_t)mg->nvec * g.V * 24;
+    void *q;
+    CHK(buf(c, "stage_out", n * 8, &q));
+    HIPCHK(c, launch_unpack(g, 24, mg->nvec, Fld{mg->P, nullptr, P32}, (double *)q, c->stream));
+    return copy_out(c, q, fields, n, flags);
+}
+
+int sapdd_mg_coarse_operator(sapdd_mg *mg, double *stencil, int flags) {
+    if (!mg || !stencil) return SAPDD_EINVAL;
+    sapdd_ctx *c = mg->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    const Geom &g = mg->f->geo;
+    const int K = mg->K;
+    const size_t n = (size_t)g.Nd * 9 * K * K;
+    std::vector<float2> h(n);
+    HIPCHK(c, hipMemcpyAsync(h.data(), mg->Dc, n * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // device: column-major blocks; canonical: row-major blocks, complex128
+    std::vector<double> o(2 * n);
+    for (size_t blk = 0; blk < (size_t)g.Nd * 9; ++blk)
+        for (int row = 0; row < K; ++row)
+            for (int col = 0; col < K; ++col) {
+                const float2 v = h[(blk * K + col) * K + row];
+                o[2 * ((blk * K + row) * K + col)] = v.x;
+                o[2 * ((blk * K + row) * K + col) + 1] = v.y;
+            }
+    if (flags & SAPDD_DEVICE_PTRS) {
+        HIPCHK(c, hipMemcpyAsync(stencil, o.data(), 2 * n * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        memcpy(stencil, o.data(), 2 * n * 8);
+    }
+    return SAPDD_OK;
+}
+
+int sapdd_mg_coarse_solve(sapdd_mg *mg, int n, const double *rhs, double *out, int flags) {
+    if (!mg || !rhs || !out || n < 1) return SAPDD_EINVAL;
+    sapdd_ctx *c = mg->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    const Geom &g = mg->f->geo;
+    const size_t nc = (size_t)g.Nd * mg->K;
+    MgWork w;
+    CHK(mg_work_init(mg, n, [&](const char *name, size_t bytes, void **q) { return buf(c, name, bytes, q); }, &w));
+    int *ident;
+    CHK(identity_list(c, n, &ident));
+    const double *src;
+    CHK(stage_in(c, "stage_in", rhs, (size_t)n * nc * 2, flags, &src));
+    const MgGmres G = mg_gmres(mg, w, ident);
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_load(G, n, src, (int64_t)nc * 2, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, n, mg->mp.coarse_iters, c->stream));
+    void *q;
+    CHK(buf(c, "stage_out", (size_t)n * nc * 16, &q));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_combine(G, n, mg->mp.coarse_iters, (double *)q, (int64_t)nc * 2,
+                                                    c->stream));
+    return copy_out(c, q, out, (size_t)n * nc * 2, flags);
+}
+
+int sapdd_mg_precond(sapdd_mg *mg, int nrhs, const double *in, double *out, int flags) {
+    if (!mg || !in || !out || nrhs < 1) return SAPDD_EINVAL;
+    sapdd_ctx *c = mg->c;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    sapdd_field *f = mg->f;
+    const Geom &g = f->geo;
+    const size_t NS = (size_t)g.V * 24;
+    std::vector<double> kap(nrhs, mg->kappa);
+    SapState s;
+    CHK(sap_prepare(c, f, kap.data(), nrhs, mg->sp.sap_prec, &s));
+    MgWork w;
+    CHK(mg_work_init(mg, nrhs, [&](const char *name, size_t bytes, void **q) { return buf(c, name, bytes, q); },
+                     &w));
+    int *ident;
+    CHK(identity_list(c, nrhs, &ident));
+    const double *src;
+    CHK(stage_in(c, "stage_in", in, (size_t)nrhs * NS, flags, &src));
+    void *q;
+    CHK(buf(c, "mg_eta", (size_t)nrhs * NS * 8, &q));
+    double *eta = (double *)q;
+    CHK(buf(c, "mg_psi", (size_t)nrhs * NS * 8, &q));
+    double *psi = (double *)q;
+    HIPCHK(c, launch_pack(g, 24, nrhs, src, Fld{eta, nullptr, P64}, c->stream));
+    CHK(mg_run(c, mg, w, s, &mg->sp, eta, 1, nullptr, 0, psi, P64, 1, ident, nrhs));
+    CHK(buf(c, "stage_out", (size_t)nrhs * NS * 8, &q));
+    HIPCHK(c, launch_unpack(g, 24, nrhs, Fld{psi, nullptr, P64}, (double *)q, c->stream));
+    return copy_out(c, q, out, (size_t)nrhs * NS, flags);
+}
+
+int sapdd_batch_set_mg(sapdd_batch *B, sapdd_mg *mg) {
+    if (!B || !mg) return SAPDD_EINVAL;
+    sapdd_ctx *c = B->c;
+    c->err.clear();
+    if (mg->f != B->f || mg->c != c) return fail(c, SAPDD_EINVAL, "the multigrid belongs to another field or context");
+    for (const auto &s : B->slots)
+        if (s.used) return fail(c, SAPDD_EINVAL, "the batch has slots in use");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);  // captured for the old preconditioner
+    B->graphs.clear();
+    CHK(mg_work_init(mg, B->cap, [&](const char *, size_t bytes, void **q) { return balloc(B, bytes, q); }, &B->mw));
+    B->mg = mg;
+    return SAPDD_OK;
+}
+
+int sapdd_mg_solve(sapdd_mg *mg, const sapdd_params *p, int nrhs, const double *b, double *x, sapdd_stats *stats) {
+    const double t0 = now_s();
+    if (!mg || !p || !b || !x) return SAPDD_EINVAL;
+    sapdd_ctx *c = mg->c;
+    if (nrhs < 1) return fail(c, SAPDD_EINVAL, "nrhs must be >= 1");
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    sapdd_batch *B = mg->batch;
+    if (batch_reusable(B, mg->f, p, nrhs)) {
+        CHK(batch_release_slots(B));
+    } else {
+        if (B) batch_free(B);
+        mg->batch = nullptr;
+        sapdd_params q = *p;
+        CHK(sapdd_batch_create(c, mg->f, &q, nrhs, &B));
+        const int r = sapdd_batch_set_mg(B, mg);
+        if (r != SAPDD_OK) {
+            batch_free(B);
+            return r;
+        }
+        mg->batch = B;
+    }
+    std::vector<double> kap(nrhs, mg->kappa);
+    return batch_solve_all(B, kap.data(), p, nrhs, b, x, stats, t0);
 }
 
 }  // extern "C"

@@ -128,4 +128,62 @@ hipError_t launch_zupdate(double *x, int64_t xstride, const void *z, int zprec, 
                           int64_t zstride_rhs, const double *y, int ystride, int nz, const int *active, int nact,
                           int64_t n, int vbh, hipStream_t st);
 
+// ---- two-level multigrid (mg.hip)
+constexpr int MG_NVEC_MAX = 16;  // test vectors (coarse dofs per aggregate and chirality)
+constexpr int MG_IMAX = 24;      // coarse GMRES steps
+constexpr int MG_CWG = 256;      // workgroup of the coarse kernels
+// Colouring of the block grid for probing the coarse operator: colour of block
+// coordinates g = sum_mu (g_mu mod m_mu) * prod_{nu < mu} m_nu, n colours.
+struct MgColouring {
+    int m[4];
+    int n;
+};
+int mg_colour_of(const int g[4], const MgColouring &cl);
+// In place: per aggregate and chirality, Gram-Schmidt (twice) over nvec FP64 fields.
+hipError_t launch_mg_orth(const Geom &geo, double *w, int nvec, hipStream_t st);
+// out(rhs) = P^H in(rhs): FP64 fields (stride in doubles) -> FP32 complex coarse vectors
+// (stride in complex numbers); rhs = active[slot] (slot if active is null).
+hipError_t launch_mg_restrict(const Geom &geo, int nvec, const double *in, int64_t in_stride, const float *P,
+                              float2 *out, int64_t out_stride, const int *active, int nact, hipStream_t st);
+// out(rhs) = P sum_{i < nb} coef(rhs)[i] basis(rhs)[i], FP64 output (stride in doubles).
+hipError_t launch_mg_prolong_basis(const Geom &geo, int nvec, const float *P, const float2 *basis, int64_t bstride,
+                                   int64_t vstride, const double *coef, int64_t cstride, int nb, double *out,
+                                   int64_t out_stride, const int *active, int nact, hipStream_t st);
+// out(col) = P e for e = 1 in coarse column k0 + col on the aggregates of colour q
+// (col < ncol; out stride V * 24 doubles).
+hipError_t launch_mg_prolong_probe(const Geom &geo, int nvec, const float *P, int q, const MgColouring &cl, int k0,
+                                   int ncol, double *out, hipStream_t st);
+// D_c columns k0 .. k0 + ncol - 1 from the restricted probe results R[col][b][row].
+hipError_t launch_mg_scatter(const Geom &geo, const float2 *R, int ncol, int k0, int K, int q,
+                             const MgColouring &cl, float2 *Dc, hipStream_t st);
+// y(rhs) += alpha * scale[rhs * sstride] * x(rhs) (scale may be null): y FP64 or FP32,
+// x FP64, strides in elements of each.
+hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double *x, int64_t xstride, double alpha,
+                          const double *scale, int sstride, const int *active, int nact, hipStream_t st);
+// Coarse GMRES state of the listed systems (all buffers per rhs, indexed by rhs).
+struct MgGmres {
+    const float2 *Dc;  // coarse operator
+    int K;             // 2 nvec
+    int grid[4];       // block grid
+    int64_t Nd;        // aggregates
+    int nwg;           // workgroups per system (mg_coarse_wgs)
+    float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride; slot 0 = rhs
+    int64_t bstride, vstride;
+    double *pn;        // [rhs][MG_IMAX + 1][nwg] |v_i|^2 partials
+    double *pd;        // [rhs][2][2 MG_IMAX][nwg] Gram-Schmidt partials
+    double *H;         // [rhs][MG_IMAX][MG_IMAX + 1] complex, column-major Hessenberg
+    double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
+    double *beta;      // [rhs] |rhs|
+    double *coef;      // [rhs][MG_IMAX] complex: solution = sum_i coef[i] basis[i]
+    const int *active;
+};
+int mg_coarse_wgs(const Geom &geo, int K);
+// k GMRES steps from zero on D_c e = basis[0] for every listed system; the solution's
+// coefficients over the stored basis go to coef.
+hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st);
+// basis(rhs)[0] = in(rhs) rounded to FP32, in complex FP64 at in + rhs * istride.
+hipError_t launch_mg_load(const MgGmres &G, int nact, const double *in, int64_t istride, hipStream_t st);
+// out(rhs) = sum_{i < nb} coef(rhs)[i] basis(rhs)[i], complex FP64 at out + rhs * ostride.
+hipError_t launch_mg_combine(const MgGmres &G, int nact, int nb, double *out, int64_t ostride, hipStream_t st);
+
 }  // namespace sapdd

@@ -1,0 +1,752 @@
+// mg.hip - kernels of the two-level aggregation multigrid preconditioner whose smoother
+// is the Schwarz procedure (Sec. 2.6: the group's multigrid solver is a Krylov method
+// preconditioned by a multigrid cycle with the domain-decomposition preconditioner of
+// Sec. 3.1 as its smoother).
+//
+// Aggregates are the Schwarz blocks, each split into its two chiralities: spins 0, 1
+// and spins 2, 3, the two eigenspaces of gamma_5 in the DeGrand-Rossi basis. The
+// interpolation P holds nvec FP32 spinor fields in the block-tiled layout; coarse index
+// k = s * nvec + j is the chirality-s half of field j on each aggregate, orthonormal
+// per aggregate and chirality. Coarse vectors are complex FP32 arrays [aggregate][K]
+// (K = 2 nvec, aggregates in block order, x fastest). The Galerkin operator
+// D_c = P^H M P couples an aggregate to itself and its eight neighbours; it is stored
+// as nine K x K blocks per aggregate, column-major within a block so that the K rows
+// of one column are contiguous: element (row, col) of block d at
+// ((b * 9 + d) * K + col) * K + row, d = 0 the aggregate itself, d = 1 + 2 mu the
+// forward and d = 2 + 2 mu the backward neighbour in direction mu.
+//
+// The coarse system is solved by a fixed number of GMRES steps from zero, entirely on
+// the device so the whole preconditioner is one static launch sequence: every Arnoldi
+// step is three kernels (operator + first Gram-Schmidt pass, second pass, norm), each
+// reduction a fixed-order sum of per-workgroup partials that every workgroup of the
+// next kernel repeats for itself, and one workgroup per system solves the small least
+// squares problem at the end.
+#include "kernels.hpp"
+
+namespace sapdd {
+
+namespace {
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+__host__ __device__ __forceinline__ int mg_colour(const int g[4], const MgColouring &cl) {
+    return (((g[3] % cl.m[3]) * cl.m[2] + g[2] % cl.m[2]) * cl.m[1] + g[1] % cl.m[1]) * cl.m[0] + g[0] % cl.m[0];
+}
+
+// Block index of neighbour d (0 = itself, 1 + 2 mu forward, 2 + 2 mu backward) of the
+// aggregate with block coordinates g.
+__device__ __forceinline__ int64_t mg_neighbour(const int G[4], const int g[4], int d) {
+    if (d == 0) return block_index(G, g);
+    const int mu = (d - 1) >> 1;
+    int h[4] = {g[0], g[1], g[2], g[3]};
+    h[mu] = (d & 1) ? (h[mu] + 1 == G[mu] ? 0 : h[mu] + 1) : (h[mu] == 0 ? G[mu] - 1 : h[mu] - 1);
+    return block_index(G, h);
+}
+
+// Sum of N doubles over the workgroup (blockDim.x a multiple of 64); every thread gets
+// the totals. lds holds (blockDim.x / 64) * N doubles.
+template <int N>
+__device__ __forceinline__ void wg_sum(double (&v)[N], double *lds) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[w * N + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double t = 0;
+        for (int q = 0; q < nw; ++q) t += lds[q * N + k];
+        v[k] = t;
+    }
+    __syncthreads();
+}
+
+// Sum of the first nval of N doubles over the workgroup, written by threads t < nval to
+// out[t * stride] (partials of one workgroup). lds holds (blockDim.x / 64) * N doubles.
+template <int N>
+__device__ __forceinline__ void wg_sum_store(double (&v)[N], double *lds, int nval, double *out, int64_t stride) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k < nval)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k < nval) lds[w * N + k] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < nval) {
+        double t = 0;
+        for (int q = 0; q < nw; ++q) t += lds[q * N + threadIdx.x];
+        out[(int64_t)threadIdx.x * stride] = t;
+    }
+}
+
+// FP64 site component c (complex) of a block-tiled spinor field.
+__device__ __forceinline__ dv2 ld64(const double *f, int64_t bp, int c, int s, int Vbh) {
+    return reinterpret_cast<const dv2 *>(f)[(bp * 12 + c) * Vbh + s];
+}
+__device__ __forceinline__ void st64(double *f, int64_t bp, int c, int s, int Vbh, dv2 x) {
+    reinterpret_cast<dv2 *>(f)[(bp * 12 + c) * Vbh + s] = x;
+}
+// The 6 complex components of chirality ch of site (bp, s) of the FP32 field P_j.
+__device__ __forceinline__ void ldP(const float *P, int64_t bp, int ch, int s, int Vbh, float (&re)[6],
+                                    float (&im)[6]) {
+    const float4 *p = reinterpret_cast<const float4 *>(P);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const float4 x = p[(bp * 6 + 3 * ch + v) * Vbh + s];
+        re[2 * v] = x.x;
+        im[2 * v] = x.y;
+        re[2 * v + 1] = x.z;
+        im[2 * v + 1] = x.w;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- set-up kernels
+
+// In place, per aggregate and chirality: modified Gram-Schmidt with one
+// reorthogonalisation pass over the nvec FP64 fields (field j at w + j * V * 24).
+__global__ __launch_bounds__(512) void mg_orth_kernel(double *w, int nvec, int64_t V, int Vbh) {
+    __shared__ double lds[8 * 2];
+    const int tid = threadIdx.x;
+    const bool act = tid < 2 * Vbh;
+    const int p = act ? tid / Vbh : 0, s = act ? tid % Vbh : 0;
+    const int64_t bp = 2 * (int64_t)blockIdx.x + p;
+    for (int ch = 0; ch < 2; ++ch)
+        for (int j = 0; j < nvec; ++j) {
+            double *fj = w + (int64_t)j * V * 24;
+            dv2 x[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) x[c] = act ? ld64(fj, bp, 6 * ch + c, s, Vbh) : dv2{0.0, 0.0};
+            for (int pass = 0; pass < 2; ++pass)
+                for (int i = 0; i < j; ++i) {
+                    const double *fi = w + (int64_t)i * V * 24;
+                    dv2 q[6];
+                    double d[2] = {0.0, 0.0};
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        q[c] = act ? ld64(fi, bp, 6 * ch + c, s, Vbh) : dv2{0.0, 0.0};
+                        d[0] += q[c].x * x[c].x + q[c].y * x[c].y;
+                        d[1] += q[c].x * x[c].y - q[c].y * x[c].x;
+                    }
+                    wg_sum<2>(d, lds);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        x[c].x -= d[0] * q[c].x - d[1] * q[c].y;
+                        x[c].y -= d[0] * q[c].y + d[1] * q[c].x;
+                    }
+                }
+            double n[1] = {0.0};
+#pragma unroll
+            for (int c = 0; c < 6; ++c) n[0] += x[c].x * x[c].x + x[c].y * x[c].y;
+            wg_sum<1>(n, lds);
+            const double inv = n[0] > 0 ? 1.0 / sqrt(n[0]) : 0.0;
+            if (act)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) st64(fj, bp, 6 * ch + c, s, Vbh, x[c] * inv);
+        }
+}
+
+hipError_t launch_mg_orth(const Geom &geo, double *w, int nvec, hipStream_t st) {
+    if (nvec < 1 || nvec > MG_NVEC_MAX) return hipErrorInvalidValue;
+    const int nt = (2 * geo.Vbh + 63) / 64 * 64;
+    hipLaunchKernelGGL(mg_orth_kernel, dim3((unsigned)geo.Nd), dim3(nt), 0, st, w, nvec, geo.V, geo.Vbh);
+    return hipGetLastError();
+}
+
+// Scatter one probe: R[col][b][row] = (P^H M P e_col)(b) for the unit coarse vectors of
+// columns k0 + col on the aggregates of colour q. Aggregates of one colour differ by a
+// multiple of m_mu in every direction, with m_mu >= 3 or m_mu = G_mu, so among an
+// aggregate and its eight neighbours at most one distinct aggregate has colour q, and
+// R(b) is that aggregate's block column (D_c vanishes between aggregates that are not
+// neighbours). With a block-grid extent of 2 the forward and backward neighbour coincide;
+// the first match (forward) then takes both couplings.
+__global__ void mg_scatter_kernel(const float2 *R, int ncol, int k0, int K, int q, MgColouring cl, Geom geo,
+                                  float2 *Dc) {
+    const int64_t n = geo.Nd * ncol * K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int row = (int)(t % K);
+    const int col = (int)(t / K % ncol);
+    const int64_t b = t / ((int64_t)K * ncol);
+    int g[4];
+    block_coords(geo.G, b, g);
+    for (int d = 0; d < 9; ++d) {
+        int h[4] = {g[0], g[1], g[2], g[3]};
+        if (d > 0) {
+            const int mu = (d - 1) >> 1;
+            h[mu] = (d & 1) ? (h[mu] + 1) % geo.G[mu] : (h[mu] + geo.G[mu] - 1) % geo.G[mu];
+        }
+        if (mg_colour(h, cl) == q) {
+            Dc[((b * 9 + d) * K + k0 + col) * K + row] = R[((int64_t)col * geo.Nd + b) * K + row];
+            return;
+        }
+    }
+}
+
+hipError_t launch_mg_scatter(const Geom &geo, const float2 *R, int ncol, int k0, int K, int q,
+                             const MgColouring &cl, float2 *Dc, hipStream_t st) {
+    const int64_t n = geo.Nd * ncol * K;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mg_scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, ncol, k0, K, q,
+                       cl, geo, Dc);
+    return hipGetLastError();
+}
+
+int mg_colour_of(const int g[4], const MgColouring &cl) { return mg_colour(g, cl); }
+
+// ---------------------------------------------------------------- fine-grid kernels
+
+// out(rhs)[b][k] = (P^H in(rhs))(b)[k] for one aggregate b per workgroup. in: FP64
+// block-tiled spinors of the listed rhs at in + rhs * in_stride; out FP32 complex at
+// out + rhs * out_stride. FP64 accumulation.
+template <int NV>
+__global__ __launch_bounds__(512) void mg_restrict_kernel(const double *in, int64_t in_stride, const float *P,
+                                                           int64_t V, int Vbh, float2 *out, int64_t out_stride,
+                                                           const int *active) {
+    __shared__ double lds[8 * 2 * NV];
+    const int tid = threadIdx.x;
+    const bool act = tid < 2 * Vbh;
+    const int p = act ? tid / Vbh : 0, s = act ? tid % Vbh : 0;
+    const int64_t b = blockIdx.x, bp = 2 * b + p;
+    const int rhs = active ? active[blockIdx.y] : (int)blockIdx.y;
+    const double *r = in + (int64_t)rhs * in_stride;
+    float2 *o = out + (int64_t)rhs * out_stride + b * (2 * NV);
+    for (int ch = 0; ch < 2; ++ch) {
+        dv2 x[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) x[c] = act ? ld64(r, bp, 6 * ch + c, s, Vbh) : dv2{0.0, 0.0};
+        double acc[2 * NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            float pr[6], pi[6];
+            if (act) ldP(P + (int64_t)j * V * 24, bp, ch, s, Vbh, pr, pi);
+            double are = 0, aim = 0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double qr = act ? (double)pr[c] : 0.0, qi = act ? (double)pi[c] : 0.0;
+                are += qr * x[c].x + qi * x[c].y;
+                aim += qr * x[c].y - qi * x[c].x;
+            }
+            acc[2 * j] = are;
+            acc[2 * j + 1] = aim;
+        }
+        wg_sum<2 * NV>(acc, lds);
+        if (tid == 0)
+#pragma unroll
+            for (int j = 0; j < NV; ++j) o[ch * NV + j] = make_float2((float)acc[2 * j], (float)acc[2 * j + 1]);
+    }
+}
+
+// out(rhs) = P e(rhs) (or out += P e with ADD) on one aggregate per workgroup, FP64
+// output. The coarse vector e on the aggregate is either
+//   probe (cprobe.q >= 0): 1 in column k0 + rhs on aggregates of colour q, else 0, or
+//   a combination sum_{i < nb} coef(rhs)[i] basis(rhs)[i] of coarse vectors.
+struct MgCoarseSrc {
+    const float2 *basis;   // basis(rhs)[i] at basis + rhs * bstride + i * vstride
+    int64_t bstride, vstride;
+    const double *coef;    // complex coef(rhs)[i] at coef + rhs * cstride + 2 i
+    int64_t cstride;
+    int nb;
+    int q, k0;             // probe colour (q < 0: no probe) and first column
+    MgColouring cl;
+};
+
+template <int NV>
+__global__ __launch_bounds__(512) void mg_prolong_kernel(MgCoarseSrc src, const float *P, Geom geo, double *out,
+                                                          int64_t out_stride, const int *active) {
+    constexpr int K = 2 * NV;
+    __shared__ float2 e[K];
+    const int tid = threadIdx.x;
+    const int Vbh = geo.Vbh;
+    const bool act = tid < 2 * Vbh;
+    const int p = act ? tid / Vbh : 0, s = act ? tid % Vbh : 0;
+    const int64_t b = blockIdx.x, bp = 2 * b + p;
+    const int rhs = active ? active[blockIdx.y] : (int)blockIdx.y;
+    if (tid < K) {
+        float2 v = make_float2(0.f, 0.f);
+        if (src.q >= 0) {
+            int g[4];
+            block_coords(geo.G, b, g);
+            if (mg_colour(g, src.cl) == src.q && tid == src.k0 + rhs) v.x = 1.f;
+        } else {
+            const float2 *bs = src.basis + (int64_t)rhs * src.bstride + b * K + tid;
+            const double *cf = src.coef + (int64_t)rhs * src.cstride;
+            double vr = 0, vi = 0;
+            for (int i = 0; i < src.nb; ++i) {
+                const float2 x = bs[(int64_t)i * src.vstride];
+                vr += cf[2 * i] * x.x - cf[2 * i + 1] * x.y;
+                vi += cf[2 * i] * x.y + cf[2 * i + 1] * x.x;
+            }
+            v = make_float2((float)vr, (float)vi);
+        }
+        e[tid] = v;
+    }
+    __syncthreads();
+    if (!act) return;
+    double *o = out + (int64_t)rhs * out_stride;
+    for (int ch = 0; ch < 2; ++ch) {
+        double yr[6] = {0, 0, 0, 0, 0, 0}, yi[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            float pr[6], pi[6];
+            ldP(P + (int64_t)j * geo.V * 24, bp, ch, s, Vbh, pr, pi);
+            const float2 c = e[ch * NV + j];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                yr[k] += (double)c.x * pr[k] - (double)c.y * pi[k];
+                yi[k] += (double)c.x * pi[k] + (double)c.y * pr[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st64(o, bp, 6 * ch + k, s, Vbh, dv2{yr[k], yi[k]});
+    }
+}
+
+template <int NV>
+static hipError_t restrict_nv(const Geom &geo, const double *in, int64_t in_stride, const float *P, float2 *out,
+                              int64_t out_stride, const int *active, int nact, hipStream_t st) {
+    const int nt = (2 * geo.Vbh + 63) / 64 * 64;
+    hipLaunchKernelGGL(mg_restrict_kernel<NV>, dim3((unsigned)geo.Nd, (unsigned)nact), dim3(nt), 0, st, in,
+                       in_stride, P, geo.V, geo.Vbh, out, out_stride, active);
+    return hipGetLastError();
+}
+template <int NV>
+static hipError_t prolong_nv(const Geom &geo, const MgCoarseSrc &src, const float *P, double *out,
+                             int64_t out_stride, const int *active, int nact, hipStream_t st) {
+    const int nt = (2 * geo.Vbh + 63) / 64 * 64;
+    hipLaunchKernelGGL(mg_prolong_kernel<NV>, dim3((unsigned)geo.Nd, (unsigned)nact), dim3(nt), 0, st, src, P, geo,
+                       out, out_stride, active);
+    return hipGetLastError();
+}
+
+#define MG_NV_SWITCH(nvec, CALL)   \
+    switch (nvec) {                \
+        case 2: return CALL(2);    \
+        case 4: return CALL(4);    \
+        case 6: return CALL(6);    \
+        case 8: return CALL(8);    \
+        case 10: return CALL(10);  \
+        case 12: return CALL(12);  \
+        case 14: return CALL(14);  \
+        case 16: return CALL(16);  \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_mg_restrict(const Geom &geo, int nvec, const double *in, int64_t in_stride, const float *P,
+                              float2 *out, int64_t out_stride, const int *active, int nact, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+#define MG_R(NV) restrict_nv<NV>(geo, in, in_stride, P, out, out_stride, active, nact, st)
+    MG_NV_SWITCH(nvec, MG_R)
+#undef MG_R
+}
+
+hipError_t launch_mg_prolong_basis(const Geom &geo, int nvec, const float *P, const float2 *basis, int64_t bstride,
+                                   int64_t vstride, const double *coef, int64_t cstride, int nb, double *out,
+                                   int64_t out_stride, const int *active, int nact, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    MgCoarseSrc src{};
+    src.basis = basis;
+    src.bstride = bstride;
+    src.vstride = vstride;
+    src.coef = coef;
+    src.cstride = cstride;
+    src.nb = nb;
+    src.q = -1;
+#define MG_P(NV) prolong_nv<NV>(geo, src, P, out, out_stride, active, nact, st)
+    MG_NV_SWITCH(nvec, MG_P)
+#undef MG_P
+}
+
+hipError_t launch_mg_prolong_probe(const Geom &geo, int nvec, const float *P, int q, const MgColouring &cl, int k0,
+                                   int ncol, double *out, hipStream_t st) {
+    MgCoarseSrc src{};
+    src.q = q;
+    src.k0 = k0;
+    src.cl = cl;
+#define MG_Q(NV) prolong_nv<NV>(geo, src, P, out, geo.V * 24, nullptr, ncol, st)
+    MG_NV_SWITCH(nvec, MG_Q)
+#undef MG_Q
+}
+
+// y(rhs) += a(rhs) x(rhs) over whole block-tiled spinor fields: x FP64, y FP64 or FP32,
+// a(rhs) = alpha * scale[rhs * sstride] (alpha alone if scale is null). One thread per
+// 16-byte vector of y.
+template <class TY>
+__global__ void mg_axpy_kernel(TY *y, int64_t ystride, const double *x, int64_t xstride, double alpha,
+                               const double *scale, int sstride, const int *active, int64_t nvec16, int Vbh) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nvec16) return;
+    const int rhs = active ? active[blockIdx.y] : (int)blockIdx.y;
+    const double a = scale ? alpha * scale[(int64_t)rhs * sstride] : alpha;
+    const dv2 *xs = reinterpret_cast<const dv2 *>(x + (int64_t)rhs * xstride);
+    if constexpr (sizeof(TY) == 8) {
+        dv2 *ys = reinterpret_cast<dv2 *>(y + (int64_t)rhs * ystride);
+        ys[t] += a * xs[t];
+    } else {
+        // FP32 vector t = ((bp * 6 + v) * Vbh + s) holds the complex components 2v, 2v+1
+        // that sit in FP64 vectors (bp * 12 + 2v) * Vbh + s and the next component
+        const int s = (int)(t % Vbh);
+        const int64_t u = t / Vbh;
+        const int v = (int)(u % 6);
+        const int64_t bp = u / 6;
+        float4 *ys = reinterpret_cast<float4 *>(y + (int64_t)rhs * ystride);
+        const dv2 x0 = xs[(bp * 12 + 2 * v) * Vbh + s], x1 = xs[(bp * 12 + 2 * v + 1) * Vbh + s];
+        float4 w = ys[t];
+        w.x = (float)((double)w.x + a * x0.x);
+        w.y = (float)((double)w.y + a * x0.y);
+        w.z = (float)((double)w.z + a * x1.x);
+        w.w = (float)((double)w.w + a * x1.y);
+        ys[t] = w;
+    }
+}
+
+hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double *x, int64_t xstride, double alpha,
+                          const double *scale, int sstride, const int *active, int nact, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    if (y.prec == P64) {
+        const int64_t n = geo.V * 12;
+        hipLaunchKernelGGL(mg_axpy_kernel<double>, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0,
+                           st, (double *)y.data, ystride, x, xstride, alpha, scale, sstride, active, n, geo.Vbh);
+    } else if (y.prec == P32) {
+        const int64_t n = geo.V * 6;
+        hipLaunchKernelGGL(mg_axpy_kernel<float>, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0, st,
+                           (float *)y.data, ystride, x, xstride, alpha, scale, sstride, active, n, geo.Vbh);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- coarse GMRES
+
+// Workgroup tiling of the coarse kernels: TB aggregates of K rows each per workgroup.
+int mg_coarse_tile(int K) { return MG_CWG / K; }
+int mg_coarse_wgs(const Geom &geo, int K) {
+    const int tb = mg_coarse_tile(K);
+    return (int)((geo.Nd + tb - 1) / tb);
+}
+
+namespace {
+
+struct CoarseThread {
+    int64_t b;
+    int a;
+    bool act;
+};
+__device__ __forceinline__ CoarseThread coarse_thread(int K, int64_t Nd) {
+    const int tb = MG_CWG / K;
+    const int bl = threadIdx.x / K;
+    CoarseThread t;
+    t.a = threadIdx.x - bl * K;
+    t.b = (int64_t)blockIdx.x * tb + bl;
+    t.act = bl < tb && t.b < Nd;
+    return t;
+}
+
+// sum over nwg partials of value k (fixed order)
+__device__ __forceinline__ double psum(const double *part, int nwg) {
+    double t = 0;
+    for (int q = 0; q < nwg; ++q) t += part[q];
+    return t;
+}
+
+// The coarse sums of one pass: h[i] (complex, i <= j) into LDS, every thread reading
+// the partials of pass `pass` in workgroup order.
+__device__ __forceinline__ void load_coefs(const MgGmres &G, int rhs, int pass, int j, double *h) {
+    const double *pd = G.pd + ((int64_t)rhs * 2 + pass) * 2 * MG_IMAX * G.nwg;
+    for (int t = threadIdx.x; t < 2 * (j + 1); t += blockDim.x) h[t] = psum(pd + (int64_t)t * G.nwg, G.nwg);
+    __syncthreads();
+}
+
+}  // namespace
+
+// |v_0|^2 partials of every listed system (v_0 = the restricted right-hand side).
+__global__ __launch_bounds__(MG_CWG) void mg_cinit_kernel(MgGmres G) {
+    __shared__ double lds[MG_CWG / 64];
+    const int rhs = G.active[blockIdx.y];
+    const CoarseThread t = coarse_thread(G.K, G.Nd);
+    const float2 *v0 = G.basis + (int64_t)rhs * G.bstride;
+    double n[1] = {0.0};
+    if (t.act) {
+        const float2 x = v0[t.b * G.K + t.a];
+        n[0] = (double)x.x * x.x + (double)x.y * x.y;
+    }
+    wg_sum<1>(n, lds);
+    if (threadIdx.x == 0) G.pn[((int64_t)rhs * (MG_IMAX + 1)) * G.nwg + blockIdx.x] = n[0];
+}
+
+// Arnoldi step j, pass 0: w = D_c (s_j v_j) into basis slot j + 1 and the partials of
+// <s_i v_i, w>, i <= j. s_j = 1 / |v_j| from the norm partials of v_j.
+__global__ __launch_bounds__(MG_CWG) void mg_capply_kernel(MgGmres G, int j) {
+    __shared__ double lds[(MG_CWG / 64) * 2 * MG_IMAX];
+    const int rhs = G.active[blockIdx.y];
+    const CoarseThread t = coarse_thread(G.K, G.Nd);
+    const int K = G.K;
+    const double nj = psum(G.pn + ((int64_t)rhs * (MG_IMAX + 1) + j) * G.nwg, G.nwg);
+    const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
+        const double hn = sqrt(nj > 0 ? nj : 0.0);
+        if (j == 0) {
+            G.beta[rhs] = hn;
+        } else {  // h_{j,j-1}
+            double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 1) * (MG_IMAX + 1);
+            Hc[2 * j] = hn;
+            Hc[2 * j + 1] = 0.0;
+        }
+    }
+    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
+    const float2 *vj = vb + (int64_t)j * G.vstride;
+    float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
+    double yr = 0, yi = 0;
+    if (t.act) {
+        int g[4];
+        block_coords(G.grid, t.b, g);
+        for (int d = 0; d < 9; ++d) {
+            const int64_t nb = mg_neighbour(G.grid, g, d);
+            const float2 *dcol = G.Dc + ((t.b * 9 + d) * K) * K + t.a;
+            const float2 *x = vj + nb * K;
+            for (int c = 0; c < K; ++c) {
+                const float2 m = dcol[(int64_t)c * K], xv = x[c];
+                yr += (double)m.x * xv.x - (double)m.y * xv.y;
+                yi += (double)m.x * xv.y + (double)m.y * xv.x;
+            }
+        }
+        yr *= sj;
+        yi *= sj;
+        w[t.b * K + t.a] = make_float2((float)yr, (float)yi);
+        yr = (double)(float)yr;  // the dot products see the stored vector
+        yi = (double)(float)yi;
+    }
+    double acc[2 * MG_IMAX];
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) {
+        acc[2 * i] = acc[2 * i + 1] = 0.0;
+        if (i <= j && t.act) {
+            const double si = i == j ? sj : G.sc[(int64_t)rhs * (MG_IMAX + 1) + i];
+            const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+            acc[2 * i] = si * ((double)v.x * yr + (double)v.y * yi);
+            acc[2 * i + 1] = si * ((double)v.x * yi - (double)v.y * yr);
+        }
+    }
+    double *pd = G.pd + ((int64_t)rhs * 2 + 0) * 2 * MG_IMAX * G.nwg;
+    wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd + blockIdx.x, G.nwg);
+}
+
+// Arnoldi step j, pass 1 (second Gram-Schmidt pass) and pass 2 (correction + norm):
+// w -= sum_i h_i s_i v_i with h from the previous pass's partials; then either the
+// partials of <s_i v_i, w> (pass 1) or of |w|^2 (pass 2). Workgroup 0 adds h into
+// column j of the Hessenberg matrix.
+__global__ __launch_bounds__(MG_CWG) void mg_cgs_kernel(MgGmres G, int j, int pass) {
+    __shared__ double lds[(MG_CWG / 64) * 2 * MG_IMAX];
+    __shared__ double h[2 * MG_IMAX];
+    const int rhs = G.active[blockIdx.y];
+    const CoarseThread t = coarse_thread(G.K, G.Nd);
+    const int K = G.K;
+    load_coefs(G, rhs, pass - 1, j, h);
+    if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
+        double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
+        const int i = threadIdx.x >> 1, ri = threadIdx.x & 1;
+        Hc[2 * i + ri] = (pass == 1 ? 0.0 : Hc[2 * i + ri]) + h[threadIdx.x];
+    }
+    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
+    float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
+    double yr = 0, yi = 0;
+    if (t.act) {
+        const float2 w0 = w[t.b * K + t.a];
+        yr = w0.x;
+        yi = w0.y;
+        for (int i = 0; i <= j; ++i) {
+            const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+            const double cr = h[2 * i] * sc[i], ci = h[2 * i + 1] * sc[i];
+            yr -= cr * v.x - ci * v.y;
+            yi -= cr * v.y + ci * v.x;
+        }
+        w[t.b * K + t.a] = make_float2((float)yr, (float)yi);
+        yr = (double)(float)yr;
+        yi = (double)(float)yi;
+    }
+    if (pass == 1) {
+        double acc[2 * MG_IMAX];
+#pragma unroll
+        for (int i = 0; i < MG_IMAX; ++i) {
+            acc[2 * i] = acc[2 * i + 1] = 0.0;
+            if (i <= j && t.act) {
+                const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+                acc[2 * i] = sc[i] * ((double)v.x * yr + (double)v.y * yi);
+                acc[2 * i + 1] = sc[i] * ((double)v.x * yi - (double)v.y * yr);
+            }
+        }
+        double *pd = G.pd + ((int64_t)rhs * 2 + 1) * 2 * MG_IMAX * G.nwg;
+        wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd + blockIdx.x, G.nwg);
+    } else {
+        double n[1] = {yr * yr + yi * yi};
+        wg_sum<1>(n, lds);
+        if (threadIdx.x == 0) G.pn[((int64_t)rhs * (MG_IMAX + 1) + j + 1) * G.nwg + blockIdx.x] = n[0];
+    }
+}
+
+// After k steps: h_{k,k-1} from the last norm partials, then min |beta e_1 - Hbar y| by
+// Givens rotations (one thread per system, FP64) and coef[i] = y_i s_i, so that the
+// coarse solution is sum_i coef[i] v_i over the stored (unnormalised) basis. A zero
+// diagonal after the rotations (exact breakdown) gives y_i = 0.
+__global__ void mg_cfinal_kernel(MgGmres G, int k) {
+    // one thread works; the small dense arrays live in LDS, not in per-lane memory
+    __shared__ double hr[MG_IMAX + 1][2];
+    __shared__ double cs[MG_IMAX], snr[MG_IMAX], sni[MG_IMAX];
+    __shared__ double gr[MG_IMAX + 1], gi[MG_IMAX + 1];
+    __shared__ double Rr[MG_IMAX][MG_IMAX], Ri[MG_IMAX][MG_IMAX];
+    __shared__ double yr[MG_IMAX], yi[MG_IMAX];
+    if (threadIdx.x != 0) return;
+    const int rhs = G.active[blockIdx.x];
+    const double nk = psum(G.pn + ((int64_t)rhs * (MG_IMAX + 1) + k) * G.nwg, G.nwg);
+    const double *Hm = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2;
+    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    for (int i = 0; i <= k; ++i) gr[i] = gi[i] = 0.0;
+    gr[0] = G.beta[rhs];
+    for (int col = 0; col < k; ++col) {
+        for (int i = 0; i <= col; ++i) {
+            hr[i][0] = Hm[2 * (col * (MG_IMAX + 1) + i)];
+            hr[i][1] = Hm[2 * (col * (MG_IMAX + 1) + i) + 1];
+        }
+        if (col + 1 < k) {
+            hr[col + 1][0] = Hm[2 * (col * (MG_IMAX + 1) + col + 1)];
+            hr[col + 1][1] = 0.0;
+        } else {
+            hr[col + 1][0] = sqrt(nk > 0 ? nk : 0.0);
+            hr[col + 1][1] = 0.0;
+        }
+        // earlier rotations: [x; y] <- [c x + s y; -conj(s) x + c y]
+        for (int i = 0; i < col; ++i) {
+            const double xr = hr[i][0], xi = hr[i][1], yr = hr[i + 1][0], yi = hr[i + 1][1];
+            hr[i][0] = cs[i] * xr + (snr[i] * yr - sni[i] * yi);
+            hr[i][1] = cs[i] * xi + (snr[i] * yi + sni[i] * yr);
+            hr[i + 1][0] = -(snr[i] * xr + sni[i] * xi) + cs[i] * yr;
+            hr[i + 1][1] = -(snr[i] * xi - sni[i] * xr) + cs[i] * yi;
+        }
+        // new rotation zeroing hr[col + 1]
+        const double ar = hr[col][0], ai = hr[col][1], br = hr[col + 1][0], bi = hr[col + 1][1];
+        const double na = sqrt(ar * ar + ai * ai), nb = sqrt(br * br + bi * bi);
+        double c, sr, si;
+        if (nb == 0.0) {
+            c = 1.0;
+            sr = si = 0.0;
+        } else if (na == 0.0) {
+            c = 0.0;
+            sr = br / nb;  // conj(b) / |b|
+            si = -bi / nb;
+        } else {
+            const double r = sqrt(na * na + nb * nb);
+            c = na / r;
+            // s = (a / |a|) conj(b) / r
+            const double ur = ar / na, ui = ai / na;
+            sr = (ur * br + ui * bi) / r;
+            si = (ui * br - ur * bi) / r;
+        }
+        cs[col] = c;
+        snr[col] = sr;
+        sni[col] = si;
+        const double xr = hr[col][0], xi = hr[col][1];
+        hr[col][0] = c * xr + (sr * br - si * bi);
+        hr[col][1] = c * xi + (sr * bi + si * br);
+        for (int i = 0; i <= col; ++i) {
+            Rr[i][col] = hr[i][0];
+            Ri[i][col] = hr[i][1];
+        }
+        const double g0r = gr[col], g0i = gi[col], g1r = gr[col + 1], g1i = gi[col + 1];
+        gr[col] = c * g0r + (sr * g1r - si * g1i);
+        gi[col] = c * g0i + (sr * g1i + si * g1r);
+        gr[col + 1] = -(sr * g0r + si * g0i) + c * g1r;
+        gi[col + 1] = -(sr * g0i - si * g0r) + c * g1i;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double tr = gr[i], ti = gi[i];
+        for (int q = i + 1; q < k; ++q) {
+            tr -= Rr[i][q] * yr[q] - Ri[i][q] * yi[q];
+            ti -= Rr[i][q] * yi[q] + Ri[i][q] * yr[q];
+        }
+        const double dr = Rr[i][i], di = Ri[i][i], dd = dr * dr + di * di;
+        if (dd > 0) {
+            yr[i] = (tr * dr + ti * di) / dd;
+            yi[i] = (ti * dr - tr * di) / dd;
+        } else {
+            yr[i] = yi[i] = 0.0;
+        }
+    }
+    double *cf = G.coef + (int64_t)rhs * 2 * MG_IMAX;
+    for (int i = 0; i < k; ++i) {
+        cf[2 * i] = yr[i] * sc[i];
+        cf[2 * i + 1] = yi[i] * sc[i];
+    }
+}
+
+hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    if (k < 1 || k > MG_IMAX || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)G.nwg, (unsigned)nact);
+    hipLaunchKernelGGL(mg_cinit_kernel, grid, dim3(MG_CWG), 0, st, G);
+    for (int j = 0; j < k; ++j) {
+        hipLaunchKernelGGL(mg_capply_kernel, grid, dim3(MG_CWG), 0, st, G, j);
+        hipLaunchKernelGGL(mg_cgs_kernel, grid, dim3(MG_CWG), 0, st, G, j, 1);
+        hipLaunchKernelGGL(mg_cgs_kernel, grid, dim3(MG_CWG), 0, st, G, j, 2);
+    }
+    hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
+    return hipGetLastError();
+}
+
+// out(rhs) = sum_{i < nb} coef(rhs)[i] basis(rhs)[i] as complex FP64 (out + rhs * ostride
+// doubles): the coarse solution itself, for callers that want it on the coarse grid.
+__global__ void mg_combine_kernel(MgGmres G, int nb, double *out, int64_t ostride) {
+    const int64_t n = G.Nd * G.K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int rhs = G.active[blockIdx.y];
+    const float2 *bs = G.basis + (int64_t)rhs * G.bstride + t;
+    const double *cf = G.coef + (int64_t)rhs * 2 * MG_IMAX;
+    double vr = 0, vi = 0;
+    for (int i = 0; i < nb; ++i) {
+        const float2 x = bs[(int64_t)i * G.vstride];
+        vr += cf[2 * i] * x.x - cf[2 * i + 1] * x.y;
+        vi += cf[2 * i] * x.y + cf[2 * i + 1] * x.x;
+    }
+    out[(int64_t)rhs * ostride + 2 * t] = vr;
+    out[(int64_t)rhs * ostride + 2 * t + 1] = vi;
+}
+
+hipError_t launch_mg_combine(const MgGmres &G, int nact, int nb, double *out, int64_t ostride, hipStream_t st) {
+    const int64_t n = G.Nd * G.K;
+    if (nact <= 0 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mg_combine_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0, st, G,
+                       nb, out, ostride);
+    return hipGetLastError();
+}
+
+// basis(rhs)[0] = in(rhs) rounded to FP32 (in: complex FP64 at in + rhs * istride).
+__global__ void mg_load_kernel(MgGmres G, const double *in, int64_t istride) {
+    const int64_t n = G.Nd * G.K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int rhs = G.active[blockIdx.y];
+    const double *x = in + (int64_t)rhs * istride + 2 * t;
+    G.basis[(int64_t)rhs * G.bstride + t] = make_float2((float)x[0], (float)x[1]);
+}
+
+hipError_t launch_mg_load(const MgGmres &G, int nact, const double *in, int64_t istride, hipStream_t st) {
+    const int64_t n = G.Nd * G.K;
+    if (nact <= 0 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mg_load_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0, st, G, in,
+                       istride);
+    return hipGetLastError();
+}
+
+}  // namespace sapdd

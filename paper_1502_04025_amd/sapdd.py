@@ -31,9 +31,11 @@ EXPORTS = (
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
     "sapdd_apply_block_D", "sapdd_sap", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
     "sapdd_profile", "sapdd_batch_create", "sapdd_batch_destroy", "sapdd_batch_add",
-    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_take",
+    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
+    "sapdd_mg_prolongator", "sapdd_mg_coarse_operator", "sapdd_mg_coarse_solve", "sapdd_mg_precond",
+    "sapdd_mg_solve", "sapdd_batch_set_mg",
 )
-KERNELS = ("sap_half", "dslash", "gram_schmidt", "block_dslash", "update", "copy")
+KERNELS = ("sap_half", "dslash", "gram_schmidt", "block_dslash", "update", "copy", "mg_fine", "mg_coarse")
 
 
 class SapddError(RuntimeError):
@@ -46,6 +48,11 @@ class Params(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("nmr", C.c_int), ("ncy", C.c_int), ("restart", C.c_int),
                 ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int),
                 ("deflate", C.c_int)]
+
+
+class MgParams(C.Structure):
+    _fields_ = [("nvec", C.c_int), ("setup_iters", C.c_int), ("coarse_iters", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class KernelProfile(C.Structure):
@@ -105,6 +112,14 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_batch_step.argtypes = [VP, P(I)]
     lib.sapdd_batch_poll.argtypes = [VP, I, P(Stats)]
     lib.sapdd_batch_take.argtypes = [VP, I, VP, I, P(Stats)]
+    lib.sapdd_mg_setup.argtypes = [VP, VP, D, P(Params), P(MgParams), VP, I, P(VP)]
+    lib.sapdd_mg_destroy.argtypes = [VP]
+    lib.sapdd_mg_prolongator.argtypes = [VP, VP, I]
+    lib.sapdd_mg_coarse_operator.argtypes = [VP, VP, I]
+    lib.sapdd_mg_coarse_solve.argtypes = [VP, I, VP, VP, I]
+    lib.sapdd_mg_precond.argtypes = [VP, I, VP, VP, I]
+    lib.sapdd_mg_solve.argtypes = [VP, P(Params), I, VP, VP, P(Stats)]
+    lib.sapdd_batch_set_mg.argtypes = [VP, VP]
     for name in EXPORTS:
         if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint"):
             getattr(lib, name).restype = I
@@ -349,6 +364,12 @@ class Batch:
             raise SapddError(rc, "bad slot")
         return bool(rc), st.as_dict()
 
+    def set_mg(self, mg: "Multigrid"):
+        """Precondition with the two-level multigrid instead of SAP (no slot in use; every
+        right-hand side added later must use the multigrid's kappa)."""
+        self.ctx._check(self.ctx.lib.sapdd_batch_set_mg(self.h, mg.h))
+        self.mg = mg  # keeps the multigrid alive as long as the batch
+
     def take(self, slot: int, out):
         """Copy the solution of a slot into `out` (host array or device tensor), free it."""
         po, dev = _ptr(out, writable=True)
@@ -356,3 +377,91 @@ class Batch:
         self.ctx._check(self.ctx.lib.sapdd_batch_take(self.h, int(slot), po, DEVICE_PTRS if dev else 0,
                                                       C.byref(st)))
         return st.as_dict()
+
+
+class Multigrid:
+    """Two-level multigrid preconditioner with SAP as smoother (sapdd_mg_*), for one field
+    and kappa. vecs: the nvec test vectors (canonical spinors [nvec,t,z,y,x,4,3]);
+    smoother keywords (nmr, ncy, prec) as Field.params."""
+
+    def __init__(self, field: "Field", kappa: float, vecs, setup_iters=0, coarse_iters=16, **smoother):
+        self.field, self.ctx, self.kappa = field, field.ctx, float(kappa)
+        self.nvec = int(vecs.shape[0])
+        self.K = 2 * self.nvec
+        self.grid = tuple(field.dims[mu] // field.block[mu] for mu in range(4))  # x, y, z, t
+        prm = field.params(**smoother)
+        mp = MgParams(self.nvec, int(setup_iters), int(coarse_iters), 0)
+        pv, dev = _ptr(vecs)
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.sapdd_mg_setup(self.ctx.h, field.h, self.kappa, C.byref(prm), C.byref(mp), pv,
+                                                    DEVICE_PTRS if dev else 0, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sapdd_mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.ctx.h:
+                self.close()
+        except Exception:
+            pass
+
+    def _coarse_shape(self):
+        gx, gy, gz, gt = self.grid
+        return (gt, gz, gy, gx)
+
+    def prolongator(self):
+        """The nvec interpolation fields as canonical spinors (host array)."""
+        lx, ly, lz, lt = self.field.dims
+        out = np.empty((self.nvec, lt, lz, ly, lx, 4, 3), dtype=np.complex128)
+        po, _ = _ptr(out, writable=True)
+        self.ctx._check(self.ctx.lib.sapdd_mg_prolongator(self.h, po, 0))
+        return out
+
+    def coarse_operator(self):
+        """D_c as [Gt,Gz,Gy,Gx,9,K,K] (block d: 0 itself, 1 + 2 mu forward, 2 + 2 mu
+        backward neighbour; row, column)."""
+        out = np.empty(self._coarse_shape() + (9, self.K, self.K), dtype=np.complex128)
+        po, _ = _ptr(out, writable=True)
+        self.ctx._check(self.ctx.lib.sapdd_mg_coarse_operator(self.h, po, 0))
+        return out
+
+    def coarse_solve(self, rhs):
+        """coarse_iters GMRES steps from zero on D_c e = rhs, rhs [n,Gt,Gz,Gy,Gx,K]."""
+        rhs = np.ascontiguousarray(rhs, dtype=np.complex128)
+        out = np.empty_like(rhs)
+        pi, _ = _ptr(rhs)
+        po, _ = _ptr(out, writable=True)
+        self.ctx._check(self.ctx.lib.sapdd_mg_coarse_solve(self.h, int(rhs.shape[0]), pi, po, 0))
+        return out
+
+    def precond(self, psi, out=None):
+        """B(psi) for canonical spinors [nrhs,t,z,y,x,4,3]."""
+        out = _empty_like(psi) if out is None else out
+        pi, dev = _ptr(psi)
+        po, _ = _ptr(out, writable=True)
+        self.ctx._check(self.ctx.lib.sapdd_mg_precond(self.h, Field._nrhs(psi), pi, po, DEVICE_PTRS if dev else 0))
+        return out
+
+    def solve(self, b, x=None, x0=None, raise_on_noconv=True, **kw) -> SolveResult:
+        """Solve M x = b with FGMRES preconditioned by the multigrid cycle; solver and
+        smoother keywords as Field.params."""
+        nrhs = Field._nrhs(b)
+        prm = self.field.params(**kw)
+        if x is None:
+            x = _empty_like(b)
+        if x0 is not None:
+            x[...] = x0
+            prm.flags |= USE_X0
+        pb, dev = _ptr(b)
+        px, _ = _ptr(x, writable=True)
+        if dev:
+            prm.flags |= DEVICE_PTRS
+        stats = (Stats * nrhs)()
+        rc = self.ctx.lib.sapdd_mg_solve(self.h, C.byref(prm), nrhs, pb, px, stats)
+        if rc != OK and not (rc == ENOCONV and not raise_on_noconv):
+            self.ctx._check(rc)
+        return SolveResult(x, [s.as_dict() for s in stats], rc)

@@ -35,20 +35,25 @@ def test_params_struct_matches_header_layout(tmp_path):
     structs."""
     fields_p = [f for f, _ in sapdd.Params._fields_]
     fields_s = [f for f, _ in sapdd.Stats._fields_]
+    fields_m = [f for f, _ in sapdd.MgParams._fields_]
     src = tmp_path / "layout.c"
     src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"sapdd.h\"\nint main(void) {\n"
-                   + f'  printf("%zu %zu\\n", sizeof(sapdd_params), sizeof(sapdd_stats));\n'
+                   + f'  printf("%zu %zu %zu\\n", sizeof(sapdd_params), sizeof(sapdd_stats), sizeof(sapdd_mg_params));\n'
                    + "".join(f'  printf("%zu\\n", offsetof(sapdd_params, {f}));\n' for f in fields_p)
                    + "".join(f'  printf("%zu\\n", offsetof(sapdd_stats, {f}));\n' for f in fields_s)
+                   + "".join(f'  printf("%zu\\n", offsetof(sapdd_mg_params, {f}));\n' for f in fields_m)
                    + "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert int(out[0]) == ctypes.sizeof(sapdd.Params)
     assert int(out[1]) == ctypes.sizeof(sapdd.Stats)
-    offs = [int(v) for v in out[2:]]
-    assert offs[:len(fields_p)] == [getattr(sapdd.Params, f).offset for f in fields_p]
-    assert offs[len(fields_p):] == [getattr(sapdd.Stats, f).offset for f in fields_s]
+    assert int(out[2]) == ctypes.sizeof(sapdd.MgParams)
+    offs = [int(v) for v in out[3:]]
+    n_p, n_s = len(fields_p), len(fields_s)
+    assert offs[:n_p] == [getattr(sapdd.Params, f).offset for f in fields_p]
+    assert offs[n_p:n_p + n_s] == [getattr(sapdd.Stats, f).offset for f in fields_s]
+    assert offs[n_p + n_s:] == [getattr(sapdd.MgParams, f).offset for f in fields_m]
 
 
 def test_product_path_does_not_import_the_oracle():
