@@ -119,6 +119,8 @@ int sapdd_compute_clover(sapdd_ctx *ctx, sapdd_field *field, double csw);
 /* Upload T(x) (canonical clover layout). Only the two chiral 6x6 blocks (spins 0-1 and
  * 2-3) are used; the entries coupling them must be zero in the Dirac basis above. */
 int sapdd_load_clover(sapdd_ctx *ctx, sapdd_field *field, const double *clover, int flags);
+/* Free a field. The context's kept sapdd_solve batch on it goes with it; batches and
+ * multigrid objects the caller made on the field must be destroyed first. */
 int sapdd_free_field(sapdd_ctx *ctx, sapdd_field *field);
 
 /* out = M in for nrhs canonical spinors, with links, clover and spinors held in storage

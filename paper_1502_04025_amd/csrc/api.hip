@@ -54,6 +54,9 @@ struct sapdd_field {
     std::vector<XEntry> xcache;
     unsigned long long use_clock = 0;
     double csw = 0.0;
+    // unique per loaded field: a kept batch is reused only for the very field it was
+    // built on, never for a later field that happens to get the same address
+    unsigned long long id = 0;
 };
 
 struct sapdd_ctx {
@@ -487,6 +490,8 @@ int sapdd_load_gauge(sapdd_ctx *c, const int dims[4], const int block[4], const 
     g.antiperiodic = antiperiodic_t ? 1 : 0;
     if ((g.Nd / 2) > 0x7fffffffLL || g.V * 24 > (1LL << 40)) return fail(c, SAPDD_EINVAL, "lattice too large");
     sapdd_field *f = new sapdd_field;
+    static unsigned long long next_field_id = 0;
+    f->id = ++next_field_id;
     f->geo = g;
     hipError_t e1 = hipMalloc((void **)&f->links64, (size_t)g.V * 72 * 8);
     hipError_t e2 = e1 == hipSuccess ? hipMalloc((void **)&f->tclov64, (size_t)g.V * 72 * 8) : e1;
@@ -547,11 +552,19 @@ int sapdd_load_clover(sapdd_ctx *c, sapdd_field *f, const double *clover, int fl
     return SAPDD_OK;
 }
 
+}  // extern "C"
+static const sapdd_field *batch_field(const sapdd_batch *B);
+extern "C" {
+
 int sapdd_free_field(sapdd_ctx *c, sapdd_field *f) {
     if (!f) return SAPDD_OK;
     if (c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
+    }
+    if (c && c->solve_batch && batch_field(c->solve_batch) == f) {  // the kept batch holds this field's buffers
+        sapdd_batch_destroy(c->solve_batch);
+        c->solve_batch = nullptr;
     }
     drop_derived(f);
     if (f->links64) (void)hipFree(f->links64);
@@ -717,7 +730,7 @@ namespace {
 
 // Workspace of one multigrid application for `cap` systems (indexed by rhs).
 struct MgWork {
-    int cap = 0, nwg = 0;
+    int cap = 0, nwa = 0, nwc = 0, pstride = 0;
     double *t1 = nullptr, *t2 = nullptr;  // FP64 fields: interpolated coarse solution, residual
     float2 *cb = nullptr;                 // coarse Krylov bases
     double *pn = nullptr, *pd = nullptr, *H = nullptr, *sc = nullptr, *beta = nullptr, *coef = nullptr;
@@ -728,7 +741,8 @@ int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
     const Geom &g = mg->f->geo;
     const size_t nc = (size_t)g.Nd * mg->K;
     w->cap = cap;
-    w->nwg = mg_coarse_wgs(g, mg->K);
+    mg_coarse_tiling(g, mg->K, &w->nwa, &w->nwc);
+    w->pstride = std::max(w->nwa, w->nwc);
     void *q;
     CHK(alloc("mg_t1", (size_t)cap * g.V * 24 * 8, &q));
     w->t1 = (double *)q;
@@ -736,9 +750,9 @@ int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
     w->t2 = (double *)q;
     CHK(alloc("mg_cb", (size_t)cap * (MG_IMAX + 1) * nc * sizeof(float2), &q));
     w->cb = (float2 *)q;
-    CHK(alloc("mg_pn", (size_t)cap * (MG_IMAX + 1) * w->nwg * 8, &q));
+    CHK(alloc("mg_pn", (size_t)cap * (MG_IMAX + 1) * w->pstride * 8, &q));
     w->pn = (double *)q;
-    CHK(alloc("mg_pd", (size_t)cap * 4 * MG_IMAX * w->nwg * 8, &q));
+    CHK(alloc("mg_pd", (size_t)cap * 4 * MG_IMAX * w->pstride * 8, &q));
     w->pd = (double *)q;
     CHK(alloc("mg_H", (size_t)cap * (MG_IMAX + 1) * MG_IMAX * 16, &q));
     w->H = (double *)q;
@@ -758,7 +772,9 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     G.K = mg->K;
     for (int mu = 0; mu < 4; ++mu) G.grid[mu] = g.G[mu];
     G.Nd = g.Nd;
-    G.nwg = w.nwg;
+    G.nwa = w.nwa;
+    G.nwc = w.nwc;
+    G.pstride = w.pstride;
     G.basis = w.cb;
     G.vstride = g.Nd * mg->K;
     G.bstride = (MG_IMAX + 1) * G.vstride;
@@ -842,6 +858,7 @@ enum { SEG_CHECK = 0, SEG_CHECK2 = 1, SEG_CYCLE = 2, SEG_DEFL = 3, SEG_GROUP = 4
 struct sapdd_batch {
     sapdd_ctx *c = nullptr;
     sapdd_field *f = nullptr;
+    unsigned long long f_id = 0;  // the field's id at creation
     sapdd_params p{};
     int cap = 0, m = 0, k = 0, prec = 0, zprec = 0;
     Geom g{};
@@ -864,6 +881,8 @@ struct sapdd_batch {
     sapdd_mg *mg = nullptr;  // multigrid preconditioner in place of SAP (sapdd_batch_set_mg)
     MgWork mw{};
 };
+
+static const sapdd_field *batch_field(const sapdd_batch *B) { return B->f; }
 
 namespace {
 
@@ -1346,7 +1365,7 @@ void batch_free(sapdd_batch *B) {
 // A batch kept between solve calls serves a new call with the same field, shape and
 // solver parameters (tolerance and iteration cap are per call).
 bool batch_reusable(const sapdd_batch *B, const sapdd_field *f, const sapdd_params *p, int nrhs) {
-    return B && B->f == f && B->cap >= nrhs && B->p.restart == p->restart && B->p.nmr == p->nmr &&
+    return B && B->f == f && B->f_id == f->id && B->cap >= nrhs && B->p.restart == p->restart && B->p.nmr == p->nmr &&
            B->p.ncy == p->ncy && B->p.sap_prec == p->sap_prec && B->p.deflate == p->deflate &&
            ((B->p.flags ^ p->flags) & SAPDD_NO_GRAPH) == 0;
 }
@@ -1384,6 +1403,7 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     sapdd_batch *B = new sapdd_batch;
     B->c = c;
     B->f = f;
+    B->f_id = f->id;
     B->p = *p;
     B->cap = cap;
     B->m = p->restart;

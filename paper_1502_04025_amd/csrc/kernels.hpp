@@ -166,18 +166,19 @@ struct MgGmres {
     int K;             // 2 nvec
     int grid[4];       // block grid
     int64_t Nd;        // aggregates
-    int nwg;           // workgroups per system (mg_coarse_wgs)
+    int nwa, nwc;      // workgroups per system of the operator and Gram-Schmidt kernels
+    int pstride;       // partials stride per value (>= nwa, nwc)
     float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride; slot 0 = rhs
     int64_t bstride, vstride;
-    double *pn;        // [rhs][MG_IMAX + 1][nwg] |v_i|^2 partials
-    double *pd;        // [rhs][2][2 MG_IMAX][nwg] Gram-Schmidt partials
+    double *pn;        // [rhs][MG_IMAX + 1][pstride] |v_i|^2 partials
+    double *pd;        // [rhs][2][2 MG_IMAX][pstride] Gram-Schmidt partials
     double *H;         // [rhs][MG_IMAX][MG_IMAX + 1] complex, column-major Hessenberg
     double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
     double *beta;      // [rhs] |rhs|
     double *coef;      // [rhs][MG_IMAX] complex: solution = sum_i coef[i] basis[i]
     const int *active;
 };
-int mg_coarse_wgs(const Geom &geo, int K);
+void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc);
 // k GMRES steps from zero on D_c e = basis[0] for every listed system; the solution's
 // coefficients over the stored basis go to coef.
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st);

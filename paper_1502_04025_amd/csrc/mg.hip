@@ -428,92 +428,117 @@ hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double 
 
 // ---------------------------------------------------------------- coarse GMRES
 
-// Workgroup tiling of the coarse kernels: TB aggregates of K rows each per workgroup.
-int mg_coarse_tile(int K) { return MG_CWG / K; }
-int mg_coarse_wgs(const Geom &geo, int K) {
-    const int tb = mg_coarse_tile(K);
-    return (int)((geo.Nd + tb - 1) / tb);
+// Workgroup tiling of the coarse kernels. The operator kernel gives every aggregate's K
+// rows eight threads each (one per neighbour group: the aggregate itself and its
+// backward t neighbour, then one neighbour each), 256 threads for 32 / K aggregates, so
+// the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. The
+// Gram-Schmidt kernels take 256 / K aggregates per 256-thread workgroup: every one of
+// their workgroups re-sums all partials of the previous kernel, so their count is kept
+// small (their re-reads grow as the product of both counts).
+constexpr int MG_AWG = 256, MG_ALANES = 32, MG_GWG = 256;
+void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc) {
+    const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    *nwa = (int)((geo.Nd + ta - 1) / ta);
+    *nwc = (int)((geo.Nd + tc - 1) / tc);
 }
 
 namespace {
 
-struct CoarseThread {
-    int64_t b;
-    int a;
-    bool act;
-};
-__device__ __forceinline__ CoarseThread coarse_thread(int K, int64_t Nd) {
-    const int tb = MG_CWG / K;
-    const int bl = threadIdx.x / K;
-    CoarseThread t;
-    t.a = threadIdx.x - bl * K;
-    t.b = (int64_t)blockIdx.x * tb + bl;
-    t.act = bl < tb && t.b < Nd;
-    return t;
-}
-
-// sum over nwg partials of value k (fixed order)
-__device__ __forceinline__ double psum(const double *part, int nwg) {
+// Sum of value v over n partials (stride 1) by one wave in a fixed order: lane l adds
+// partials l, l + 64, ..., then a butterfly over the lanes; every lane gets the total.
+__device__ __forceinline__ double wave_sum_parts(const double *part, int n) {
+    const int lane = threadIdx.x & 63;
     double t = 0;
-    for (int q = 0; q < nwg; ++q) t += part[q];
+    for (int q = lane; q < n; q += 64) t += part[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     return t;
 }
 
-// The coarse sums of one pass: h[i] (complex, i <= j) into LDS, every thread reading
-// the partials of pass `pass` in workgroup order.
-__device__ __forceinline__ void load_coefs(const MgGmres &G, int rhs, int pass, int j, double *h) {
-    const double *pd = G.pd + ((int64_t)rhs * 2 + pass) * 2 * MG_IMAX * G.nwg;
-    for (int t = threadIdx.x; t < 2 * (j + 1); t += blockDim.x) h[t] = psum(pd + (int64_t)t * G.nwg, G.nwg);
+// The totals of nval <= 2 MG_IMAX values (value v's n partials at part + v * pstride)
+// into h[v] in LDS in a fixed order: value v by wave v mod 4 (blockDim.x = 256), whose
+// lane l adds partials l, l + 64, ... (all of the wave's loads in flight together), then
+// one butterfly per value; then a barrier.
+__device__ __forceinline__ void load_totals(const double *part, int64_t pstride, int n, int nval, double *h) {
+    constexpr int NW = MG_GWG / 64, PER = (2 * MG_IMAX + NW - 1) / NW;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double acc[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+    for (int q = lane; q < n; q += 64)
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (w + NW * u < nval) acc[u] += part[(int64_t)(w + NW * u) * pstride + q];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (w + NW * u < nval) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+            if (lane == 0) h[w + NW * u] = acc[u];
+        }
     __syncthreads();
+}
+
+// Wave-level fixed-order sums of N values, written by lane 0 of the wave to
+// out[k * stride] for k < nval.
+template <int N>
+__device__ __forceinline__ void wave_store(double (&v)[N], int nval, double *out, int64_t stride) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k < nval)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k < nval) out[(int64_t)k * stride] = v[k];
+}
+
+__device__ __forceinline__ double *pd_of(const MgGmres &G, int rhs, int pass) {
+    return G.pd + ((int64_t)rhs * 2 + pass) * 2 * MG_IMAX * G.pstride;
+}
+__device__ __forceinline__ double *pn_of(const MgGmres &G, int rhs, int i) {
+    return G.pn + ((int64_t)rhs * (MG_IMAX + 1) + i) * G.pstride;
 }
 
 }  // namespace
 
 // |v_0|^2 partials of every listed system (v_0 = the restricted right-hand side).
-__global__ __launch_bounds__(MG_CWG) void mg_cinit_kernel(MgGmres G) {
-    __shared__ double lds[MG_CWG / 64];
+__global__ __launch_bounds__(MG_GWG) void mg_cinit_kernel(MgGmres G) {
     const int rhs = G.active[blockIdx.y];
-    const CoarseThread t = coarse_thread(G.K, G.Nd);
-    const float2 *v0 = G.basis + (int64_t)rhs * G.bstride;
+    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * tc + bl;
+    __shared__ double lds[MG_GWG / 64];
     double n[1] = {0.0};
-    if (t.act) {
-        const float2 x = v0[t.b * G.K + t.a];
+    if (bl < tc && b < G.Nd) {
+        const float2 x = G.basis[(int64_t)rhs * G.bstride + b * K + a];
         n[0] = (double)x.x * x.x + (double)x.y * x.y;
     }
-    wg_sum<1>(n, lds);
-    if (threadIdx.x == 0) G.pn[((int64_t)rhs * (MG_IMAX + 1)) * G.nwg + blockIdx.x] = n[0];
+    wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, 0) + blockIdx.x, 1);
 }
 
 // Arnoldi step j, pass 0: w = D_c (s_j v_j) into basis slot j + 1 and the partials of
 // <s_i v_i, w>, i <= j. s_j = 1 / |v_j| from the norm partials of v_j.
-__global__ __launch_bounds__(MG_CWG) void mg_capply_kernel(MgGmres G, int j) {
-    __shared__ double lds[(MG_CWG / 64) * 2 * MG_IMAX];
+__global__ __launch_bounds__(MG_AWG) void mg_capply_kernel(MgGmres G, int j) {
+    __shared__ double ys[2][8][MG_ALANES];
+    __shared__ double hn[1];
     const int rhs = G.active[blockIdx.y];
-    const CoarseThread t = coarse_thread(G.K, G.Nd);
-    const int K = G.K;
-    const double nj = psum(G.pn + ((int64_t)rhs * (MG_IMAX + 1) + j) * G.nwg, G.nwg);
-    const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
-        const double hn = sqrt(nj > 0 ? nj : 0.0);
-        if (j == 0) {
-            G.beta[rhs] = hn;
-        } else {  // h_{j,j-1}
-            double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 1) * (MG_IMAX + 1);
-            Hc[2 * j] = hn;
-            Hc[2 * j + 1] = 0.0;
-        }
-    }
+    const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
+    const int dg = threadIdx.x / MG_ALANES, r = threadIdx.x % MG_ALANES;
+    const int bl = r / K, a = r - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * ta + bl;
+    const bool act = bl < ta && b < G.Nd;
     const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
     const float2 *vj = vb + (int64_t)j * G.vstride;
     float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
-    double yr = 0, yi = 0;
-    if (t.act) {
+    double yr = 0, yi = 0;  // (D_c v_j) row a of aggregate b, this thread's neighbour group
+    if (act) {
         int g[4];
-        block_coords(G.grid, t.b, g);
-        for (int d = 0; d < 9; ++d) {
+        block_coords(G.grid, b, g);
+        for (int d = dg; d < 9; d += 8) {
             const int64_t nb = mg_neighbour(G.grid, g, d);
-            const float2 *dcol = G.Dc + ((t.b * 9 + d) * K) * K + t.a;
+            const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
             const float2 *x = vj + nb * K;
             for (int c = 0; c < K; ++c) {
                 const float2 m = dcol[(int64_t)c * K], xv = x[c];
@@ -521,9 +546,41 @@ __global__ __launch_bounds__(MG_CWG) void mg_capply_kernel(MgGmres G, int j) {
                 yi += (double)m.x * xv.y + (double)m.y * xv.x;
             }
         }
+    }
+    ys[0][dg][r] = yr;
+    ys[1][dg][r] = yi;
+    if (threadIdx.x < 64) {  // |v_j|^2, while the other waves finish their rows
+        const double t = wave_sum_parts(pn_of(G, rhs, j), G.nwc);
+        if (threadIdx.x == 0) hn[0] = t;
+    }
+    __syncthreads();
+    const double nj = hn[0];
+    const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
+        const double h = sqrt(nj > 0 ? nj : 0.0);
+        if (j == 0) {
+            G.beta[rhs] = h;
+        } else {  // h_{j,j-1}
+            double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 1) * (MG_IMAX + 1);
+            Hc[2 * j] = h;
+            Hc[2 * j + 1] = 0.0;
+        }
+    }
+    // wave 0 finishes the aggregate(s): its lanes < 32 own the rows, lanes 32..63 add
+    // zeros to the wave sums (every lane of the wave must take part in the shuffles)
+    if (threadIdx.x >= 64) return;
+    const bool own = dg == 0 && act;
+    yr = yi = 0;
+    if (own) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            yr += ys[0][q][r];
+            yi += ys[1][q][r];
+        }
         yr *= sj;
         yi *= sj;
-        w[t.b * K + t.a] = make_float2((float)yr, (float)yi);
+        w[b * K + a] = make_float2((float)yr, (float)yi);
         yr = (double)(float)yr;  // the dot products see the stored vector
         yi = (double)(float)yi;
     }
@@ -531,48 +588,48 @@ __global__ __launch_bounds__(MG_CWG) void mg_capply_kernel(MgGmres G, int j) {
 #pragma unroll
     for (int i = 0; i < MG_IMAX; ++i) {
         acc[2 * i] = acc[2 * i + 1] = 0.0;
-        if (i <= j && t.act) {
+        if (i <= j && own) {
             const double si = i == j ? sj : G.sc[(int64_t)rhs * (MG_IMAX + 1) + i];
-            const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+            const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
             acc[2 * i] = si * ((double)v.x * yr + (double)v.y * yi);
             acc[2 * i + 1] = si * ((double)v.x * yi - (double)v.y * yr);
         }
     }
-    double *pd = G.pd + ((int64_t)rhs * 2 + 0) * 2 * MG_IMAX * G.nwg;
-    wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd + blockIdx.x, G.nwg);
+    wave_store<2 * MG_IMAX>(acc, 2 * (j + 1), pd_of(G, rhs, 0) + blockIdx.x, G.pstride);
 }
 
 // Arnoldi step j, pass 1 (second Gram-Schmidt pass) and pass 2 (correction + norm):
 // w -= sum_i h_i s_i v_i with h from the previous pass's partials; then either the
 // partials of <s_i v_i, w> (pass 1) or of |w|^2 (pass 2). Workgroup 0 adds h into
 // column j of the Hessenberg matrix.
-__global__ __launch_bounds__(MG_CWG) void mg_cgs_kernel(MgGmres G, int j, int pass) {
-    __shared__ double lds[(MG_CWG / 64) * 2 * MG_IMAX];
+__global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int pass) {
     __shared__ double h[2 * MG_IMAX];
+    __shared__ double lds[(MG_GWG / 64) * 2 * MG_IMAX];
     const int rhs = G.active[blockIdx.y];
-    const CoarseThread t = coarse_thread(G.K, G.Nd);
-    const int K = G.K;
-    load_coefs(G, rhs, pass - 1, j, h);
+    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * tc + bl;
+    const bool act = bl < tc && b < G.Nd;
+    load_totals(pd_of(G, rhs, pass - 1), G.pstride, pass == 1 ? G.nwa : G.nwc, 2 * (j + 1), h);
     if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
         double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
-        const int i = threadIdx.x >> 1, ri = threadIdx.x & 1;
-        Hc[2 * i + ri] = (pass == 1 ? 0.0 : Hc[2 * i + ri]) + h[threadIdx.x];
+        Hc[threadIdx.x] = (pass == 1 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x];
     }
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
     float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
     double yr = 0, yi = 0;
-    if (t.act) {
-        const float2 w0 = w[t.b * K + t.a];
+    if (act) {
+        const float2 w0 = w[b * K + a];
         yr = w0.x;
         yi = w0.y;
         for (int i = 0; i <= j; ++i) {
-            const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+            const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
             const double cr = h[2 * i] * sc[i], ci = h[2 * i + 1] * sc[i];
             yr -= cr * v.x - ci * v.y;
             yi -= cr * v.y + ci * v.x;
         }
-        w[t.b * K + t.a] = make_float2((float)yr, (float)yi);
+        w[b * K + a] = make_float2((float)yr, (float)yi);
         yr = (double)(float)yr;
         yi = (double)(float)yi;
     }
@@ -581,124 +638,120 @@ __global__ __launch_bounds__(MG_CWG) void mg_cgs_kernel(MgGmres G, int j, int pa
 #pragma unroll
         for (int i = 0; i < MG_IMAX; ++i) {
             acc[2 * i] = acc[2 * i + 1] = 0.0;
-            if (i <= j && t.act) {
-                const float2 v = vb[(int64_t)i * G.vstride + t.b * K + t.a];
+            if (i <= j && act) {
+                const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
                 acc[2 * i] = sc[i] * ((double)v.x * yr + (double)v.y * yi);
                 acc[2 * i + 1] = sc[i] * ((double)v.x * yi - (double)v.y * yr);
             }
         }
-        double *pd = G.pd + ((int64_t)rhs * 2 + 1) * 2 * MG_IMAX * G.nwg;
-        wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd + blockIdx.x, G.nwg);
+        wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd_of(G, rhs, 1) + blockIdx.x, G.pstride);
     } else {
         double n[1] = {yr * yr + yi * yi};
-        wg_sum<1>(n, lds);
-        if (threadIdx.x == 0) G.pn[((int64_t)rhs * (MG_IMAX + 1) + j + 1) * G.nwg + blockIdx.x] = n[0];
+        wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, j + 1) + blockIdx.x, 1);
     }
 }
 
-// After k steps: h_{k,k-1} from the last norm partials, then min |beta e_1 - Hbar y| by
-// Givens rotations (one thread per system, FP64) and coef[i] = y_i s_i, so that the
-// coarse solution is sum_i coef[i] v_i over the stored (unnormalised) basis. A zero
-// diagonal after the rotations (exact breakdown) gives y_i = 0.
-__global__ void mg_cfinal_kernel(MgGmres G, int k) {
-    // one thread works; the small dense arrays live in LDS, not in per-lane memory
-    __shared__ double hr[MG_IMAX + 1][2];
-    __shared__ double cs[MG_IMAX], snr[MG_IMAX], sni[MG_IMAX];
-    __shared__ double gr[MG_IMAX + 1], gi[MG_IMAX + 1];
-    __shared__ double Rr[MG_IMAX][MG_IMAX], Ri[MG_IMAX][MG_IMAX];
-    __shared__ double yr[MG_IMAX], yi[MG_IMAX];
-    if (threadIdx.x != 0) return;
+// After k steps, one wave per system: h_{k,k-1} from the last norm partials, then
+// min |beta e_1 - Hbar y| by Givens rotations with lane c holding column c of Hbar (each
+// rotation is broadcast from the lane of its column and applied by all lanes), back
+// substitution with a lane sum per row, and coef[i] = y_i s_i, so that the coarse
+// solution is sum_i coef[i] v_i over the stored (unnormalised) basis. A zero diagonal
+// after the rotations (exact breakdown) gives y_i = 0.
+__global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
     const int rhs = G.active[blockIdx.x];
-    const double nk = psum(G.pn + ((int64_t)rhs * (MG_IMAX + 1) + k) * G.nwg, G.nwg);
+    const int lane = threadIdx.x;
+    const double nk = wave_sum_parts(pn_of(G, rhs, k), G.nwc);
     const double *Hm = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2;
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
-    for (int i = 0; i <= k; ++i) gr[i] = gi[i] = 0.0;
+    double hr[MG_IMAX + 1], hi[MG_IMAX + 1];  // column `lane` of Hbar, rows 0..MG_IMAX
+#pragma unroll
+    for (int r = 0; r <= MG_IMAX; ++r) {
+        hr[r] = hi[r] = 0.0;
+        if (lane < k && r <= lane) {
+            hr[r] = Hm[2 * (lane * (MG_IMAX + 1) + r)];
+            hi[r] = Hm[2 * (lane * (MG_IMAX + 1) + r) + 1];
+        } else if (lane < k && r == lane + 1) {
+            hr[r] = lane + 1 < k ? Hm[2 * (lane * (MG_IMAX + 1) + r)] : sqrt(nk > 0 ? nk : 0.0);
+        }
+    }
+    double gr[MG_IMAX + 1], gi[MG_IMAX + 1];
+#pragma unroll
+    for (int r = 0; r <= MG_IMAX; ++r) gr[r] = gi[r] = 0.0;
     gr[0] = G.beta[rhs];
-    for (int col = 0; col < k; ++col) {
-        for (int i = 0; i <= col; ++i) {
-            hr[i][0] = Hm[2 * (col * (MG_IMAX + 1) + i)];
-            hr[i][1] = Hm[2 * (col * (MG_IMAX + 1) + i) + 1];
-        }
-        if (col + 1 < k) {
-            hr[col + 1][0] = Hm[2 * (col * (MG_IMAX + 1) + col + 1)];
-            hr[col + 1][1] = 0.0;
-        } else {
-            hr[col + 1][0] = sqrt(nk > 0 ? nk : 0.0);
-            hr[col + 1][1] = 0.0;
-        }
-        // earlier rotations: [x; y] <- [c x + s y; -conj(s) x + c y]
-        for (int i = 0; i < col; ++i) {
-            const double xr = hr[i][0], xi = hr[i][1], yr = hr[i + 1][0], yi = hr[i + 1][1];
-            hr[i][0] = cs[i] * xr + (snr[i] * yr - sni[i] * yi);
-            hr[i][1] = cs[i] * xi + (snr[i] * yi + sni[i] * yr);
-            hr[i + 1][0] = -(snr[i] * xr + sni[i] * xi) + cs[i] * yr;
-            hr[i + 1][1] = -(snr[i] * xi - sni[i] * xr) + cs[i] * yi;
-        }
-        // new rotation zeroing hr[col + 1]
-        const double ar = hr[col][0], ai = hr[col][1], br = hr[col + 1][0], bi = hr[col + 1][1];
-        const double na = sqrt(ar * ar + ai * ai), nb = sqrt(br * br + bi * bi);
-        double c, sr, si;
-        if (nb == 0.0) {
-            c = 1.0;
-            sr = si = 0.0;
-        } else if (na == 0.0) {
-            c = 0.0;
-            sr = br / nb;  // conj(b) / |b|
-            si = -bi / nb;
-        } else {
-            const double r = sqrt(na * na + nb * nb);
-            c = na / r;
-            // s = (a / |a|) conj(b) / r
-            const double ur = ar / na, ui = ai / na;
-            sr = (ur * br + ui * bi) / r;
-            si = (ui * br - ur * bi) / r;
-        }
-        cs[col] = c;
-        snr[col] = sr;
-        sni[col] = si;
-        const double xr = hr[col][0], xi = hr[col][1];
-        hr[col][0] = c * xr + (sr * br - si * bi);
-        hr[col][1] = c * xi + (sr * bi + si * br);
-        for (int i = 0; i <= col; ++i) {
-            Rr[i][col] = hr[i][0];
-            Ri[i][col] = hr[i][1];
-        }
-        const double g0r = gr[col], g0i = gi[col], g1r = gr[col + 1], g1i = gi[col + 1];
-        gr[col] = c * g0r + (sr * g1r - si * g1i);
-        gi[col] = c * g0i + (sr * g1i + si * g1r);
-        gr[col + 1] = -(sr * g0r + si * g0i) + c * g1r;
-        gi[col + 1] = -(sr * g0i - si * g0r) + c * g1i;
-    }
-    for (int i = k - 1; i >= 0; --i) {
-        double tr = gr[i], ti = gi[i];
-        for (int q = i + 1; q < k; ++q) {
-            tr -= Rr[i][q] * yr[q] - Ri[i][q] * yi[q];
-            ti -= Rr[i][q] * yi[q] + Ri[i][q] * yr[q];
-        }
-        const double dr = Rr[i][i], di = Ri[i][i], dd = dr * dr + di * di;
-        if (dd > 0) {
-            yr[i] = (tr * dr + ti * di) / dd;
-            yi[i] = (ti * dr - tr * di) / dd;
-        } else {
-            yr[i] = yi[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) {
+        if (i < k) {
+            // rotation [[c, s], [-conj(s), c]] with c a + s b = r, -conj(s) a + c b = 0 for
+            // (a, b) = rows i, i + 1 of column i
+            const double ar = __shfl(hr[i], i, 64), ai = __shfl(hi[i], i, 64);
+            const double br = __shfl(hr[i + 1], i, 64), bi = __shfl(hi[i + 1], i, 64);
+            const double na = sqrt(ar * ar + ai * ai), nb = sqrt(br * br + bi * bi);
+            double c, sr, si;
+            if (nb == 0.0) {
+                c = 1.0;
+                sr = si = 0.0;
+            } else if (na == 0.0) {
+                c = 0.0;
+                sr = br / nb;
+                si = -bi / nb;
+            } else {
+                const double rr = sqrt(na * na + nb * nb);
+                c = na / rr;
+                const double ur = ar / na, ui = ai / na;  // s = (a / |a|) conj(b) / r
+                sr = (ur * br + ui * bi) / rr;
+                si = (ui * br - ur * bi) / rr;
+            }
+            const double xr = hr[i], xi = hi[i], yr = hr[i + 1], yi = hi[i + 1];
+            hr[i] = c * xr + (sr * yr - si * yi);
+            hi[i] = c * xi + (sr * yi + si * yr);
+            hr[i + 1] = -(sr * xr + si * xi) + c * yr;
+            hi[i + 1] = -(sr * xi - si * xr) + c * yi;
+            const double g0r = gr[i], g0i = gi[i], g1r = gr[i + 1], g1i = gi[i + 1];
+            gr[i] = c * g0r + (sr * g1r - si * g1i);
+            gi[i] = c * g0i + (sr * g1i + si * g1r);
+            gr[i + 1] = -(sr * g0r + si * g0i) + c * g1r;
+            gi[i + 1] = -(sr * g0i - si * g0r) + c * g1i;
         }
     }
-    double *cf = G.coef + (int64_t)rhs * 2 * MG_IMAX;
-    for (int i = 0; i < k; ++i) {
-        cf[2 * i] = yr[i] * sc[i];
-        cf[2 * i + 1] = yi[i] * sc[i];
+    // back substitution: lane q holds R[i][q] in (hr[i], hi[i]) and, once known, y_q
+    double ylr = 0.0, yli = 0.0;
+#pragma unroll
+    for (int i = MG_IMAX - 1; i >= 0; --i) {
+        if (i < k) {
+            double pr = 0.0, pi = 0.0;
+            if (lane > i && lane < k) {
+                pr = hr[i] * ylr - hi[i] * yli;
+                pi = hr[i] * yli + hi[i] * ylr;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                pr += __shfl_xor(pr, off, 64);
+                pi += __shfl_xor(pi, off, 64);
+            }
+            const double dr = __shfl(hr[i], i, 64), di = __shfl(hi[i], i, 64), dd = dr * dr + di * di;
+            const double tr = gr[i] - pr, ti = gi[i] - pi;
+            if (lane == i) {
+                ylr = dd > 0 ? (tr * dr + ti * di) / dd : 0.0;
+                yli = dd > 0 ? (ti * dr - tr * di) / dd : 0.0;
+            }
+        }
+    }
+    if (lane < k) {
+        double *cf = G.coef + (int64_t)rhs * 2 * MG_IMAX;
+        cf[2 * lane] = ylr * sc[lane];
+        cf[2 * lane + 1] = yli * sc[lane];
     }
 }
 
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st) {
     if (nact <= 0) return hipSuccess;
     if (k < 1 || k > MG_IMAX || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)G.nwg, (unsigned)nact);
-    hipLaunchKernelGGL(mg_cinit_kernel, grid, dim3(MG_CWG), 0, st, G);
+    const dim3 ga((unsigned)G.nwa, (unsigned)nact), gc((unsigned)G.nwc, (unsigned)nact);
+    hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
     for (int j = 0; j < k; ++j) {
-        hipLaunchKernelGGL(mg_capply_kernel, grid, dim3(MG_CWG), 0, st, G, j);
-        hipLaunchKernelGGL(mg_cgs_kernel, grid, dim3(MG_CWG), 0, st, G, j, 1);
-        hipLaunchKernelGGL(mg_cgs_kernel, grid, dim3(MG_CWG), 0, st, G, j, 2);
+        hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
+        hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1);
+        hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 2);
     }
     hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
     return hipGetLastError();

@@ -204,3 +204,23 @@ def test_error_paths(ctx):
         f.solve(0.12, b, prec="f64")
     assert e.value.code == ESINGULAR
     f.free()
+
+
+def test_solve_after_freeing_a_field_and_loading_another_blocking(ctx):
+    """Freeing a field drops the context's kept solver batch with it: a later solve on a
+    new field (same lattice, other blocking, so possibly the same host address for the
+    new field object) builds a batch for that field instead of reusing buffers of the
+    freed one."""
+    print("solve, free, reload with other blocks, solve", flush=True)
+    dims = (16, 8, 8, 8)
+    u = synthetic.gauge_field(dims, 0.3, 83)
+    t = wilson.clover_term(u, 1.0)
+    b = synthetic.gaussian_source(dims, 1, 89)
+    for block in [(8, 4, 4, 4), (4, 4, 4, 4), (8, 4, 4, 4)]:
+        f = ctx.load_gauge(u, block)
+        f.compute_clover(1.0)
+        res = f.solve(0.125, b, nmr=4, ncy=4, restart=8, tol=1e-10, prec="f32")
+        assert res.stats[0]["converged"]
+        rel = np.linalg.norm(b[0] - wilson.apply_M(u, t, 0.125, res.x[0])) / np.linalg.norm(b[0])
+        assert rel <= 1e-10
+        f.free()
