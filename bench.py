@@ -3,6 +3,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c2_f64|c3|c3_f64_1rhs|c5|c5_host_io|serve]
     python bench.py --sweep          # time to solution over nmr x ncy x domain shape
+    python bench.py --workload mg    # two-level multigrid (SAP smoother) against SAP alone
 
 One step = one complete solve of M x = b to a true relative residual of 1e-10 (SAP
 preconditioner + FP64 flexible GMRES, every kernel of the hot path), with b and x
@@ -306,13 +307,111 @@ def run_sweep(args):
     print(json.dumps({"sweep": "16x16x16x32, 1 gaussian RHS, FP32 SAP, FGMRES(16) to 1e-10", "steps": args.steps,
                       "best": best, "grid": grid}), flush=True)
 
+# Two-level multigrid workload: the 16^3 x 32 field of the default workload at kappa 0.145,
+# near its critical value, where SAP-FGMRES needs over a thousand steps. 16 test vectors
+# per aggregate and chirality, 4 smoothing passes in the set-up, 24 coarse GMRES steps,
+# SAP smoother with 4 MR steps and 4 cycles in FP32 storage.
+MG_RUN = dict(kappa=0.145, nvec=16, setup_iters=4, coarse_iters=24, nmr=4, ncy=4, restart=16, prec="f32",
+              vec_seed=77)
+
+
+def run_mg(args):
+    import torch
+
+    import synthetic
+    from paper_1502_04025_amd import Context, Multigrid
+    from paper_1502_04025_amd import perfmodel as pm
+    cfg = dict(synthetic.CONFIGS["c2_16x16x16x32_f32"])
+    mc = dict(MG_RUN)
+    cfg["kappa"] = mc["kappa"]
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = Context(0, stream=stream)
+    u, field = make_field(ctx, cfg)
+    b = torch.from_numpy(make_source(cfg)).cuda()
+    x = torch.empty_like(b)
+    vecs = synthetic.gaussian_source(cfg["dims"], mc["nvec"], mc["vec_seed"])
+    kw = dict(nmr=mc["nmr"], ncy=mc["ncy"], restart=mc["restart"], tol=1e-10, prec=mc["prec"], max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = Multigrid(field, mc["kappa"], vecs, setup_iters=mc["setup_iters"], coarse_iters=mc["coarse_iters"],
+                   nmr=mc["nmr"], ncy=mc["ncy"], prec=mc["prec"])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = None
+        for _ in range(args.steps):
+            r = step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, r
+
+    t_mg, r_mg = timed(lambda: mg.solve(b, x=x, **kw))
+    x_mg = x[0].cpu().numpy()
+    t_sap, r_sap = timed(lambda: field.solve(mc["kappa"], b, x=x, **kw))
+    # per-family device time of one solve launched without graphs
+    ctx.profile(True)
+    mg.solve(b, x=x, flags=4, **kw)
+    fam = ctx.profile(False)
+    from oracle import wilson
+    t_or = wilson.clover_term(u, cfg["csw"])
+    b0 = b[0].cpu().numpy()
+    oracle_relres = float(np.linalg.norm(b0 - wilson.apply_M(u, t_or, mc["kappa"], x_mg)) / np.linalg.norm(b0))
+    st = r_mg.stats[0]
+    napp = fam["mg_coarse"]["launches"]
+    t_coarse = fam["mg_coarse"]["seconds"] / max(napp, 1)
+    nagg = int(np.prod(cfg["dims"])) // int(np.prod(cfg["block"]))
+    cbytes = pm.mg_coarse_bytes(nagg, 2 * mc["nvec"], mc["coarse_iters"])
+    line = {
+        "metric": "two-level multigrid (SAP smoother) FGMRES solves/s @ rel. residual 1e-10",
+        "value": round(1.0 / t_mg, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_mg, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"mg_16x16x16x32: {'x'.join(map(str, cfg['dims']))} lattice, "
+                               f"{'x'.join(map(str, cfg['block']))} aggregates = Schwarz domains, kappa {mc['kappa']}, "
+                               f"c_sw {cfg['csw']}, links exp(i {cfg['eps']} H), 1 gaussian RHS, {mc['nvec']} test "
+                               f"vectors, {mc['setup_iters']} set-up smoothing passes, {mc['coarse_iters']} coarse GMRES "
+                               f"steps, SAP smoother {mc['prec']} (nmr {mc['nmr']}, ncy {mc['ncy']}), FP64 "
+                               f"FGMRES({mc['restart']}) to 1e-10",
+                   "parallelism": "single GPU"},
+        "mg": {"outer_iters": st["iters"], "converged": bool(st["converged"]), "true_relres": st["true_relres"],
+               "oracle_relres": oracle_relres, "setup_s": round(setup_s, 4),
+               "ms_per_step_incl_setup": round(1e3 * (t_mg + setup_s), 3)},
+        "sap_only": {"outer_iters": r_sap.stats[0]["iters"], "converged": bool(r_sap.stats[0]["converged"]),
+                     "ms_per_step": round(1e3 * t_sap, 3), "solves_per_s": round(1.0 / t_sap, 4)},
+        "kernel_time_one_step_no_graph_s": {k: round(v["seconds"], 6) for k, v in fam.items() if v["launches"]},
+        "roofline": {"kernel": "coarse GMRES (mg_capply_kernel + mg_cgs_kernel + mg_cfinal_kernel)", "bound": "hbm",
+                     "achieved": round(cbytes / t_coarse / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(cbytes / t_coarse / 8e12, 4), "traffic": None,
+                     "avg_solve_us": round(t_coarse * 1e6, 2), "launches": napp,
+                     "algorithmic_bytes_per_launch": cbytes, "cache_resident": True},
+    }
+    print(json.dumps(line), flush=True)
+    mg.close()
+    field.free()
+    ctx.close()
+    if not st["converged"] or oracle_relres > 1e-10:
+        sys.exit(1)
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve", "mg"])
     ap.add_argument("--requests", type=int, default=60, help="serve: requests per arrival rate")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="serve: HBM budget for admission")
     ap.add_argument("--nmr", type=int, default=4, help="MR iterations per block solve")
@@ -341,6 +440,8 @@ def main():
         return run_sweep(args)
     if args.workload == "serve":
         return run_serving(args)
+    if args.workload == "mg":
+        return run_mg(args)
     name, prec, over = WORKLOADS[args.workload]
     cfg = dict(synthetic.CONFIGS[name])
     cfg.update(over)

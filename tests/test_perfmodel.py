@@ -43,3 +43,11 @@ def test_block_dslash_bytes_per_site():
     # f L + C + 2 S at one right-hand side
     assert pm.block_dslash_bytes((4, 4, 4, 4), "f64") == 0.75 * 576 + 576 + 2 * 192
     assert pm.block_dslash_bytes((8, 4, 4, 4), "f16") == 0.78125 * 148 + 148 + 2 * 52
+
+
+def test_mg_coarse_bytes_one_step():
+    """One coarse step over one aggregate with K = 2: the first vector's norm, the stencil
+    (9 blocks of 2 x 2 complex FP32), v_0, three Gram-Schmidt reads of v_0 and three
+    writes of v_1, each vector 2 complex FP32 numbers."""
+    nc = 2 * 8
+    assert pm.mg_coarse_bytes(1, 2, 1) == nc + 9 * 4 * 8 + nc + 3 * nc + 3 * nc
