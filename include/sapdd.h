@@ -187,17 +187,17 @@ int sapdd_batch_take(sapdd_batch *batch, int slot, double *x, int flags, sapdd_s
  *   Coarse operator: D_c = P^H M P (Galerkin), nine K x K blocks per aggregate (itself
  *     and its forward and backward neighbour in each direction), FP32, built on the
  *     device by applying the FP64 operator to interpolated unit vectors.
- *   Preconditioner B(r) = e + SAP(r - M e), e = P GMRES_k(D_c, P^H r): coarse_iters
- *     GMRES steps from zero, run on the device, then one SAP application (smoother
- *     params: nmr, ncy, sap_prec) on the remaining residual.
+ *   Preconditioner B(r) = e + SAP(r - M e), e = P GMRES(D_c, P^H r): coarse_cycles
+ *     cycles of restarted GMRES(coarse_iters) from zero, run on the device, then one SAP
+ *     application (smoother params: nmr, ncy, sap_prec) on the remaining residual.
  * Coarse vectors in the canonical form are complex [aggregate][K], aggregates in block
  * order (x fastest), as complex128. A multigrid object belongs to its field and kappa
  * and must be destroyed before the field is freed. */
 typedef struct {
     int nvec;         /* test vectors per aggregate and chirality: even, 2..16          */
     int setup_iters;  /* smoothing passes per test vector before P is built (>= 0)     */
-    int coarse_iters; /* GMRES steps of every coarse solve (1..24)                     */
-    int reserved;     /* must be 0                                                     */
+    int coarse_iters; /* GMRES steps per coarse restart cycle (1..24)                  */
+    int coarse_cycles;/* restart cycles of every coarse solve (0..64; 0 = 1)           */
 } sapdd_mg_params;
 /* Build P and D_c for (field, kappa). vecs: nvec canonical spinors (flags:
  * SAPDD_DEVICE_PTRS). smoother supplies nmr, ncy and sap_prec of the smoothing passes
@@ -213,8 +213,8 @@ int sapdd_mg_prolongator(sapdd_mg *mg, double *fields, int flags);
  * block grid of extent 2 in direction mu both neighbours are one aggregate and the
  * forward block holds the whole coupling (the backward block is zero). */
 int sapdd_mg_coarse_operator(sapdd_mg *mg, double *stencil, int flags);
-/* out = GMRES_k(D_c, rhs) for n canonical coarse vectors (k = coarse_iters, from zero;
- * rhs rounded to FP32). */
+/* out = the coarse solve of D_c e = rhs (coarse_cycles cycles of GMRES(coarse_iters)
+ * from zero) for n canonical coarse vectors; rhs rounded to FP32. */
 int sapdd_mg_coarse_solve(sapdd_mg *mg, int n, const double *rhs, double *out, int flags);
 /* out = B(in) for nrhs canonical spinors. */
 int sapdd_mg_precond(sapdd_mg *mg, int nrhs, const double *in, double *out, int flags);

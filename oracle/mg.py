@@ -18,7 +18,8 @@ out the standard two-level form of that method with these readings:
     whose R has a positive real diagonal); coarse index k = s * nvec + j;
   * coarse operator: the Galerkin product D_c = P^H M P, which couples an aggregate
     only to itself and its eight neighbours;
-  * coarse solve: coarse_iters steps of GMRES from zero on D_c e = P^H r, no restart;
+  * coarse solve: coarse_cycles cycles of restarted GMRES(coarse_iters) from zero on
+    D_c e = P^H r (every cycle minimises over the Krylov space of the current residual);
   * preconditioner: B(r) = e + SAP(r - M e) with e = P GMRES(D_c, P^H r), the
     coarse-grid correction followed by one Schwarz application (ncy cycles).
 
@@ -135,14 +136,23 @@ def gmres_fixed(apply_a, rhs: np.ndarray, k: int) -> np.ndarray:
     return out
 
 
+def gmres_restarted(apply_a, rhs: np.ndarray, k: int, cycles: int) -> np.ndarray:
+    """cycles cycles of GMRES(k) from zero: e <- e + GMRES_k(A, rhs - A e)."""
+    e = np.zeros_like(rhs)
+    for _ in range(int(cycles)):
+        e = e + gmres_fixed(apply_a, rhs - apply_a(e), k)
+    return e
+
+
 class TwoLevel:
     """The two-level preconditioner for one gauge field, kappa and blocking."""
 
     def __init__(self, u, t, kappa, block, vecs, ncy=5, nmr=4, setup_iters=0,
-                 coarse_iters=16, antiperiodic=True):
+                 coarse_iters=16, coarse_cycles=1, antiperiodic=True):
         self.sys = BlockSystem(u, t, kappa, block, antiperiodic)
         self.block = tuple(int(b) for b in block)
         self.ncy, self.nmr, self.coarse_iters = int(ncy), int(nmr), int(coarse_iters)
+        self.coarse_cycles = int(coarse_cycles)
         vecs = [np.array(v, dtype=np.complex128) for v in vecs]
         for _ in range(int(setup_iters)):
             vecs = [v - sap(self.sys, self.apply_m(v), self.ncy, self.nmr) for v in vecs]
@@ -157,10 +167,13 @@ class TwoLevel:
         """D_c e = P^H M P e."""
         return restrict(self.cols, self.apply_m(prolong(self.cols, e, self.block)), self.block)
 
+    def coarse_solve(self, rc):
+        """The coarse solve: coarse_cycles cycles of GMRES(coarse_iters) on D_c e = rc."""
+        return gmres_restarted(self.coarse_apply, rc, self.coarse_iters, self.coarse_cycles)
+
     def coarse_correction(self, r):
-        """P GMRES_k(D_c, P^H r)."""
-        rc = restrict(self.cols, r, self.block)
-        return prolong(self.cols, gmres_fixed(self.coarse_apply, rc, self.coarse_iters), self.block)
+        """P GMRES(D_c, P^H r)."""
+        return prolong(self.cols, self.coarse_solve(restrict(self.cols, r, self.block)), self.block)
 
     def precond(self, r):
         """B(r): coarse-grid correction, then one Schwarz application on the residual."""

@@ -718,7 +718,7 @@ struct sapdd_mg {
     double kappa = 0;
     sapdd_params sp{};     // smoother of the set-up and of sapdd_mg_precond
     sapdd_mg_params mp{};
-    int nvec = 0, K = 0;
+    int nvec = 0, K = 0, cycles = 1;
     MgColouring cl{};
     float *P = nullptr;    // nvec FP32 fields
     float2 *Dc = nullptr;  // coarse operator, Nd * 9 * K * K
@@ -733,6 +733,7 @@ struct MgWork {
     int cap = 0, nwa = 0, nwc = 0, pstride = 0;
     double *t1 = nullptr, *t2 = nullptr;  // FP64 fields: interpolated coarse solution, residual
     float2 *cb = nullptr;                 // coarse Krylov bases
+    float2 *rc = nullptr, *xc = nullptr;  // coarse right-hand sides and solutions
     double *pn = nullptr, *pd = nullptr, *H = nullptr, *sc = nullptr, *beta = nullptr, *coef = nullptr;
 };
 
@@ -750,6 +751,10 @@ int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
     w->t2 = (double *)q;
     CHK(alloc("mg_cb", (size_t)cap * (MG_IMAX + 1) * nc * sizeof(float2), &q));
     w->cb = (float2 *)q;
+    CHK(alloc("mg_rc", (size_t)cap * nc * sizeof(float2), &q));
+    w->rc = (float2 *)q;
+    CHK(alloc("mg_xc", (size_t)cap * nc * sizeof(float2), &q));
+    w->xc = (float2 *)q;
     CHK(alloc("mg_pn", (size_t)cap * (MG_IMAX + 1) * w->pstride * 8, &q));
     w->pn = (double *)q;
     CHK(alloc("mg_pd", (size_t)cap * 4 * MG_IMAX * w->pstride * 8, &q));
@@ -778,6 +783,8 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     G.basis = w.cb;
     G.vstride = g.Nd * mg->K;
     G.bstride = (MG_IMAX + 1) * G.vstride;
+    G.rc = w.rc;
+    G.xc = w.xc;
     G.pn = w.pn;
     G.pd = w.pd;
     G.H = w.H;
@@ -789,7 +796,7 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
 }
 
 // psi = B(s eta) for the listed systems (s = eta_scale[rhs * eta_sstride], 1 if null):
-// e = P GMRES_k(D_c, P^H eta) (the coarse solve is homogeneous, so it runs on the
+// e = P GMRES(D_c, P^H eta) (restarted GMRES(k), a homogeneous map, so it runs on the
 // unscaled eta), t2 = eta - M e, psi = SAP(s t2) + s e. eta: FP64 fields with stride
 // eta_stride fields per rhs; psi in psi_prec with stride psi_stride fields; per-rhs kappa
 // and clover from ss.
@@ -800,11 +807,11 @@ int mg_run(sapdd_ctx *c, const sapdd_mg *mg, const MgWork &w, const SapState &ss
     const int64_t NS = g.V * 24;
     const MgGmres G = mg_gmres(mg, w, active);
     const int k = mg->mp.coarse_iters;
-    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_restrict(g, mg->nvec, eta, eta_stride * NS, mg->P, w.cb, G.bstride, active,
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_restrict(g, mg->nvec, eta, eta_stride * NS, mg->P, w.rc, G.vstride, active,
                                                    nact, c->stream));
-    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, nact, k, c->stream));
-    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_prolong_basis(g, mg->nvec, mg->P, w.cb, G.bstride, G.vstride, w.coef,
-                                                        2 * MG_IMAX, k, w.t1, NS, active, nact, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, nact, k, mg->cycles, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_FINE, launch_mg_prolong_basis(g, mg->nvec, mg->P, w.xc, G.vstride, 0, nullptr, 0, 1, w.t1,
+                                                        NS, active, nact, c->stream));
     DslashIO io{};
     io.in = Fld{w.t1, nullptr, P64};
     io.out = Fld{w.t2, nullptr, P64};
@@ -1833,7 +1840,8 @@ int sapdd_mg_setup(sapdd_ctx *c, sapdd_field *f, double kappa, const sapdd_param
         return fail(c, SAPDD_EINVAL, "nvec must be even and in 2..%d", MG_NVEC_MAX);
     if (mgp->coarse_iters < 1 || mgp->coarse_iters > MG_IMAX)
         return fail(c, SAPDD_EINVAL, "coarse_iters must be in 1..%d", MG_IMAX);
-    if (mgp->setup_iters < 0 || mgp->reserved != 0) return fail(c, SAPDD_EINVAL, "bad multigrid parameters");
+    if (mgp->setup_iters < 0 || mgp->coarse_cycles < 0 || mgp->coarse_cycles > 64)
+        return fail(c, SAPDD_EINVAL, "setup_iters must be >= 0 and coarse_cycles in 0..64");
     const Geom &g = f->geo;
     if (g.Vb > 512) return fail(c, SAPDD_EINVAL, "multigrid aggregates (Schwarz blocks) must have <= 512 sites");
     if ((int64_t)mgp->coarse_iters > g.Nd * 2 * mgp->nvec)
@@ -1846,6 +1854,7 @@ int sapdd_mg_setup(sapdd_ctx *c, sapdd_field *f, double kappa, const sapdd_param
     mg->mp = *mgp;
     mg->nvec = mgp->nvec;
     mg->K = 2 * mgp->nvec;
+    mg->cycles = std::max(1, mgp->coarse_cycles);
     mg->cl = mg_colouring(g);
     const int r = mg_setup_body(mg, vecs, flags);
     if (r != SAPDD_OK) {
@@ -1918,11 +1927,10 @@ int sapdd_mg_coarse_solve(sapdd_mg *mg, int n, const double *rhs, double *out, i
     CHK(stage_in(c, "stage_in", rhs, (size_t)n * nc * 2, flags, &src));
     const MgGmres G = mg_gmres(mg, w, ident);
     KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_load(G, n, src, (int64_t)nc * 2, c->stream));
-    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, n, mg->mp.coarse_iters, c->stream));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_coarse_gmres(G, n, mg->mp.coarse_iters, mg->cycles, c->stream));
     void *q;
     CHK(buf(c, "stage_out", (size_t)n * nc * 16, &q));
-    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_combine(G, n, mg->mp.coarse_iters, (double *)q, (int64_t)nc * 2,
-                                                    c->stream));
+    KLAUNCH(c, SAPDD_K_MG_COARSE, launch_mg_solution(G, n, (double *)q, (int64_t)nc * 2, c->stream));
     return copy_out(c, q, out, (size_t)n * nc * 2, flags);
 }
 

@@ -145,7 +145,8 @@ hipError_t launch_mg_orth(const Geom &geo, double *w, int nvec, hipStream_t st);
 // (stride in complex numbers); rhs = active[slot] (slot if active is null).
 hipError_t launch_mg_restrict(const Geom &geo, int nvec, const double *in, int64_t in_stride, const float *P,
                               float2 *out, int64_t out_stride, const int *active, int nact, hipStream_t st);
-// out(rhs) = P sum_{i < nb} coef(rhs)[i] basis(rhs)[i], FP64 output (stride in doubles).
+// out(rhs) = P sum_{i < nb} coef(rhs)[i] basis(rhs)[i] (coef null: P basis(rhs)), FP64
+// output (stride in doubles).
 hipError_t launch_mg_prolong_basis(const Geom &geo, int nvec, const float *P, const float2 *basis, int64_t bstride,
                                    int64_t vstride, const double *coef, int64_t cstride, int nb, double *out,
                                    int64_t out_stride, const int *active, int nact, hipStream_t st);
@@ -168,23 +169,24 @@ struct MgGmres {
     int64_t Nd;        // aggregates
     int nwa, nwc;      // workgroups per system of the operator and Gram-Schmidt kernels
     int pstride;       // partials stride per value (>= nwa, nwc)
-    float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride; slot 0 = rhs
+    float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride
     int64_t bstride, vstride;
+    float2 *rc;        // right-hand side(rhs) at rc + rhs * vstride
+    float2 *xc;        // solution(rhs) at xc + rhs * vstride
     double *pn;        // [rhs][MG_IMAX + 1][pstride] |v_i|^2 partials
     double *pd;        // [rhs][2][2 MG_IMAX][pstride] Gram-Schmidt partials
     double *H;         // [rhs][MG_IMAX][MG_IMAX + 1] complex, column-major Hessenberg
     double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
     double *beta;      // [rhs] |rhs|
-    double *coef;      // [rhs][MG_IMAX] complex: solution = sum_i coef[i] basis[i]
+    double *coef;      // [rhs][MG_IMAX] complex: a cycle's correction = sum_i coef[i] basis[i]
     const int *active;
 };
 void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc);
-// k GMRES steps from zero on D_c e = basis[0] for every listed system; the solution's
-// coefficients over the stored basis go to coef.
-hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st);
-// basis(rhs)[0] = in(rhs) rounded to FP32, in complex FP64 at in + rhs * istride.
+// cycles cycles of restarted GMRES(k) from zero on D_c xc = rc for every listed system.
+hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st);
+// rc(rhs) = in(rhs) rounded to FP32, in complex FP64 at in + rhs * istride.
 hipError_t launch_mg_load(const MgGmres &G, int nact, const double *in, int64_t istride, hipStream_t st);
-// out(rhs) = sum_{i < nb} coef(rhs)[i] basis(rhs)[i], complex FP64 at out + rhs * ostride.
-hipError_t launch_mg_combine(const MgGmres &G, int nact, int nb, double *out, int64_t ostride, hipStream_t st);
+// out(rhs) = xc(rhs) as complex FP64 at out + rhs * ostride.
+hipError_t launch_mg_solution(const MgGmres &G, int nact, double *out, int64_t ostride, hipStream_t st);
 
 }  // namespace sapdd

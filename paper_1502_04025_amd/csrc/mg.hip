@@ -15,12 +15,13 @@
 // ((b * 9 + d) * K + col) * K + row, d = 0 the aggregate itself, d = 1 + 2 mu the
 // forward and d = 2 + 2 mu the backward neighbour in direction mu.
 //
-// The coarse system is solved by a fixed number of GMRES steps from zero, entirely on
-// the device so the whole preconditioner is one static launch sequence: every Arnoldi
-// step is three kernels (operator + first Gram-Schmidt pass, second pass, norm), each
-// reduction a fixed-order sum of per-workgroup partials that every workgroup of the
-// next kernel repeats for itself, and one workgroup per system solves the small least
-// squares problem at the end.
+// The coarse system is solved by a fixed number of restarted GMRES cycles of a fixed
+// number of steps, from zero, entirely on the device so the whole preconditioner is one
+// static launch sequence: every Arnoldi step is three kernels (operator + first
+// Gram-Schmidt pass, second pass, norm), each reduction a fixed-order sum of
+// per-workgroup partials that every workgroup of the next kernel repeats for itself; one
+// wave per system solves the small least squares problem at the end of a cycle, and the
+// cycle's correction is added to the coarse solution, whose residual starts the next.
 #include "kernels.hpp"
 
 namespace sapdd {
@@ -246,14 +247,15 @@ __global__ __launch_bounds__(512) void mg_restrict_kernel(const double *in, int6
     }
 }
 
-// out(rhs) = P e(rhs) (or out += P e with ADD) on one aggregate per workgroup, FP64
-// output. The coarse vector e on the aggregate is either
-//   probe (cprobe.q >= 0): 1 in column k0 + rhs on aggregates of colour q, else 0, or
+// out(rhs) = P e(rhs) on one aggregate per workgroup, FP64 output. The coarse vector e
+// on the aggregate is either
+//   probe (q >= 0): 1 in column k0 + rhs on aggregates of colour q, else 0,
+//   the coarse vector basis(rhs) itself (coef null), or
 //   a combination sum_{i < nb} coef(rhs)[i] basis(rhs)[i] of coarse vectors.
 struct MgCoarseSrc {
     const float2 *basis;   // basis(rhs)[i] at basis + rhs * bstride + i * vstride
     int64_t bstride, vstride;
-    const double *coef;    // complex coef(rhs)[i] at coef + rhs * cstride + 2 i
+    const double *coef;    // complex coef(rhs)[i] at coef + rhs * cstride + 2 i (null: basis(rhs) itself)
     int64_t cstride;
     int nb;
     int q, k0;             // probe colour (q < 0: no probe) and first column
@@ -277,6 +279,8 @@ __global__ __launch_bounds__(512) void mg_prolong_kernel(MgCoarseSrc src, const 
             int g[4];
             block_coords(geo.G, b, g);
             if (mg_colour(g, src.cl) == src.q && tid == src.k0 + rhs) v.x = 1.f;
+        } else if (!src.coef) {  // a plain coarse vector
+            v = src.basis[(int64_t)rhs * src.bstride + b * K + tid];
         } else {
             const float2 *bs = src.basis + (int64_t)rhs * src.bstride + b * K + tid;
             const double *cf = src.coef + (int64_t)rhs * src.cstride;
@@ -743,55 +747,116 @@ __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
     }
 }
 
-hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, hipStream_t st) {
-    if (nact <= 0) return hipSuccess;
-    if (k < 1 || k > MG_IMAX || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
-    const dim3 ga((unsigned)G.nwa, (unsigned)nact), gc((unsigned)G.nwc, (unsigned)nact);
-    hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
-    for (int j = 0; j < k; ++j) {
-        hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
-        hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1);
-        hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 2);
+// Start of a restart cycle: v_0 = rc - D_c xc (v_0 = rc on the first cycle, xc = 0).
+// Same tiling as the operator kernel.
+__global__ __launch_bounds__(MG_AWG) void mg_cres_kernel(MgGmres G, int first) {
+    __shared__ double ys[2][8][MG_ALANES];
+    const int rhs = G.active[blockIdx.y];
+    const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
+    const int dg = threadIdx.x / MG_ALANES, r = threadIdx.x % MG_ALANES;
+    const int bl = r / K, a = r - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * ta + bl;
+    const bool act = bl < ta && b < G.Nd;
+    const float2 *xc = G.xc + (int64_t)rhs * G.vstride;
+    const float2 rc = act ? G.rc[(int64_t)rhs * G.vstride + b * K + a] : make_float2(0.f, 0.f);
+    float2 *v0 = G.basis + (int64_t)rhs * G.bstride;
+    if (first) {
+        if (act && dg == 0) v0[b * K + a] = rc;
+        return;
     }
-    hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
-    return hipGetLastError();
+    double yr = 0, yi = 0;
+    if (act) {
+        int g[4];
+        block_coords(G.grid, b, g);
+        for (int d = dg; d < 9; d += 8) {
+            const int64_t nb = mg_neighbour(G.grid, g, d);
+            const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
+            const float2 *x = xc + nb * K;
+            for (int c = 0; c < K; ++c) {
+                const float2 m = dcol[(int64_t)c * K], xv = x[c];
+                yr += (double)m.x * xv.x - (double)m.y * xv.y;
+                yi += (double)m.x * xv.y + (double)m.y * xv.x;
+            }
+        }
+    }
+    ys[0][dg][r] = yr;
+    ys[1][dg][r] = yi;
+    __syncthreads();
+    if (dg != 0 || !act) return;
+    yr = yi = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        yr += ys[0][q][r];
+        yi += ys[1][q][r];
+    }
+    v0[b * K + a] = make_float2((float)(rc.x - yr), (float)(rc.y - yi));
 }
 
-// out(rhs) = sum_{i < nb} coef(rhs)[i] basis(rhs)[i] as complex FP64 (out + rhs * ostride
-// doubles): the coarse solution itself, for callers that want it on the coarse grid.
-__global__ void mg_combine_kernel(MgGmres G, int nb, double *out, int64_t ostride) {
+// End of a restart cycle: xc = (first ? 0 : xc) + sum_{i < k} coef[i] v_i.
+__global__ void mg_caccum_kernel(MgGmres G, int k, int first) {
     const int64_t n = G.Nd * G.K;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int rhs = G.active[blockIdx.y];
     const float2 *bs = G.basis + (int64_t)rhs * G.bstride + t;
     const double *cf = G.coef + (int64_t)rhs * 2 * MG_IMAX;
-    double vr = 0, vi = 0;
-    for (int i = 0; i < nb; ++i) {
+    float2 *xc = G.xc + (int64_t)rhs * G.vstride + t;
+    double vr = first ? 0.0 : (double)xc->x, vi = first ? 0.0 : (double)xc->y;
+    for (int i = 0; i < k; ++i) {
         const float2 x = bs[(int64_t)i * G.vstride];
         vr += cf[2 * i] * x.x - cf[2 * i + 1] * x.y;
         vi += cf[2 * i] * x.y + cf[2 * i + 1] * x.x;
     }
-    out[(int64_t)rhs * ostride + 2 * t] = vr;
-    out[(int64_t)rhs * ostride + 2 * t + 1] = vi;
+    *xc = make_float2((float)vr, (float)vi);
 }
 
-hipError_t launch_mg_combine(const MgGmres &G, int nact, int nb, double *out, int64_t ostride, hipStream_t st) {
+hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    if (k < 1 || k > MG_IMAX || cycles < 1 || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
+    const dim3 ga((unsigned)G.nwa, (unsigned)nact), gc((unsigned)G.nwc, (unsigned)nact);
     const int64_t n = G.Nd * G.K;
-    if (nact <= 0 || n == 0) return hipSuccess;
-    hipLaunchKernelGGL(mg_combine_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0, st, G,
-                       nb, out, ostride);
+    const dim3 ge((unsigned)((n + 255) / 256), (unsigned)nact);
+    for (int cyc = 0; cyc < cycles; ++cyc) {
+        hipLaunchKernelGGL(mg_cres_kernel, ga, dim3(MG_AWG), 0, st, G, (int)(cyc == 0));
+        hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
+        for (int j = 0; j < k; ++j) {
+            hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
+            hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1);
+            hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 2);
+        }
+        hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
+        hipLaunchKernelGGL(mg_caccum_kernel, ge, dim3(256), 0, st, G, k, (int)(cyc == 0));
+    }
     return hipGetLastError();
 }
 
-// basis(rhs)[0] = in(rhs) rounded to FP32 (in: complex FP64 at in + rhs * istride).
+// out(rhs) = the coarse solution xc(rhs) as complex FP64 (out + rhs * ostride doubles).
+__global__ void mg_solution_kernel(MgGmres G, double *out, int64_t ostride) {
+    const int64_t n = G.Nd * G.K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int rhs = G.active[blockIdx.y];
+    const float2 x = G.xc[(int64_t)rhs * G.vstride + t];
+    out[(int64_t)rhs * ostride + 2 * t] = x.x;
+    out[(int64_t)rhs * ostride + 2 * t + 1] = x.y;
+}
+
+hipError_t launch_mg_solution(const MgGmres &G, int nact, double *out, int64_t ostride, hipStream_t st) {
+    const int64_t n = G.Nd * G.K;
+    if (nact <= 0 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mg_solution_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nact), dim3(256), 0, st, G,
+                       out, ostride);
+    return hipGetLastError();
+}
+
+// rc(rhs) = in(rhs) rounded to FP32 (in: complex FP64 at in + rhs * istride).
 __global__ void mg_load_kernel(MgGmres G, const double *in, int64_t istride) {
     const int64_t n = G.Nd * G.K;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int rhs = G.active[blockIdx.y];
     const double *x = in + (int64_t)rhs * istride + 2 * t;
-    G.basis[(int64_t)rhs * G.bstride + t] = make_float2((float)x[0], (float)x[1]);
+    G.rc[(int64_t)rhs * G.vstride + t] = make_float2((float)x[0], (float)x[1]);
 }
 
 hipError_t launch_mg_load(const MgGmres &G, int nact, const double *in, int64_t istride, hipStream_t st) {

@@ -52,7 +52,7 @@ class Params(C.Structure):
 
 class MgParams(C.Structure):
     _fields_ = [("nvec", C.c_int), ("setup_iters", C.c_int), ("coarse_iters", C.c_int),
-                ("reserved", C.c_int)]
+                ("coarse_cycles", C.c_int)]
 
 
 class KernelProfile(C.Structure):
@@ -384,13 +384,14 @@ class Multigrid:
     and kappa. vecs: the nvec test vectors (canonical spinors [nvec,t,z,y,x,4,3]);
     smoother keywords (nmr, ncy, prec) as Field.params."""
 
-    def __init__(self, field: "Field", kappa: float, vecs, setup_iters=0, coarse_iters=16, **smoother):
+    def __init__(self, field: "Field", kappa: float, vecs, setup_iters=0, coarse_iters=16, coarse_cycles=1,
+                 **smoother):
         self.field, self.ctx, self.kappa = field, field.ctx, float(kappa)
         self.nvec = int(vecs.shape[0])
         self.K = 2 * self.nvec
         self.grid = tuple(field.dims[mu] // field.block[mu] for mu in range(4))  # x, y, z, t
         prm = field.params(**smoother)
-        mp = MgParams(self.nvec, int(setup_iters), int(coarse_iters), 0)
+        mp = MgParams(self.nvec, int(setup_iters), int(coarse_iters), int(coarse_cycles))
         pv, dev = _ptr(vecs)
         h = C.c_void_p()
         self.ctx._check(self.ctx.lib.sapdd_mg_setup(self.ctx.h, field.h, self.kappa, C.byref(prm), C.byref(mp), pv,
@@ -430,7 +431,7 @@ class Multigrid:
         return out
 
     def coarse_solve(self, rhs):
-        """coarse_iters GMRES steps from zero on D_c e = rhs, rhs [n,Gt,Gz,Gy,Gx,K]."""
+        """The coarse solve of D_c e = rhs (restarted GMRES from zero), rhs [n,Gt,Gz,Gy,Gx,K]."""
         rhs = np.ascontiguousarray(rhs, dtype=np.complex128)
         out = np.empty_like(rhs)
         pi, _ = _ptr(rhs)

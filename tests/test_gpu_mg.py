@@ -119,6 +119,32 @@ def test_coarse_gmres_matches_oracle(small):
         assert np.linalg.norm(got[i] - ref) <= 1e-4 * np.linalg.norm(ref)
 
 
+def test_restarted_coarse_solve_and_application_match_oracle(small):
+    """Three restart cycles of GMRES(6) on the coarse system, alone and inside one
+    preconditioner application."""
+    print("mg restarted coarse GMRES", flush=True)
+    from paper_1502_04025_amd import Multigrid
+    f, kappa = small["f"], small["kappa"]
+    vecs = synthetic.gaussian_source(small["dims"], 4, 44)
+    mg = Multigrid(f, kappa, vecs, setup_iters=2, coarse_iters=6, coarse_cycles=3, nmr=4, ncy=2, prec="f64")
+    tl = omg.TwoLevel(small["u"], small["t"], kappa, small["block"], list(vecs), ncy=2, nmr=4, setup_iters=2,
+                      coarse_iters=6, coarse_cycles=3)
+    rng = np.random.default_rng(9)
+    shape = (2, 2, 2, 2, 8)
+    rhs = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))[None]
+    got = mg.coarse_solve(rhs)[0]
+    ref = tl.coarse_solve(rhs[0])
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    # the restarts reach further than one cycle of the same length
+    one = omg.gmres_fixed(tl.coarse_apply, rhs[0], 6)
+    assert np.linalg.norm(rhs[0] - tl.coarse_apply(ref)) < np.linalg.norm(rhs[0] - tl.coarse_apply(one))
+    r = synthetic.gaussian_source(small["dims"], 1, 48)
+    got = mg.precond(r)[0]
+    ref = tl.precond(r[0])
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    mg.close()
+
+
 def test_preconditioner_application_matches_oracle(small):
     print("mg one application", flush=True)
     r = synthetic.gaussian_source(small["dims"], 2, 47)

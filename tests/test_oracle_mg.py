@@ -145,6 +145,27 @@ def test_gmres_fixed_is_the_krylov_least_squares_minimiser():
     np.testing.assert_allclose(a @ e, rhs, atol=1e-9)
 
 
+def test_restarted_gmres_minimises_each_cycle_over_its_residual_krylov_space():
+    """Cycle c of the restarted solve adds the minimiser of |r - A d| over the Krylov space
+    of its starting residual r (an explicit least-squares solve over that basis), and one
+    cycle is plain GMRES(k)."""
+    rng = np.random.default_rng(4)
+    n, k = 30, 4
+    a = np.eye(n) * 2 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    rhs = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    op = lambda v: a @ v  # noqa: E731
+    np.testing.assert_allclose(mg.gmres_restarted(op, rhs, k, 1), mg.gmres_fixed(op, rhs, k), atol=1e-12)
+    e = np.zeros(n, dtype=complex)
+    for c in range(1, 4):
+        r = rhs - a @ e
+        kry = np.stack([np.linalg.matrix_power(a, i) @ r for i in range(k)], axis=1)
+        q, _ = np.linalg.qr(kry)
+        e = e + q @ np.linalg.lstsq(a @ q, r, rcond=None)[0]
+        got = mg.gmres_restarted(op, rhs, k, c)
+        np.testing.assert_allclose(got, e, atol=1e-10 * np.linalg.norm(e))
+    assert np.linalg.norm(rhs - a @ e) < np.linalg.norm(rhs - a @ mg.gmres_fixed(op, rhs, k))
+
+
 def test_two_grid_with_exact_coarse_solve_reproduces_the_coarse_space(long_t):
     f = long_t
     tl = mg.TwoLevel(f["u"], f["t"], f["kappa"], f["block"], f["vecs"], ncy=2, nmr=3,

@@ -51,3 +51,5 @@ def test_mg_coarse_bytes_one_step():
     writes of v_1, each vector 2 complex FP32 numbers."""
     nc = 2 * 8
     assert pm.mg_coarse_bytes(1, 2, 1) == nc + 9 * 4 * 8 + nc + 3 * nc + 3 * nc
+    # two systems share the stencil and double everything else
+    assert pm.mg_coarse_bytes(1, 2, 1, 2) == 2 * nc + 9 * 4 * 8 + 2 * (nc + 3 * nc + 3 * nc)
