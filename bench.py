@@ -140,21 +140,22 @@ def dslash_bandwidth(ctx, warm=10, reps=100):
     out = torch.empty_like(psi)
     V = int(np.prod(cfg["dims"]))
     res = {}
-    for prec in ("f16", "f32"):
+    for prec, two_row in (("f16", False), ("f32", False), ("f16", True), ("f32", True)):
         for _ in range(warm):  # the first one builds the low-precision copies
-            f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out)
+            f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out, links12=two_row)
         ts = []
         for _ in range(reps):
             ctx.profile(True, families=["block_dslash"])
-            f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out)
+            f.apply_block_D(cfg["kappa"], psi, prec=prec, out=out, links12=two_row)
             ts.append(ctx.profile(False)["block_dslash"]["seconds"])
         med, p10, p90 = (float(np.percentile(ts, q)) for q in (50, 10, 90))
-        byts = pm.block_dslash_bytes(cfg["block"], prec) * V
+        byts = pm.block_dslash_bytes(cfg["block"], prec, links12=two_row) * V
         gbs = byts / med / 1e9
-        res[prec] = dict(GB_s=round(gbs, 1), frac=round(gbs / pm.HBM_PEAK_GBS, 4),
-                         median_launch_us=round(med * 1e6, 2), p10_us=round(p10 * 1e6, 2),
-                         p90_us=round(p90 * 1e6, 2), launches=reps, algorithmic_bytes_per_launch=byts,
-                         traffic=profiled_traffic(f"dslash_block_kernel 32x32x32x64 4x4x4x4 {prec}"))
+        kname = "dslash_block12_kernel" if two_row else "dslash_block_kernel"
+        res[prec + ("_links12" if two_row else "")] = dict(
+            GB_s=round(gbs, 1), frac=round(gbs / pm.HBM_PEAK_GBS, 4), median_launch_us=round(med * 1e6, 2),
+            p10_us=round(p10 * 1e6, 2), p90_us=round(p90 * 1e6, 2), launches=reps,
+            algorithmic_bytes_per_launch=byts, traffic=profiled_traffic(f"{kname} 32x32x32x64 4x4x4x4 {prec}"))
     f.free()
     return dict(kernel="dslash_block_kernel", lattice="32x32x32x64", block=list(cfg["block"]), **res)
 
@@ -548,9 +549,9 @@ def main():
         except Exception as e:  # report, do not hide the main number
             line["dslash"] = {"error": str(e)}
         line["copy_GB_s"] = copy_bandwidth(ctx)
-        for prec in ("f16", "f32"):  # also as a fraction of the measured copy bandwidth
-            if isinstance(line["dslash"].get(prec), dict):
-                line["dslash"][prec]["frac_of_copy"] = round(line["dslash"][prec]["GB_s"] / line["copy_GB_s"], 4)
+        for key in ("f16", "f32", "f16_links12", "f32_links12"):  # also as a fraction of the copy bandwidth
+            if isinstance(line["dslash"].get(key), dict):
+                line["dslash"][key]["frac_of_copy"] = round(line["dslash"][key]["GB_s"] / line["copy_GB_s"], 4)
         if prec != "f64":
             t0 = time.perf_counter()
             n64 = 3

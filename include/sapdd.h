@@ -66,7 +66,9 @@ enum { SAPDD_F64 = 0, SAPDD_F32 = 1, SAPDD_F16 = 2 }; /* storage precisions */
 enum {
     SAPDD_DEVICE_PTRS = 1, /* array arguments are device pointers              */
     SAPDD_USE_X0 = 2,      /* sapdd_solve starts from the x passed in, not 0    */
-    SAPDD_NO_GRAPH = 4     /* sapdd_solve launches the SAP sweep without a graph */
+    SAPDD_NO_GRAPH = 4,    /* sapdd_solve launches the SAP sweep without a graph */
+    SAPDD_LINKS12 = 8      /* sapdd_apply_block_D: links stored as their first two
+                            * rows, the third rebuilt in the kernel (FP32/FP16)  */
 };
 
 /* Solver parameters (Sec. 3.1 names the pieces; Sec. 3.7 uses 4-5 MR iterations and
@@ -129,7 +131,11 @@ int sapdd_free_field(sapdd_ctx *ctx, sapdd_field *field);
 int sapdd_apply_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec, int nrhs,
                   const double *in, double *out, int flags);
 /* out = M_B in: M with every hop between two different Schwarz blocks removed (the
- * block-diagonal part of the splitting in Sec. 3.1), same arguments as sapdd_apply_D. */
+ * block-diagonal part of the splitting in Sec. 3.1), same arguments as sapdd_apply_D.
+ * With SAPDD_LINKS12 in flags (FP32 or FP16 only) every link is read as its first two
+ * rows and the third is rebuilt as the complex conjugate of their cross product: a third
+ * fewer link bytes, exact for special unitary links (the library does not check that).
+ * The two-row copy is made on first use and kept with the field. */
 int sapdd_apply_block_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec,
                         int nrhs, const double *in, double *out, int flags);
 /* out = SAP(in): params->ncy cycles of MR block solves over colour 0 then colour 1,

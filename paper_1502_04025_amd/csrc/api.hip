@@ -51,6 +51,7 @@ struct sapdd_field {
     double *tclov64 = nullptr;
     Fld links_lo[3] = {};  // [P32], [P16] lower-precision copies, made on demand
     Fld tclov_lo[3] = {};
+    Fld links12[3] = {};   // [P32], [P16] links as their first two rows, made on demand
     std::vector<XEntry> xcache;
     unsigned long long use_clock = 0;
     double csw = 0.0;
@@ -247,6 +248,21 @@ int lo_copies(sapdd_ctx *c, sapdd_field *f, int prec) {
         HIPCHK(c, launch_convert(g, 72, 1, which == 0 ? f->links64 : f->tclov64, fl, c->stream));
         (which == 0 ? f->links_lo[prec] : f->tclov_lo[prec]) = fl;
     }
+    return SAPDD_OK;
+}
+
+// The links as their first two rows in storage precision prec (P32 or P16), made once.
+int links12_copy(sapdd_ctx *c, sapdd_field *f, int prec) {
+    if (f->links12[prec].data) return SAPDD_OK;
+    const Geom &g = f->geo;
+    size_t bytes = (size_t)g.V * 48 * prec_bytes(prec);
+    const size_t sc_off = (bytes + 255) / 256 * 256;
+    if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
+    void *p = nullptr;
+    HIPCHK(c, hipMalloc(&p, bytes));
+    Fld fl{p, prec == P16 ? (float *)((char *)p + sc_off) : nullptr, prec};
+    HIPCHK(c, launch_links12_pack(g, f->links64, fl, c->stream));
+    f->links12[prec] = fl;
     return SAPDD_OK;
 }
 
@@ -521,6 +537,7 @@ static void drop_derived(sapdd_field *f) {
     for (int p = 1; p < 3; ++p) {
         free_fld(f->links_lo[p]);
         free_fld(f->tclov_lo[p]);
+        free_fld(f->links12[p]);
     }
     for (auto &e : f->xcache) free_fld(e.x);
     f->xcache.clear();
@@ -583,14 +600,20 @@ static int apply_common(sapdd_ctx *c, const sapdd_field *fc, double kappa, int p
     sapdd_field *f = const_cast<sapdd_field *>(fc);
     const Geom &g = f->geo;
     const size_t nd = (size_t)g.V * 24 * nrhs;
+    const bool two_row = block && (flags & SAPDD_LINKS12);
+    if (two_row && prec == P64) return fail(c, SAPDD_EINVAL, "two-row links are for FP32 and FP16 storage");
     CHK(lo_copies(c, f, prec));
+    if (two_row) CHK(links12_copy(c, f, prec));
     const double *src;
     CHK(stage_in(c, "stage_in", in, nd, flags, &src));
     Fld fin, fout;
     CHK(spinor_buf(c, "op_in", g, nrhs, prec, 24, &fin));
     CHK(spinor_buf(c, "op_out", g, nrhs, prec, 24, &fout));
     HIPCHK(c, launch_pack(g, 24, nrhs, src, fin, c->stream));
-    if (block) {
+    if (two_row) {
+        KLAUNCH(c, SAPDD_K_BLOCK_DSLASH,
+                launch_dslash_block12(g, f->links12[prec], tclov_of(f, prec), kappa, fin, fout, nrhs, c->stream));
+    } else if (block) {
         KLAUNCH(c, SAPDD_K_BLOCK_DSLASH, launch_dslash_block(g, links_of(f, prec), tclov_of(f, prec), kappa, fin, fout, nrhs, c->stream));
     } else {
         int *ident;

@@ -57,6 +57,15 @@ hipError_t launch_dslash_full(const Geom &geo, Fld links, Fld tclov, double kapp
 hipError_t launch_dslash_block(const Geom &geo, Fld links, Fld tclov, double kappa, Fld in, Fld out, int nrhs,
                                hipStream_t st);
 
+// ---- block operator with two-row links (links12.hip)
+// Rows 0 and 1 of every link of the FP64 block-tiled field (48 reals per site) in out.prec
+// (P32 or P16 with per-site scales).
+hipError_t launch_links12_pack(const Geom &geo, const double *links64, Fld out, hipStream_t st);
+// out = M_B in with the links in that form (third rows rebuilt in the kernel), FP32 or
+// FP16 storage throughout.
+hipError_t launch_dslash_block12(const Geom &geo, Fld links12, Fld tclov, double kappa, Fld in, Fld out, int nrhs,
+                                 hipStream_t st);
+
 // ---- Schwarz sweep (sap.hip)
 struct SapArgsHost {
     Fld links;                // storage-precision links

@@ -34,10 +34,15 @@ def internal_fraction(block) -> float:
     return sum((b - 1) / b for b in block) / 4.0
 
 
-def block_dslash_bytes(block, prec: str, nrhs: int = 1) -> float:
+# links stored as their first two rows (4 x 12 reals, FP16 plus a 4-byte site scale)
+LINK12_BYTES = {"f32": 192, "f16": 100}
+
+
+def block_dslash_bytes(block, prec: str, nrhs: int = 1, links12: bool = False) -> float:
     """Block operator M_B: internal links, clover, one spinor read and one written."""
     f = internal_fraction(block)
-    return f * LINK_BYTES[prec] + CLOVER_BYTES[prec] + 2 * nrhs * SPINOR_BYTES[prec]
+    lb = LINK12_BYTES[prec] if links12 else LINK_BYTES[prec]
+    return f * lb + CLOVER_BYTES[prec] + 2 * nrhs * SPINOR_BYTES[prec]
 
 
 def block_dslash_flops(block) -> float:

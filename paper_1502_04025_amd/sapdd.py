@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libsapdd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16 = 0, 1, 2
-DEVICE_PTRS, USE_X0, NO_GRAPH = 1, 2, 4
+DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12 = 1, 2, 4, 8
 PRECS = {"f64": F64, "f32": F32, "f16": F16}
 
 # Entry points declared in include/sapdd.h (the CPU tests check the library exports them).
@@ -247,21 +247,22 @@ class Field:
     def _nrhs(psi):
         return 1 if psi.ndim == 6 else int(psi.shape[0])
 
-    def _apply(self, fn, kappa, psi, prec, out):
+    def _apply(self, fn, kappa, psi, prec, out, flags=0):
         out = _empty_like(psi) if out is None else out
         pi, dev = _ptr(psi)
         po, dev2 = _ptr(out, writable=True)
         if dev != dev2:
             raise ValueError("input and output must both be host or both be device arrays")
         self.ctx._check(fn(self.ctx.h, self.h, float(kappa), PRECS[prec] if isinstance(prec, str) else int(prec),
-                           self._nrhs(psi), pi, po, DEVICE_PTRS if dev else 0))
+                           self._nrhs(psi), pi, po, (DEVICE_PTRS if dev else 0) | flags))
         return out
 
     def apply_D(self, kappa, psi, prec="f64", out=None):
         return self._apply(self.ctx.lib.sapdd_apply_D, kappa, psi, prec, out)
 
-    def apply_block_D(self, kappa, psi, prec="f64", out=None):
-        return self._apply(self.ctx.lib.sapdd_apply_block_D, kappa, psi, prec, out)
+    def apply_block_D(self, kappa, psi, prec="f64", out=None, links12=False):
+        """M_B psi; links12: links read as their first two rows (FP32/FP16 storage)."""
+        return self._apply(self.ctx.lib.sapdd_apply_block_D, kappa, psi, prec, out, LINKS12 if links12 else 0)
 
     def params(self, nmr=4, ncy=5, restart=16, max_iter=1000, tol=1e-10, prec="f64", flags=0,
                deflate=0) -> Params:

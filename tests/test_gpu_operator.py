@@ -76,6 +76,29 @@ def test_block_operator(ctx, dims, block, prec):
     assert relerr(out[0], ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("dims,block", CASES)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_block_operator_two_row_links(ctx, dims, block, prec):
+    """Links read as their first two rows, the third rebuilt as the conjugate cross
+    product: same tolerance against the oracle's M_B as the 18-real links (the field's
+    links are special unitary to rounding)."""
+    print(f"block D two-row links {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    psi = synthetic.gaussian_source(dims, 2, 9)
+    out = f.apply_block_D(0.126, psi, prec=prec, links12=True)
+    for r in range(2):
+        ref = wilson.apply_M(u, t, 0.126, psi[r], block=block)
+        assert relerr(out[r], ref) <= TOL[prec]
+
+
+def test_two_row_links_reject_fp64(ctx):
+    from paper_1502_04025_amd import EINVAL, SapddError
+    u, t, f = setup_case(ctx, (4, 4, 4, 4), (2, 2, 2, 2))
+    with pytest.raises(SapddError) as e:
+        f.apply_block_D(0.126, synthetic.gaussian_source((4, 4, 4, 4), 1, 9), prec="f64", links12=True)
+    assert e.value.code == EINVAL
+
+
 def test_loaded_clover_equals_device_built(ctx):
     dims, block = (4, 4, 8, 4), (2, 2, 2, 2)
     u = synthetic.gauge_field(dims, 0.3, 9)

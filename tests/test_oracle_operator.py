@@ -176,3 +176,13 @@ def test_block_restricted_operator_matches_dense_blocks():
     same = bid[:, None] == bid[None, :]
     assert np.max(np.abs(mb - np.where(same, m, 0))) == 0.0
     assert np.max(np.abs(np.where(same, 0, m))) > 0  # there are hops between blocks
+
+
+def test_synthetic_links_are_special_unitary():
+    """The two-row link storage of the block operator rebuilds row 2 of every link as the
+    conjugate cross product of rows 0 and 1, which holds exactly for special unitary
+    matrices; the generator's links satisfy it to rounding (and U U^+ = 1, det U = 1)."""
+    u = synthetic.gauge_field((4, 4, 4, 4), 0.3, 5)
+    assert np.abs(np.conj(np.cross(u[..., 0, :], u[..., 1, :])) - u[..., 2, :]).max() < 1e-13
+    assert np.abs(u @ np.conj(np.swapaxes(u, -1, -2)) - np.eye(3)).max() < 1e-13
+    assert np.abs(np.linalg.det(u) - 1.0).max() < 1e-13

@@ -53,3 +53,13 @@ def test_mg_coarse_bytes_one_step():
     assert pm.mg_coarse_bytes(1, 2, 1) == nc + 9 * 4 * 8 + nc + 3 * nc + 3 * nc
     # two systems share the stencil and double everything else
     assert pm.mg_coarse_bytes(1, 2, 1, 2) == 2 * nc + 9 * 4 * 8 + 2 * (nc + 3 * nc + 3 * nc)
+
+
+def test_two_row_link_bytes():
+    """4 directions x 12 reals: FP32 192 bytes; FP16 96 bytes plus the 4-byte site scale.
+    On 4^4 blocks the block operator then reads 624 (FP32) and 327 (FP16) bytes per site
+    instead of 696 and 363."""
+    assert pm.LINK12_BYTES == {"f32": 4 * 12 * 4, "f16": 4 * 12 * 2 + 4}
+    assert pm.block_dslash_bytes((4, 4, 4, 4), "f32", links12=True) == 0.75 * 192 + 288 + 192
+    assert pm.block_dslash_bytes((4, 4, 4, 4), "f16", links12=True) == 0.75 * 100 + 148 + 104
+    assert pm.block_dslash_bytes((4, 4, 4, 4), "f32") == 696
