@@ -814,6 +814,9 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     G.sc = w.sc;
     G.beta = w.beta;
     G.coef = w.coef;
+    // one classical Gram-Schmidt pass per coarse step: a second pass left the outer step
+    // count unchanged on 16^3 x 32 (229 / 230 steps) and cost a quarter of the coarse time
+    G.reorth = 0;
     G.active = active;
     return G;
 }

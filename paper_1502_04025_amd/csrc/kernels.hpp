@@ -188,6 +188,7 @@ struct MgGmres {
     double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
     double *beta;      // [rhs] |rhs|
     double *coef;      // [rhs][MG_IMAX] complex: a cycle's correction = sum_i coef[i] basis[i]
+    int reorth;        // 1: classical Gram-Schmidt twice per step, 0: once
     const int *active;
 };
 void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc);

@@ -17,11 +17,12 @@
 //
 // The coarse system is solved by a fixed number of restarted GMRES cycles of a fixed
 // number of steps, from zero, entirely on the device so the whole preconditioner is one
-// static launch sequence: every Arnoldi step is three kernels (operator + first
-// Gram-Schmidt pass, second pass, norm), each reduction a fixed-order sum of
-// per-workgroup partials that every workgroup of the next kernel repeats for itself; one
-// wave per system solves the small least squares problem at the end of a cycle, and the
-// cycle's correction is added to the coarse solution, whose residual starts the next.
+// static launch sequence: every Arnoldi step is two kernels (operator + the dot products
+// of classical Gram-Schmidt, then correction + norm; a second Gram-Schmidt pass is
+// available), each reduction a fixed-order sum of per-workgroup partials that every
+// workgroup of the next kernel repeats for itself; one wave per system solves the small
+// least squares problem at the end of a cycle, and the cycle's correction is added to
+// the coarse solution, whose residual starts the next.
 #include "kernels.hpp"
 
 namespace sapdd {
@@ -602,11 +603,12 @@ __global__ __launch_bounds__(MG_AWG) void mg_capply_kernel(MgGmres G, int j) {
     wave_store<2 * MG_IMAX>(acc, 2 * (j + 1), pd_of(G, rhs, 0) + blockIdx.x, G.pstride);
 }
 
-// Arnoldi step j, pass 1 (second Gram-Schmidt pass) and pass 2 (correction + norm):
-// w -= sum_i h_i s_i v_i with h from the previous pass's partials; then either the
-// partials of <s_i v_i, w> (pass 1) or of |w|^2 (pass 2). Workgroup 0 adds h into
-// column j of the Hessenberg matrix.
-__global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int pass) {
+// Arnoldi step j, a correction pass: w -= sum_i h_i s_i v_i with h the totals of the
+// partials of pass `src` (0: the operator kernel's <s_i v_i, w>, 1: a second pass's);
+// then either the partials of <s_i v_i, w> for a further pass (norm = 0) or of |w|^2
+// (norm = 1). Workgroup 0 sets (src 0) or adds (src 1) h into column j of the
+// Hessenberg matrix.
+__global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int src, int norm) {
     __shared__ double h[2 * MG_IMAX];
     __shared__ double lds[(MG_GWG / 64) * 2 * MG_IMAX];
     const int rhs = G.active[blockIdx.y];
@@ -614,10 +616,10 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int pa
     const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
     const int64_t b = (int64_t)blockIdx.x * tc + bl;
     const bool act = bl < tc && b < G.Nd;
-    load_totals(pd_of(G, rhs, pass - 1), G.pstride, pass == 1 ? G.nwa : G.nwc, 2 * (j + 1), h);
+    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
     if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
         double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
-        Hc[threadIdx.x] = (pass == 1 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x];
+        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x];
     }
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
@@ -637,7 +639,7 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int pa
         yr = (double)(float)yr;
         yi = (double)(float)yi;
     }
-    if (pass == 1) {
+    if (!norm) {
         double acc[2 * MG_IMAX];
 #pragma unroll
         for (int i = 0; i < MG_IMAX; ++i) {
@@ -821,8 +823,12 @@ hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles,
         hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
         for (int j = 0; j < k; ++j) {
             hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
-            hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1);
-            hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 2);
+            if (G.reorth) {  // classical Gram-Schmidt twice
+                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 0, 0);
+                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1, 1);
+            } else {  // once
+                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 0, 1);
+            }
         }
         hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
         hipLaunchKernelGGL(mg_caccum_kernel, ge, dim3(256), 0, st, G, k, (int)(cyc == 0));

@@ -104,12 +104,12 @@ def mg_coarse_bytes(n_agg: int, K: int, k: int, nrhs: int = 1) -> float:
     """Algorithmic bytes of one coarse GMRES cycle of k steps for nrhs systems solved
     together (K coarse dofs per aggregate, FP32 complex, 8 bytes each): per step j the
     stencil (9 K x K blocks per aggregate, shared by all systems) and, per system, v_j for
-    the operator, basis vectors 0..j read by each of the three Gram-Schmidt reads (dots,
-    correction, correction) and the new vector written three times; the first vector of
-    each system read once for its norm."""
+    the operator, the new vector written, basis vectors 0..j read twice (dot products,
+    correction), the new vector read and written again by the correction; the first
+    vector of each system read once for its norm."""
     nc = n_agg * K * 8
     stencil = n_agg * 9 * K * K * 8
     total = nrhs * nc
     for j in range(k):
-        total += stencil + nrhs * (nc + 3 * (j + 1) * nc + 3 * nc)
+        total += stencil + nrhs * (2 * (j + 1) * nc + 4 * nc)
     return float(total)

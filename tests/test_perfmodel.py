@@ -47,12 +47,13 @@ def test_block_dslash_bytes_per_site():
 
 def test_mg_coarse_bytes_one_step():
     """One coarse step over one aggregate with K = 2: the first vector's norm, the stencil
-    (9 blocks of 2 x 2 complex FP32), v_0, three Gram-Schmidt reads of v_0 and three
-    writes of v_1, each vector 2 complex FP32 numbers."""
+    (9 blocks of 2 x 2 complex FP32), v_0 for the operator, the new vector written, two
+    Gram-Schmidt reads of v_0, the new vector read and written by the correction, each
+    vector 2 complex FP32 numbers."""
     nc = 2 * 8
-    assert pm.mg_coarse_bytes(1, 2, 1) == nc + 9 * 4 * 8 + nc + 3 * nc + 3 * nc
+    assert pm.mg_coarse_bytes(1, 2, 1) == nc + 9 * 4 * 8 + nc + nc + 2 * nc + 2 * nc
     # two systems share the stencil and double everything else
-    assert pm.mg_coarse_bytes(1, 2, 1, 2) == 2 * nc + 9 * 4 * 8 + 2 * (nc + 3 * nc + 3 * nc)
+    assert pm.mg_coarse_bytes(1, 2, 1, 2) == 2 * nc + 9 * 4 * 8 + 2 * (6 * nc)
 
 
 def test_two_row_link_bytes():
