@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -223,9 +224,14 @@ class Field:
 
     def __init__(self, ctx: Context, h, dims, block):
         self.ctx, self.h, self.dims, self.block = ctx, h, dims, block
+        self._deps = weakref.WeakSet()  # batches and multigrid objects built on this field
 
     def free(self):
+        """Free the field; batches and multigrid objects built on it are closed first (the
+        library requires that order)."""
         if self.h:
+            for d in list(self._deps):
+                d.close()
             self.ctx.lib.sapdd_free_field(self.ctx.h, self.h)
             self.h = None
 
@@ -327,6 +333,7 @@ class Batch:
                                                         C.byref(h)))
         self.h = h
         self.capacity = int(capacity)
+        field._deps.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -370,6 +377,7 @@ class Batch:
         right-hand side added later must use the multigrid's kappa)."""
         self.ctx._check(self.ctx.lib.sapdd_batch_set_mg(self.h, mg.h))
         self.mg = mg  # keeps the multigrid alive as long as the batch
+        mg._users.add(self)
 
     def take(self, slot: int, out):
         """Copy the solution of a slot into `out` (host array or device tensor), free it."""
@@ -398,9 +406,14 @@ class Multigrid:
         self.ctx._check(self.ctx.lib.sapdd_mg_setup(self.ctx.h, field.h, self.kappa, C.byref(prm), C.byref(mp), pv,
                                                     DEVICE_PTRS if dev else 0, C.byref(h)))
         self.h = h
+        self._users = weakref.WeakSet()  # batches that precondition with this multigrid
+        field._deps.add(self)
 
     def close(self):
+        """Destroy the multigrid; batches that precondition with it are closed first."""
         if getattr(self, "h", None):
+            for b in list(self._users):
+                b.close()
             self.ctx.lib.sapdd_mg_destroy(self.h)
             self.h = None
 

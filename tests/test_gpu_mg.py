@@ -208,6 +208,26 @@ def test_errors_are_reported(small):
     batch.close()
 
 
+def test_freeing_objects_closes_what_depends_on_them(ctx):
+    """Closing a multigrid closes the batches that precondition with it; freeing a field
+    closes its batches and multigrid objects (the library needs them gone first)."""
+    print("mg close order", flush=True)
+    from paper_1502_04025_amd import Batch, Multigrid
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    u, t, f, vecs = _setup(ctx, dims, block, seed=97, nvec=2)
+    mg = Multigrid(f, 0.128, vecs, coarse_iters=2, nmr=2, ncy=1, prec="f32")
+    batch = Batch(f, 1, nmr=2, ncy=1, restart=4)
+    batch.set_mg(mg)
+    mg.close()
+    assert batch.h is None and mg.h is None
+    mg2 = Multigrid(f, 0.128, vecs, coarse_iters=2, nmr=2, ncy=1, prec="f32")
+    batch2 = Batch(f, 1, nmr=2, ncy=1, restart=4)
+    batch3 = Batch(f, 1, nmr=2, ncy=1, restart=4)
+    batch3.set_mg(mg2)
+    f.free()
+    assert batch2.h is None and batch3.h is None and mg2.h is None and f.h is None
+
+
 def test_full_size_16x16x16x32_sampled_columns_and_solve(ctx):
     """16^3 x 32 with 8x4^3 aggregates and 8 test vectors: sampled block columns of D_c
     against the oracle's P^H M P e, gamma_5-Hermiticity of the whole stencil, and an FP32
