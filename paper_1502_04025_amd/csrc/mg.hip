@@ -545,6 +545,7 @@ __global__ __launch_bounds__(MG_AWG) void mg_capply_kernel(MgGmres G, int j) {
             const int64_t nb = mg_neighbour(G.grid, g, d);
             const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
             const float2 *x = vj + nb * K;
+#pragma unroll 8
             for (int c = 0; c < K; ++c) {
                 const float2 m = dcol[(int64_t)c * K], xv = x[c];
                 yr += (double)m.x * xv.x - (double)m.y * xv.y;
@@ -629,6 +630,7 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int sr
         const float2 w0 = w[b * K + a];
         yr = w0.x;
         yi = w0.y;
+#pragma unroll 4
         for (int i = 0; i <= j; ++i) {
             const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
             const double cr = h[2 * i] * sc[i], ci = h[2 * i + 1] * sc[i];
@@ -774,6 +776,7 @@ __global__ __launch_bounds__(MG_AWG) void mg_cres_kernel(MgGmres G, int first) {
             const int64_t nb = mg_neighbour(G.grid, g, d);
             const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
             const float2 *x = xc + nb * K;
+#pragma unroll 8
             for (int c = 0; c < K; ++c) {
                 const float2 m = dcol[(int64_t)c * K], xv = x[c];
                 yr += (double)m.x * xv.x - (double)m.y * xv.y;
