@@ -191,6 +191,23 @@ def test_batch_results_do_not_depend_on_the_batch(small):
     batch.close()
 
 
+def test_graph_replays_equal_direct_launches(small):
+    """The multigrid cycle inside the FGMRES batch replays from HIP graphs (one per slot
+    count and Arnoldi step, replayed every cycle); two graph solves in a row and a solve
+    without graphs give the same bits."""
+    print("mg graphs vs direct", flush=True)
+    from paper_1502_04025_amd import NO_GRAPH
+    b = synthetic.gaussian_source(small["dims"], 2, 61)
+    kw = dict(nmr=4, ncy=2, restart=4, tol=1e-10, prec="f32")
+    mg = small["mg"]
+    g1 = mg.solve(b, **kw).x.copy()
+    g2 = mg.solve(b, **kw).x.copy()
+    d = mg.solve(b, flags=NO_GRAPH, **kw)
+    assert all(st["converged"] for st in d.stats)
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(g1, d.x)
+
+
 def test_errors_are_reported(small):
     from paper_1502_04025_amd import Batch, Multigrid, SapddError, EINVAL
     f = small["f"]
