@@ -14,8 +14,10 @@ per block solve and 8 Schwarz cycles per preconditioner application.
 Printed: one JSON line with solves/s (RHS solves per second), p50/p99 solve latency, the
 roofline of the dominant kernel (per-kernel HIP-event times measured on the solve's
 stream during the timed steps), the block-Dslash bandwidth on the 32^3 x 64 lattice
-(FP16 storage, working set far above the 256 MB Infinity Cache), the all-FP64 path on
-the same problem, and the CPU oracle timed on a bounded sample of the same solve.
+(FP16 and FP32 storage, 18-real and two-row links; working set far above the 256 MB
+Infinity Cache), the two-level multigrid against SAP alone on one right-hand side near
+the critical kappa, the all-FP64 path on the same problem, and the CPU oracle timed on a
+bounded sample of the same solve.
 """
 from __future__ import annotations
 
@@ -158,6 +160,43 @@ def dslash_bandwidth(ctx, warm=10, reps=100):
             algorithmic_bytes_per_launch=byts, traffic=profiled_traffic(f"{kname} 32x32x32x64 4x4x4x4 {prec}"))
     f.free()
     return dict(kernel="dslash_block_kernel", lattice="32x32x32x64", block=list(cfg["block"]), **res)
+
+
+def mg_extra(ctx):
+    """One Gaussian RHS on the default workload's field at kappa 0.145 (near critical):
+    the two-level multigrid of `--workload mg` against SAP alone, one timed solve each
+    after a warm-up."""
+    import torch
+
+    import synthetic
+    from paper_1502_04025_amd import Multigrid
+    cfg = dict(synthetic.CONFIGS["c2_16x16x16x32_f32"])
+    mc = dict(MG_RUN)
+    u, f = make_field(ctx, cfg)
+    del u
+    b = torch.from_numpy(synthetic.gaussian_source(cfg["dims"], 1, cfg["source_seed"])).cuda()
+    x = torch.empty_like(b)
+    vecs = synthetic.gaussian_source(cfg["dims"], mc["nvec"], mc["vec_seed"])
+    kw = dict(nmr=mc["nmr"], ncy=mc["ncy"], restart=mc["restart"], tol=1e-10, prec=mc["prec"], max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = Multigrid(f, mc["kappa"], vecs, setup_iters=mc["setup_iters"], coarse_iters=mc["coarse_iters"],
+                   coarse_cycles=mc["coarse_cycles"], nmr=mc["nmr"], ncy=mc["ncy"], prec=mc["prec"])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    out = {"workload": f"16x16x16x32, kappa {mc['kappa']}, 1 gaussian RHS (see --workload mg)",
+           "setup_s": round(setup_s, 3)}
+    for name, step in (("mg", lambda: mg.solve(b, x=x, **kw)), ("sap_only", lambda: f.solve(mc["kappa"], b, x=x, **kw))):
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = step()
+        torch.cuda.synchronize()
+        out[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 2), "outer_iters": r.stats[0]["iters"],
+                     "converged": bool(r.stats[0]["converged"])}
+    mg.close()
+    f.free()
+    return out
 
 
 def copy_bandwidth(ctx, nbytes=1 << 31, reps=10):
@@ -549,6 +588,10 @@ def main():
         except Exception as e:  # report, do not hide the main number
             line["dslash"] = {"error": str(e)}
         line["copy_GB_s"] = copy_bandwidth(ctx)
+        try:
+            line["mg_near_critical"] = mg_extra(ctx)
+        except Exception as e:  # report, do not hide the main number
+            line["mg_near_critical"] = {"error": str(e)}
         for key in ("f16", "f32", "f16_links12", "f32_links12"):  # also as a fraction of the copy bandwidth
             if isinstance(line["dslash"].get(key), dict):
                 line["dslash"][key]["frac_of_copy"] = round(line["dslash"][key]["GB_s"] / line["copy_GB_s"], 4)
