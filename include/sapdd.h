@@ -227,7 +227,9 @@ int sapdd_mg_precond(sapdd_mg *mg, int nrhs, const double *in, double *out, int 
 /* Solve M x = b (the multigrid's kappa) with FGMRES(params->restart) preconditioned by B:
  * the batch solver with the multigrid cycle in place of the plain SAP application, its
  * smoother set by params (nmr, ncy, sap_prec). Same arguments and results as
- * sapdd_solve; the multigrid object keeps the batch for later calls. */
+ * sapdd_solve; the multigrid object keeps the batch for later calls. Near the critical
+ * kappa keep ncy small (1-2): every further SAP cycle per application amplifies the
+ * slowest modes again (measured: 44 outer steps at ncy 2, no convergence at ncy 5). */
 int sapdd_mg_solve(sapdd_mg *mg, const sapdd_params *params, int nrhs, const double *b, double *x,
                    sapdd_stats *stats);
 /* Make a batch (no slot in use) precondition with mg instead of SAP; every RHS added
