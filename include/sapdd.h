@@ -88,6 +88,13 @@ typedef struct {
                      * matrix, those of smallest modulus, are kept across each full
                      * restart (0 = plain restarts; 0 <= k < restart). With k > 0 the
                      * preconditioned vectors Z are held in FP64 whatever sap_prec is.  */
+    double gap;     /* reliable-update gap (0 = 10): at the end of every restart cycle
+                     * the FP64 true residual |b - M x| is compared with the cycle's
+                     * implicit one (the least-squares residual the Arnoldi relation
+                     * carries); when true > gap * implicit the implicit residual is not
+                     * trusted and the next cycle restarts plainly from the true
+                     * residual, dropping a deflated basis (counted in
+                     * sapdd_stats.gap_restarts).                                       */
 } sapdd_params;
 
 /* Per right-hand-side result of sapdd_solve. Times are seconds of device time
@@ -101,6 +108,7 @@ typedef struct {
     double implicit_relres; /* least-squares residual estimate at the last step      */
     double t_total;         /* wall time of the call                                 */
     double t_sap, t_dslash, t_gs, t_host;
+    int gap_restarts;       /* cycles whose true residual exceeded gap x implicit    */
 } sapdd_stats;
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t;
@@ -110,40 +118,63 @@ void sapdd_destroy(sapdd_ctx *ctx);
 /* Message of the last failed call on ctx ("" if none). Valid until the next call. */
 const char *sapdd_last_error(const sapdd_ctx *ctx);
 
-/* Upload a gauge field (canonical links) and fix its device layout: the lattice is tiled
+/* Sec. 3.2 (data layout) and Sec. 3.5 (two-coloured domains): upload a gauge field
+ * (canonical links, host or device per flags, copied into library-owned memory freed by
+ * sapdd_free_field) and fix its device layout: the lattice is tiled
  * by Schwarz blocks of extents block[] (each even and >= 2, dividing dims, with an even
  * number of blocks per direction so the blocks two-colour the lattice, Sec. 3.5 footnote).
  * Supported block shapes: 2x2x2x2, 4x4x4x4, 8x4x4x4. The clover term starts at zero. */
 int sapdd_load_gauge(sapdd_ctx *ctx, const int dims[4], const int block[4], const double *links,
                      int antiperiodic_t, int flags, sapdd_field **out);
-/* Build T(x) on the device from the resident links with coefficient c_sw >= 0. */
+/* Sec. 3.1 (the operator is Wilson-clover): build the clover term T(x) on the device from
+ * the resident links, with coefficient c_sw >= 0, in the form stated at the top of this
+ * header (four same-orientation plaquette leaves per plane, traceless F). Replaces any
+ * clover loaded before and drops the field's derived low-precision and per-kappa copies.
+ * EINVAL for c_sw < 0 or a null argument; EDEVICE on a HIP error. */
 int sapdd_compute_clover(sapdd_ctx *ctx, sapdd_field *field, double csw);
-/* Upload T(x) (canonical clover layout). Only the two chiral 6x6 blocks (spins 0-1 and
- * 2-3) are used; the entries coupling them must be zero in the Dirac basis above. */
+/* Sec. 3.1 (Wilson-clover operator): upload a caller-made T(x) (canonical clover layout,
+ * FP64 host or device array per flags, copied; the caller keeps ownership). Only the two
+ * chiral 6x6 blocks (spins 0-1 and 2-3) are read; the entries coupling them must be zero
+ * in the Dirac basis above. EINVAL for a null argument; EDEVICE on a HIP error. */
 int sapdd_load_clover(sapdd_ctx *ctx, sapdd_field *field, const double *clover, int flags);
 /* Free a field. The context's kept sapdd_solve batch on it goes with it; batches and
  * multigrid objects the caller made on the field must be destroyed first. */
 int sapdd_free_field(sapdd_ctx *ctx, sapdd_field *field);
 
-/* out = M in for nrhs canonical spinors, with links, clover and spinors held in storage
- * precision `prec` (arithmetic in FP64 for SAPDD_F64, FP32 otherwise). in and out may
- * not overlap. */
+/* Sec. 3.1 (the Wilson-clover operator M the solver inverts; Sec. 3.7 counts it at 1848
+ * flop per site): out = M in for nrhs canonical spinors ([nrhs][t][z][y][x][4][3]
+ * complex128, host or device per flags), with links, clover and spinors held in storage
+ * precision `prec` (arithmetic in FP64 for SAPDD_F64, FP32 otherwise; SAPDD_F16 stores
+ * every site with one FP32 scale, the half-precision storage of Sec. 3.3). in and out
+ * may not overlap; the caller owns both. EINVAL for nrhs < 1, a bad precision or a null
+ * argument; ENOMEM if a workspace cannot be allocated. */
 int sapdd_apply_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec, int nrhs,
                   const double *in, double *out, int flags);
-/* out = M_B in: M with every hop between two different Schwarz blocks removed (the
- * block-diagonal part of the splitting in Sec. 3.1), same arguments as sapdd_apply_D.
+/* Sec. 3.1 (the splitting of M into its block-diagonal part and the remainder): out =
+ * M_B in, M with every hop between two different Schwarz blocks removed; same arguments,
+ * layouts, ownership and errors as sapdd_apply_D.
  * With SAPDD_LINKS12 in flags (FP32 or FP16 only) every link is read as its first two
  * rows and the third is rebuilt as the complex conjugate of their cross product: a third
  * fewer link bytes, exact for special unitary links (the library does not check that).
  * The two-row copy is made on first use and kept with the field. */
 int sapdd_apply_block_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, int prec,
                         int nrhs, const double *in, double *out, int flags);
-/* out = SAP(in): params->ncy cycles of MR block solves over colour 0 then colour 1,
- * FP64 canonical in and out, internal storage params->sap_prec. */
-int sapdd_sap(sapdd_ctx *ctx, const sapdd_field *field, double kappa, const sapdd_params *params,
+/* Sec. 3.1 (the multiplicative Schwarz preconditioner: red/black domains, each solved
+ * approximately by MR with even-odd preconditioning) and Sec. 3.3 (half-precision
+ * storage): out = SAP(in), params->ncy cycles of params->nmr MR steps per block solve over
+ * colour 0 then colour 1, starting from zero; kappa[nrhs] may differ per right-hand side
+ * (all of them share every launch). in and out: nrhs canonical spinors (FP64,
+ * host or device per params->flags, caller-owned, not overlapping); storage inside the
+ * sweep params->sap_prec (SAPDD_F16: one FP32 scale per site), arithmetic FP32 below FP64.
+ * EINVAL for bad params (block differs from the field's, nmr or ncy < 1) or kappa <= 0; ESINGULAR if
+ * 1 + kappa T is singular on some site; ENOMEM if a workspace cannot be allocated. */
+int sapdd_sap(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa, const sapdd_params *params,
               int nrhs, const double *in, double *out);
-/* Solve M x = b for nrhs right-hand sides with SAP-preconditioned FGMRES(m) in FP64
- * (a batch of nrhs slots stepped to completion; the context keeps it for later calls).
+/* Sec. 3.1 (the outer flexible GMRES, preconditioned by the Schwarz procedure, in FP64
+ * with lower-precision preconditioning, Sec. 3.3): solve M x = b for nrhs right-hand
+ * sides with SAP-preconditioned FGMRES(m) (a batch of nrhs slots stepped to completion;
+ * the context keeps it for later calls). b and x: canonical spinors, host or device per
+ * params->flags, caller-owned; every RHS finishes on its FP64 true residual.
  * kappa[nrhs] may differ per RHS. x holds nrhs canonical spinors (read as the start
  * vector if SAPDD_USE_X0). stats may be NULL, else it has nrhs entries. Returns
  * SAPDD_ENOCONV if some RHS missed tol within max_iter. */

@@ -6,7 +6,7 @@ preconditioner it wraps is the Schwarz procedure, which is not a fixed linear ma
 implements the plain restarted flexible GMRES of Saad (1993) without deflation:
 
   restart:  r = b - M x, beta = |r|; stop if beta <= tol |b|; v_1 = r / beta
-  step j:   z_j = P(v_j)   (optionally rounded to the precision Z is stored in)
+  step j:   z_j = P(v_j)
             w = M z_j, orthogonalised against v_1..v_j by modified Gram-Schmidt
             h_{j+1,j} = |w|, v_{j+1} = w / h_{j+1,j}
             y_j = argmin |beta e_1 - Hbar_j y| (numpy.linalg.lstsq)
@@ -40,8 +40,7 @@ def _dot(a, b):
     return np.vdot(a.reshape(-1), b.reshape(-1))
 
 
-def fgmres(apply_m, precond, b, m=16, tol=1e-10, max_iter=2000, x0=None,
-           z_dtype=None, record=None):
+def fgmres(apply_m, precond, b, m=16, tol=1e-10, max_iter=2000, x0=None, record=None):
     """Solve M x = b. Returns (x, info) with info = dict(iters, restarts, relres,
     converged, history). `record`, if a dict, receives the last cycle's V, Z, Hbar."""
     bnorm = float(np.linalg.norm(b))
@@ -68,8 +67,6 @@ def fgmres(apply_m, precond, b, m=16, tol=1e-10, max_iter=2000, x0=None,
         y = None
         for j in range(m):
             z = precond(vs[j])
-            if z_dtype is not None:
-                z = z.astype(z_dtype).astype(np.complex128)
             zs.append(z)
             w = apply_m(z)
             for i in range(j + 1):
@@ -93,8 +90,7 @@ def fgmres(apply_m, precond, b, m=16, tol=1e-10, max_iter=2000, x0=None,
         restarts += 1
 
 
-def fgmres_dr(apply_m, precond, b, m=16, k=2, tol=1e-10, max_iter=2000, x0=None,
-              z_dtype=None, record=None):
+def fgmres_dr(apply_m, precond, b, m=16, k=2, tol=1e-10, max_iter=2000, x0=None, record=None):
     """Solve M x = b with FGMRES-DR(m, k). Returns (x, info) as fgmres. `record`, if a
     dict, receives the last cycle's V, Z, Hbar, the coefficient vector c of its start,
     and the harmonic Ritz values of every deflated restart (list `theta`)."""
@@ -121,8 +117,6 @@ def fgmres_dr(apply_m, precond, b, m=16, k=2, tol=1e-10, max_iter=2000, x0=None,
         y = None
         for j in range(j0, m):
             z = precond(vs[j])
-            if z_dtype is not None:
-                z = z.astype(z_dtype).astype(np.complex128)
             zs.append(z)
             w = apply_m(z)
             for i in range(j + 1):

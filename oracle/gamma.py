@@ -26,7 +26,3 @@ GAMMA5 = GAMMA[0] @ GAMMA[1] @ GAMMA[2] @ GAMMA[3]
 
 ONE = np.eye(4, dtype=np.complex128)
 
-
-def sigma(mu: int, nu: int) -> np.ndarray:
-    """sigma_mu,nu = (i/2)[gamma_mu, gamma_nu]."""
-    return 0.5j * (GAMMA[mu] @ GAMMA[nu] - GAMMA[nu] @ GAMMA[mu])

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -344,6 +345,7 @@ int check_params(sapdd_ctx *c, const sapdd_field *f, const sapdd_params *p) {
                 return fail(c, SAPDD_EINVAL, "params.block differs from the field's blocking");
     if (p->nmr < 1 || p->ncy < 1) return fail(c, SAPDD_EINVAL, "nmr and ncy must be >= 1");
     if (p->sap_prec < SAPDD_F64 || p->sap_prec > SAPDD_F16) return fail(c, SAPDD_EINVAL, "bad sap_prec");
+    if (!(p->gap >= 0)) return fail(c, SAPDD_EINVAL, "gap must be >= 0 (0 = the default 10)");
     return SAPDD_OK;
 }
 
@@ -506,8 +508,9 @@ int sapdd_load_gauge(sapdd_ctx *c, const int dims[4], const int block[4], const 
     g.antiperiodic = antiperiodic_t ? 1 : 0;
     if ((g.Nd / 2) > 0x7fffffffLL || g.V * 24 > (1LL << 40)) return fail(c, SAPDD_EINVAL, "lattice too large");
     sapdd_field *f = new sapdd_field;
-    static unsigned long long next_field_id = 0;
-    f->id = ++next_field_id;
+    // fields may be loaded from several host threads (one context each)
+    static std::atomic<unsigned long long> next_field_id{0};
+    f->id = next_field_id.fetch_add(1) + 1;
     f->geo = g;
     hipError_t e1 = hipMalloc((void **)&f->links64, (size_t)g.V * 72 * 8);
     hipError_t e2 = e1 == hipSuccess ? hipMalloc((void **)&f->tclov64, (size_t)g.V * 72 * 8) : e1;
@@ -648,9 +651,9 @@ int sapdd_apply_block_D(sapdd_ctx *c, const sapdd_field *f, double kappa, int pr
     return apply_common(c, f, kappa, prec, nrhs, in, out, flags, true);
 }
 
-int sapdd_sap(sapdd_ctx *c, const sapdd_field *fc, double kappa, const sapdd_params *p, int nrhs, const double *in,
-              double *out) {
-    if (!c || !fc || !in || !out) return fail(c, SAPDD_EINVAL, "null argument");
+int sapdd_sap(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const sapdd_params *p, int nrhs,
+              const double *in, double *out) {
+    if (!c || !fc || !kappa || !in || !out) return fail(c, SAPDD_EINVAL, "null argument");
     if (nrhs < 1) return fail(c, SAPDD_EINVAL, "nrhs must be >= 1");
     c->err.clear();
     HIPCHK(c, hipSetDevice(c->device));
@@ -660,9 +663,10 @@ int sapdd_sap(sapdd_ctx *c, const sapdd_field *fc, double kappa, const sapdd_par
     const size_t nd = (size_t)g.V * 24 * nrhs;
     const int prec = p->sap_prec;
     const int psi_prec = prec == P64 ? P64 : P32;
-    std::vector<double> kap(nrhs, kappa);
+    for (int r = 0; r < nrhs; ++r)
+        if (!(kappa[r] > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
     SapState s;
-    CHK(sap_prepare(c, f, kap.data(), nrhs, prec, &s));
+    CHK(sap_prepare(c, f, kappa, nrhs, prec, &s));
     const double *src;
     CHK(stage_in(c, "stage_in", in, nd, p->flags, &src));
     Fld eta, psi;
@@ -873,7 +877,7 @@ typedef std::complex<double> cd;
 struct Slot {
     bool used = false, finished = false, ready = false, dirty = false, in_cycle = false;
     double kappa = 0, bnorm = 0, beta = 0, est = 0, true_relres = 0;
-    int iters = 0, restarts = 0, converged = 0, nz = 0, status = SAPDD_OK;
+    int iters = 0, restarts = 0, converged = 0, nz = 0, status = SAPDD_OK, gap_restarts = 0;
     std::vector<cd> H, cs, sn, gv;  // Hessenberg matrix as the Givens rotations leave it
     // Deflated restarts: Hr is the cycle's Hbar as built ((m+1) x m, column-major), c0 the
     // coordinates of the residual in the basis at the cycle start, j0 the first Arnoldi
@@ -996,12 +1000,34 @@ int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     B->t_d += ms * 1e-3;
+    // reliable update: the implicit residual of the cycle that just ended is the
+    // least-squares residual (its norm est * |b|), or for a slot continuing a deflated
+    // basis the recursive residual V c0 (norm |c0|, V orthonormal)
+    const double gap = B->p.gap > 0 ? B->p.gap : 10.0;
+    std::vector<int> redo;
     for (int r : list) {
         Slot &s = B->slots[r];
         s.dirty = false;
         s.beta = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
         s.true_relres = s.beta / s.bnorm;
         s.ready = false;
+        double implicit = -1;
+        if (s.deflated) {
+            double q = 0;
+            for (const cd &v : s.c0) q += std::norm(v);
+            implicit = std::sqrt(q);
+        } else if (s.restarts > 0) {
+            implicit = s.est * s.bnorm;
+        }
+        if (implicit >= 0 && std::isfinite(s.beta) && s.beta > gap * implicit) {
+            s.gap_restarts += 1;
+            if (s.deflated && s.true_relres > B->p.tol && s.iters < B->p.max_iter) {
+                // restart now from the true residual, computed into basis vector 0 below
+                s.deflated = false;
+                redo.push_back(r);
+                continue;
+            }
+        }
         if (!std::isfinite(s.beta)) {
             s.status = SAPDD_ENAN;
             s.finished = true;
@@ -1015,6 +1041,7 @@ int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
             s.ready = true;
         }
     }
+    if (!redo.empty()) return batch_residual(B, redo);
     return SAPDD_OK;
 }
 
@@ -1641,6 +1668,7 @@ int sapdd_batch_poll(const sapdd_batch *B, int slot, sapdd_stats *st) {
         st->t_dslash = B->t_d;
         st->t_gs = B->t_gs;
         st->t_host = B->t_host;
+        st->gap_restarts = s.gap_restarts;
     }
     return s.finished ? 1 : 0;
 }
@@ -1707,6 +1735,7 @@ int batch_solve_all(sapdd_batch *B, const double *kappa, const sapdd_params *p, 
     sapdd_ctx *c = B->c;
     B->p.tol = p->tol;
     B->p.max_iter = p->max_iter;
+    B->p.gap = p->gap;
     B->t_sap = B->t_d = B->t_gs = B->t_host = 0;
     const size_t NS = (size_t)B->NS;
     std::vector<int> slot(nrhs);

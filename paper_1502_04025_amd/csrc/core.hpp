@@ -126,6 +126,11 @@ __device__ __forceinline__ void load_site(const S *__restrict__ data, const floa
     load_reals<R, N, 0, N, S, false, NT>(data, scale, bp, s, Vbh, out);
 }
 
+// Reciprocal of an FP16 site scale m (the site's max |value|). A site whose maximum lies
+// below the smallest normal float is stored as zero with scale 0: 1/m would overflow to
+// +inf there, and 0 * inf = NaN would poison the whole site.
+__host__ __device__ __forceinline__ float fp16_site_inv(float m) { return m >= 1.17549435e-38f ? 1.0f / m : 0.f; }
+
 // Store N reals of one site; FP16 storage divides by the site's max |value| and rounds
 // to nearest even (scale 0 stores zeros).
 template <class R, int N, class S, bool NT = false>
@@ -138,8 +143,8 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < N; ++k) m = fmaxf(m, fabsf((float)in[k]));
-        scale[bp * Vbh + s] = m;
-        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        const float inv = fp16_site_inv(m);
+        scale[bp * Vbh + s] = inv > 0.f ? m : 0.f;
 #pragma unroll
         for (int v = 0; v < N / W; ++v) {
             VT x;

@@ -48,7 +48,7 @@ class SapddError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("nmr", C.c_int), ("ncy", C.c_int), ("restart", C.c_int),
                 ("max_iter", C.c_int), ("tol", C.c_double), ("sap_prec", C.c_int), ("flags", C.c_int),
-                ("deflate", C.c_int)]
+                ("deflate", C.c_int), ("gap", C.c_double)]
 
 
 class MgParams(C.Structure):
@@ -68,7 +68,7 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("true_relres", C.c_double), ("implicit_relres", C.c_double),
                 ("t_total", C.c_double), ("t_sap", C.c_double), ("t_dslash", C.c_double),
-                ("t_gs", C.c_double), ("t_host", C.c_double)]
+                ("t_gs", C.c_double), ("t_host", C.c_double), ("gap_restarts", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,7 +101,7 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_free_field.argtypes = [VP, VP]
     lib.sapdd_apply_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
     lib.sapdd_apply_block_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
-    lib.sapdd_sap.argtypes = [VP, VP, D, P(Params), I, VP, VP]
+    lib.sapdd_sap.argtypes = [VP, VP, P(D), P(Params), I, VP, VP]
     lib.sapdd_solve.argtypes = [VP, VP, P(D), P(Params), I, VP, VP, P(Stats)]
     lib.sapdd_solve_footprint.argtypes = [VP, P(Params), I]
     lib.sapdd_solve_footprint.restype = C.c_longlong
@@ -271,7 +271,7 @@ class Field:
         return self._apply(self.ctx.lib.sapdd_apply_block_D, kappa, psi, prec, out, LINKS12 if links12 else 0)
 
     def params(self, nmr=4, ncy=5, restart=16, max_iter=1000, tol=1e-10, prec="f64", flags=0,
-               deflate=0) -> Params:
+               deflate=0, gap=0.0) -> Params:
         p = Params()
         for i in range(4):
             p.block[i] = self.block[i]
@@ -279,17 +279,21 @@ class Field:
         p.sap_prec = PRECS[prec] if isinstance(prec, str) else int(prec)
         p.flags = flags
         p.deflate = deflate
+        p.gap = float(gap)
         return p
 
     def sap(self, kappa, psi, out=None, **kw):
+        """SAP(psi); kappa is a float or one value per right-hand side."""
         prm = self.params(**kw)
+        nrhs = self._nrhs(psi)
+        kap = np.broadcast_to(np.asarray(kappa, dtype=np.float64), (nrhs,)).copy()
         out = _empty_like(psi) if out is None else out
         pi, dev = _ptr(psi)
         po, _ = _ptr(out, writable=True)
         if dev:
             prm.flags |= DEVICE_PTRS
-        self.ctx._check(self.ctx.lib.sapdd_sap(self.ctx.h, self.h, float(kappa), C.byref(prm), self._nrhs(psi),
-                                               pi, po))
+        self.ctx._check(self.ctx.lib.sapdd_sap(self.ctx.h, self.h, kap.ctypes.data_as(C.POINTER(C.c_double)),
+                                               C.byref(prm), nrhs, pi, po))
         return out
 
     def footprint(self, nrhs=1, **kw) -> int:

@@ -12,15 +12,24 @@ Canonical layouts (all complex128, x fastest):
 
 Gauge fields follow the recipe of the benchmark configurations: every link is
 U = exp(i * eps * H) with H a traceless Hermitian 3x3 matrix whose underlying complex
-entries are i.i.d. standard normal, drawn from numpy's default_rng(seed) in the order
-site index ascending, then mu = 0..3. The exponential is taken through the eigen
-decomposition of H.
+entries are i.i.d. standard normal; the exponential is taken through the eigen
+decomposition of H. Random numbers come from numpy's default_rng in fixed site chunks of
+CHUNK sites: chunk k of a field draws from the k-th child of SeedSequence(seed) (sites
+ascending, then mu = 0..3, inside the chunk), so any chunk can be drawn on its own and
+the result does not depend on how many worker processes draw the chunks. Gaussian
+sources do the same per right-hand side: source r draws from the r-th child of
+SeedSequence(seed), chunk k of it from that child's k-th child.
 """
 from __future__ import annotations
+
+import concurrent.futures as cf
+import multiprocessing as mp
+import os
 
 import numpy as np
 
 __all__ = [
+    "CHUNK",
     "CONFIGS",
     "gauge_field",
     "gaussian_source",
@@ -28,6 +37,8 @@ __all__ = [
     "random_su3",
     "serving_requests",
 ]
+
+CHUNK = 1 << 16  # sites per random-number chunk
 
 
 def _exp_i_eps_h(g: np.ndarray, eps: float) -> np.ndarray:
@@ -37,37 +48,84 @@ def _exp_i_eps_h(g: np.ndarray, eps: float) -> np.ndarray:
     h = h - tr[..., None, None] * np.eye(3)
     lam, v = np.linalg.eigh(h)
     ph = np.exp(1j * eps * lam)
-    return np.einsum("...ab,...b,...cb->...ac", v, ph, np.conj(v))
+    return (v * ph[..., None, :]) @ np.conj(np.swapaxes(v, -1, -2))
 
 
-def gauge_field(dims, eps: float, seed: int, chunk_sites: int = 1 << 18, progress=None) -> np.ndarray:
+def _link_chunk(seq, n: int, eps: float) -> np.ndarray:
+    g = np.random.default_rng(seq).standard_normal((n, 4, 3, 3, 2))
+    return _exp_i_eps_h(g[..., 0] + 1j * g[..., 1], eps)
+
+
+def _normal_chunk(seq, n: int) -> np.ndarray:
+    g = np.random.default_rng(seq).standard_normal((n, 4, 3, 2))
+    return g[..., 0] + 1j * g[..., 1]
+
+
+def _workers(vol: int, workers):
+    if workers is not None:
+        return max(1, int(workers))
+    if vol < (1 << 20):
+        return 1
+    # forked workers only draw random numbers; eight at most keeps the process count of a
+    # GPU job low even when the parent already holds the device
+    return max(1, min(8, len(os.sched_getaffinity(0))))
+
+
+def _fill(out: np.ndarray, jobs, fn, workers: int, progress=None, total: int = 0):
+    """out[s0:s0 + n] = fn(*args) for every (s0, n, args) job, in worker processes if
+    workers > 1 (fork: the children only compute and send back their chunk)."""
+    done = 0
+    if workers == 1:
+        for s0, n, args in jobs:
+            out[s0:s0 + n] = fn(*args)
+            done += n
+            if progress is not None:
+                progress(done, total)
+        return
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        futs = {ex.submit(fn, *args): (s0, n) for s0, n, args in jobs}
+        for f in cf.as_completed(futs):
+            s0, n = futs[f]
+            out[s0:s0 + n] = f.result()
+            done += n
+            if progress is not None:
+                progress(done, total)
+
+
+def gauge_field(dims, eps: float, seed: int, workers=None, progress=None) -> np.ndarray:
     """Random SU(3) gauge field U[t,z,y,x,mu,3,3] for lattice dims = (Lx, Ly, Lz, Lt).
 
-    Links are generated in site chunks; numpy's Generator produces the same stream
-    whether the normals are drawn at once or chunk by chunk, so the result does not
-    depend on chunk_sites. `progress(done_sites, total_sites)` is called after every
-    chunk if given.
+    `workers` processes draw the chunks (default: one below 2^20 sites, else up to eight);
+    the field is the same for every worker count. `progress(done_sites, total_sites)` is
+    called after every chunk if given.
     """
     lx, ly, lz, lt = (int(d) for d in dims)
     vol = lx * ly * lz * lt
-    rng = np.random.default_rng(seed)
+    kids = np.random.SeedSequence(seed).spawn((vol + CHUNK - 1) // CHUNK)
     out = np.empty((vol, 4, 3, 3), dtype=np.complex128)
-    for s0 in range(0, vol, chunk_sites):
-        n = min(chunk_sites, vol - s0)
-        g = rng.standard_normal((n, 4, 3, 3, 2))
-        gc = g[..., 0] + 1j * g[..., 1]
-        out[s0:s0 + n] = _exp_i_eps_h(gc, eps)
-        if progress is not None:
-            progress(s0 + n, vol)
+    jobs = [(k * CHUNK, min(CHUNK, vol - k * CHUNK), (kid, min(CHUNK, vol - k * CHUNK), eps))
+            for k, kid in enumerate(kids)]
+    _fill(out, jobs, _link_chunk, _workers(vol, workers), progress, vol)
     return out.reshape(lt, lz, ly, lx, 4, 3, 3)
 
 
-def gaussian_source(dims, nrhs: int, seed: int) -> np.ndarray:
-    """Gaussian spinors psi[rhs,t,z,y,x,4,3], Re and Im i.i.d. N(0,1) per component."""
+def gaussian_source(dims, nrhs: int, seed: int, rhs=None, workers=None) -> np.ndarray:
+    """Gaussian spinors psi[rhs,t,z,y,x,4,3], Re and Im i.i.d. N(0,1) per component.
+
+    `rhs` (a list of indices) draws only those right-hand sides of the nrhs, equal to the
+    same entries of the full set."""
     lx, ly, lz, lt = (int(d) for d in dims)
-    rng = np.random.default_rng(seed)
-    g = rng.standard_normal((nrhs, lt, lz, ly, lx, 4, 3, 2))
-    return g[..., 0] + 1j * g[..., 1]
+    vol = lx * ly * lz * lt
+    which = list(range(nrhs)) if rhs is None else [int(r) for r in rhs]
+    kids = np.random.SeedSequence(seed).spawn(nrhs)
+    out = np.empty((len(which) * vol, 4, 3), dtype=np.complex128)
+    jobs = []
+    for i, r in enumerate(which):
+        for k, kid in enumerate(kids[r].spawn((vol + CHUNK - 1) // CHUNK)):
+            n = min(CHUNK, vol - k * CHUNK)
+            jobs.append((i * vol + k * CHUNK, n, (kid, n)))
+    _fill(out, jobs, _normal_chunk, _workers(vol * len(which), workers))
+    return out.reshape(len(which), lt, lz, ly, lx, 4, 3)
 
 
 def point_sources(dims, origin=(0, 0, 0, 0)) -> np.ndarray:

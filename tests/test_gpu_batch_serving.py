@@ -101,6 +101,18 @@ def test_serving_loop_results_equal_alone(env):
                 torch.cuda.synchronize()
                 assert torch.equal(alone[0], r.x[i])
                 assert r.stats[i]["converged"] and r.stats[i]["true_relres"] <= 1e-10
+    # every served solution reaches 1e-10 by the oracle's own FP64 operator
+    fields = {0: ((8, 8, 8, 8), 5), 1: ((8, 8, 8, 16), 6)}
+    ops = {}
+    for k, (dims, seed) in fields.items():
+        u = synthetic.gauge_field(dims, 0.3, seed)
+        ops[k] = (u, wilson.clover_term(u, 1.0))
+    for r in done:
+        u, t = ops[r.vol]
+        bs = vols[r.vol].make_source(r)
+        for i in range(r.nrhs):
+            rel = oracle_relres(u, t, r.kappa, r.x[i].cpu().numpy(), bs[i].cpu().numpy())
+            assert rel <= 1e-10, (r.id, i, rel)
     s = sv.summarize(done, wall=max(r.t_done for r in done))
     assert s["requests"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0
     for v in vols:

@@ -90,3 +90,31 @@ def test_deflation_parameter_checked(ctx):
             f.solve(0.12, b, restart=4, deflate=k, prec="f64")
         assert e.value.code == EINVAL
     f.free()
+
+
+def test_reliable_update_gap_forces_plain_restarts(ctx):
+    """The reliable-update gap rule: when a cycle's FP64 true residual exceeds gap times
+    the implicit residual the Arnoldi relation carries, the next cycle restarts plainly
+    from the true residual and drops the deflated basis. Forcing the rule on every cycle
+    (gap 1e-300, any nonzero true residual exceeds it) turns FGMRES-DR(4, 2) into plain
+    FGMRES(4): the same iterate bit for bit, one gap restart per cycle after the first
+    deflated one. With the default gap (10) the FP64 path never triggers it."""
+    cfg = synthetic.CONFIGS["c1_4x4x4x4_f64"]
+    dims, block = cfg["dims"], cfg["block"]
+    u = synthetic.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    t = wilson.clover_term(u, cfg["csw"])
+    b = synthetic.gaussian_source(dims, 1, cfg["source_seed"])
+    f = ctx.load_gauge(u, block)
+    f.compute_clover(cfg["csw"])
+    kw = dict(nmr=2, ncy=1, restart=4, tol=1e-10, prec="f64")
+    plain = f.solve(cfg["kappa"], b, deflate=0, **kw)
+    forced = f.solve(cfg["kappa"], b, deflate=2, gap=1e-300, **kw)
+    normal = f.solve(cfg["kappa"], b, deflate=2, **kw)
+    sp, sf, sn = plain.stats[0], forced.stats[0], normal.stats[0]
+    assert sp["converged"] and sf["converged"] and sn["converged"]
+    assert np.array_equal(plain.x, forced.x)
+    assert sf["iters"] == sp["iters"] and sf["restarts"] == sp["restarts"]
+    assert sf["gap_restarts"] == sf["restarts"] >= 2
+    assert sn["gap_restarts"] == 0 and sp["gap_restarts"] == 0
+    assert oracle_relres(u, t, cfg["kappa"], forced.x[0], b[0]) <= 1e-10
+    f.free()

@@ -1,0 +1,170 @@
+"""Full-size GPU parity against the oracle: operators and the Schwarz preconditioner on
+lattices whose block grid has four or more blocks in every direction (so a block's two
+neighbours in a direction are different blocks, and the colour enumeration and the
+workgroup numbering run over several groups of eight), on the 16^3 x 32 geometry of the
+benchmark's 8x4x4x4 domains (block grid 2 x 4 x 4 x 8), and with several right-hand
+sides of different kappa in one launch sequence.
+
+Every comparison is element-wise as well as normwise: with ref the oracle's FP64 result
+on the same seeded input,
+    rel2   = |out - ref|_2 / |ref|_2
+    relinf = max |out - ref| / max |ref|      (largest single deviation, any site)
+Operator tolerances (both measures): FP64 1e-12, FP32 1e-6, FP16 5e-3 (FP16 storage
+rounds every real to 11 significant bits of its site's maximum, 2^-11 = 4.9e-4; the
+operator's sums stay within ten such roundings). SAP tolerances: FP64 1e-10; FP32 and
+FP16 storage bound the measured error of a nonlinear iteration (the MR step lengths
+depend on the rounded data), FP32 1e-5 and FP16 1e-2 in the 2-norm; the element-wise
+bound is four times that. Set SAPDD_PARITY_LOG to a file path to collect the measured
+errors as JSON lines.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import sap as osap
+from oracle import wilson
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = {"f64": 1e-12, "f32": 1e-6, "f16": 5e-3}
+SAP_TOL = {"f64": 1e-10, "f32": 1e-5, "f16": 1e-2}
+SAP_INF_FACTOR = 4.0
+
+# (lattice, block): block grids (4,4,4,4) for every block shape, and the benchmark's
+# 16^3 x 32 with 8x4x4x4 domains
+OP_CASES = [
+    ((8, 8, 8, 8), (2, 2, 2, 2)),
+    ((16, 16, 16, 16), (4, 4, 4, 4)),
+    ((32, 16, 16, 16), (8, 4, 4, 4)),
+    ((16, 16, 16, 32), (8, 4, 4, 4)),
+]
+SAP_CASES = [
+    ((16, 16, 16, 16), (4, 4, 4, 4), 0.125),
+    ((32, 16, 16, 16), (8, 4, 4, 4), 0.125),
+    ((16, 16, 16, 32), (8, 4, 4, 4), 0.125),
+]
+NMR, NCY = 4, 2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1502_04025_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+_fields, _refs = {}, {}
+
+
+def setup_case(ctx, dims, block, eps=0.3, seed=51):
+    key = (dims, block)
+    if key not in _fields:
+        u = synthetic.gauge_field(dims, eps, seed)
+        t = wilson.clover_term(u, 1.0)
+        f = ctx.load_gauge(u, block)
+        f.compute_clover(1.0)
+        _fields[key] = (u, t, f)
+    return _fields[key]
+
+
+def errors(out, ref):
+    d = np.abs(out - ref)
+    return float(np.linalg.norm(out - ref) / np.linalg.norm(ref)), float(d.max() / np.abs(ref).max())
+
+
+def log(rec):
+    path = os.environ.get("SAPDD_PARITY_LOG")
+    print(json.dumps(rec), flush=True)
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+
+
+@pytest.mark.parametrize("dims,block", OP_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_full_operator_elementwise(ctx, dims, block, prec):
+    print(f"full D {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    psi = synthetic.gaussian_source(dims, 2, 61)
+    kappa = 0.124
+    out = f.apply_D(kappa, psi, prec=prec)
+    for r in range(2):
+        rel2, relinf = errors(out[r], wilson.apply_M(u, t, kappa, psi[r]))
+        log(dict(test="full_operator", dims=dims, block=block, prec=prec, rhs=r, rel2=rel2, relinf=relinf))
+        assert rel2 <= OP_TOL[prec] and relinf <= OP_TOL[prec]
+
+
+@pytest.mark.parametrize("dims,block", OP_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_block_operator_elementwise(ctx, dims, block, prec):
+    print(f"block D {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    psi = synthetic.gaussian_source(dims, 1, 62)
+    kappa = 0.126
+    out = f.apply_block_D(kappa, psi, prec=prec)
+    rel2, relinf = errors(out[0], wilson.apply_M(u, t, kappa, psi[0], block=block))
+    log(dict(test="block_operator", dims=dims, block=block, prec=prec, rel2=rel2, relinf=relinf))
+    assert rel2 <= OP_TOL[prec] and relinf <= OP_TOL[prec]
+
+
+def sap_ref(u, t, dims, block, kappa, eta_seed, r=0):
+    key = (dims, block, kappa, eta_seed, r)
+    if key not in _refs:
+        eta = synthetic.gaussian_source(dims, 2, eta_seed)[r]
+        _refs[key] = osap.sap(osap.BlockSystem(u, t, kappa, block), eta, NCY, NMR)
+    return _refs[key]
+
+
+@pytest.mark.parametrize("dims,block,kappa", SAP_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_elementwise(ctx, dims, block, kappa, prec):
+    print(f"SAP {dims} {block} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    eta = synthetic.gaussian_source(dims, 2, 63)[:1].copy()
+    out = f.sap(kappa, eta, nmr=NMR, ncy=NCY, prec=prec)
+    rel2, relinf = errors(out[0], sap_ref(u, t, dims, block, kappa, 63))
+    log(dict(test="sap", dims=dims, block=block, prec=prec, nmr=NMR, ncy=NCY, rel2=rel2, relinf=relinf))
+    assert rel2 <= SAP_TOL[prec] and relinf <= SAP_INF_FACTOR * SAP_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_two_rhs_two_kappa(ctx, prec):
+    """Two right-hand sides with different kappa share every launch of one SAP
+    application (grid of 8x4x4x4 domains 2 x 4 x 4 x 8): each equals the oracle's SAP with
+    its own kappa, and each equals its own single-right-hand-side application bit for bit
+    (the slots are independent)."""
+    dims, block = (16, 16, 16, 32), (8, 4, 4, 4)
+    print(f"SAP 2 rhs 2 kappa {dims} {prec}", flush=True)
+    u, t, f = setup_case(ctx, dims, block)
+    eta = synthetic.gaussian_source(dims, 2, 63)
+    kap = np.array([0.125, 0.121])
+    out = f.sap(kap, eta, nmr=NMR, ncy=NCY, prec=prec)
+    for r in range(2):
+        rel2, relinf = errors(out[r], sap_ref(u, t, dims, block, float(kap[r]), 63, r))
+        log(dict(test="sap_2rhs", dims=dims, block=block, prec=prec, rhs=r, kappa=float(kap[r]), rel2=rel2,
+                 relinf=relinf))
+        assert rel2 <= SAP_TOL[prec] and relinf <= SAP_INF_FACTOR * SAP_TOL[prec]
+        alone = f.sap(float(kap[r]), eta[r:r + 1].copy(), nmr=NMR, ncy=NCY, prec=prec)
+        assert np.array_equal(alone[0], out[r])
+
+
+def test_fp16_storage_of_subnormal_sites(ctx):
+    """A site whose largest value lies below the smallest normal float is stored as zero
+    in FP16 storage (no NaN from 0 * inf): the FP16 operator output stays finite and
+    matches the oracle applied to the input with those sites zeroed."""
+    dims, block = (8, 8, 8, 8), (2, 2, 2, 2)
+    u, t, f = setup_case(ctx, dims, block)
+    psi = synthetic.point_sources(dims)[:1].copy()
+    psi[0, 5, 5, 5, 5] = 3e-39  # every component of one far site: maximum below FLT_MIN
+    out = f.apply_D(0.124, psi, prec="f16")
+    assert np.all(np.isfinite(out))
+    ref = psi.copy()
+    ref[0, 5, 5, 5, 5] = 0
+    rel2, relinf = errors(out[0], wilson.apply_M(u, t, 0.124, ref[0]))
+    assert rel2 <= OP_TOL["f16"] and relinf <= OP_TOL["f16"]

@@ -63,3 +63,21 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", src).replace("oracle's", ""), f
+
+
+def test_fp16_site_scale_rule_on_the_host(tmp_path):
+    """The FP16 storage helpers' scale reciprocal (core.hpp fp16_site_inv), compiled for the
+    host: finite for every finite maximum, zero for a maximum below the smallest normal
+    float (such a site stores zeros instead of NaN = 0 * inf), and |v| * inv <= 1."""
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = tmp_path / "fp16chk"
+    subprocess.run([hipcc, "-O1", "-std=c++17", "--offload-arch=gfx950", "-Wno-unused-command-line-argument",
+                    "-I", os.path.join(ROOT, "paper_1502_04025_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "fp16_scale_check.cpp"), "-o", str(exe)],
+                   check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout
+    assert "BAD" not in r.stdout and r.stdout.count(" ok") == 12
