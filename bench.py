@@ -1,23 +1,24 @@
 #!/usr/bin/env python
 """Benchmark: SAP-preconditioned FGMRES solves on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c2_f64|c3|c3_f64_1rhs|c5|c5_host_io|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c5_host_io|c2|c2_f64|c3|c3_f64_1rhs|serve|mg]
     python bench.py --sweep          # time to solution over nmr x ncy x domain shape
-    python bench.py --workload mg    # two-level multigrid (SAP smoother) against SAP alone
 
-One step = one complete solve of M x = b to a true relative residual of 1e-10 (SAP
-preconditioner + FP64 flexible GMRES, every kernel of the hot path), with b and x
-resident in HBM. The default workload is the 16^3 x 32 lattice with 8x4x4x4 domains,
-FP32 Schwarz/MR storage and FP64 outer solver, one Gaussian right-hand side; 4 MR steps
-per block solve and 8 Schwarz cycles per preconditioner application.
+One step = one complete solve of M x = b for every right-hand side of the workload to a
+true relative residual of 1e-10 (SAP preconditioner + FP64 flexible GMRES, every kernel
+of the hot path), with b and x resident in HBM. The default workload is the largest
+single-GPU configuration: the 48^3 x 96 lattice with 8x4x4x4 domains, 12 Gaussian
+right-hand sides solved together, FP16 Schwarz/MR storage, FP64 FGMRES(3) whose true
+residual is recomputed at every restart; 4 MR steps per block solve and 8 Schwarz
+cycles per preconditioner application.
 
-Printed: one JSON line with solves/s (RHS solves per second), p50/p99 solve latency, the
-roofline of the dominant kernel (per-kernel HIP-event times measured on the solve's
-stream during the timed steps), the block-Dslash bandwidth on the 32^3 x 64 lattice
-(FP16 and FP32 storage, 18-real and two-row links; working set far above the 256 MB
-Infinity Cache), the two-level multigrid against SAP alone on one right-hand side near
-the critical kappa, the all-FP64 path on the same problem, and the CPU oracle timed on a
-bounded sample of the same solve.
+Printed: one JSON line with RHS solves/s, the roofline of the dominant kernel (the SAP
+half-sweep: per-kernel HIP-event times measured on the solve's stream during the timed
+steps, HBM traffic from the committed rocprofv3 counters), and as sub-objects: the
+block-Dslash bandwidth on 32^3 x 64, the 16^3 x 32 single-RHS solve (FP32 SAP and the
+all-FP64 path), the mixed-precision 12-RHS form against plain FP64 single-RHS solves on
+32^3 x 64, a bounded serving phase with p50/p99 latency, the two-level multigrid near
+the critical kappa, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -47,6 +48,8 @@ WORKLOADS = {
     # PCIe one right-hand side at a time, inside the timed region).
     "c5": ("c5_48x48x48x96_f16", "f16", {"restart": 3, "ncy": NCY}),
     "c5_host_io": ("c5_48x48x48x96_f16", "f16", {"restart": 3, "ncy": NCY, "host_io": True}),
+    # the paper's half-precision mode: FP16 links and clover, FP32 Schwarz spinors
+    "c5_f16l": ("c5_48x48x48x96_f16", "f16l", {"restart": 3, "ncy": NCY}),
 }
 
 
@@ -54,16 +57,10 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def make_field(ctx, cfg):
+def make_field(ctx, cfg, u=None):
     import synthetic
-    vol = int(np.prod(cfg["dims"]))
-    prog = None
-    if vol > 4_000_000:  # long generation: report progress so the run is visibly alive
-        def prog(done, total, _last=[0.0]):
-            if time.time() - _last[0] > 20:
-                print(f"# gauge field: {done}/{total} sites", flush=True)
-                _last[0] = time.time()
-    u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"], progress=prog)
+    if u is None:
+        u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"])
     f = ctx.load_gauge(u, cfg["block"])
     f.compute_clover(cfg["csw"])
     return u, f
@@ -98,33 +95,43 @@ def profiled_traffic(entry):
 
 
 def roofline_sap(prof, cfg, prec, nmr):
+    """Roofline of the SAP half-sweep from the HIP-event times of the timed steps: flops
+    and algorithmic bytes per launch (one colour, every right-hand side), both roofs, and
+    the HBM traffic per launch that the committed rocprofv3 counters give for this kernel
+    and workload."""
     from paper_1502_04025_amd import perfmodel as pm
     k = prof["sap_half"]
     if k["launches"] == 0:
         return None
     V = int(np.prod(cfg["dims"]))
+    nrhs = cfg["nrhs_active"]
     avg = k["seconds"] / k["launches"]
-    units = V / 2 * cfg["nrhs_active"]  # sites of one colour per launch
-    flops = pm.sap_half_flops(cfg["block"], nmr) * units
-    byts = pm.sap_half_bytes(cfg["block"], prec) * units
-    alu_peak = pm.ALU_PEAK_TFLOPS["f64" if prec == "f64" else "f32"]
+    flops = pm.sap_half_flops(cfg["block"], nmr) * V / 2 * nrhs
+    byts = pm.sap_half_bytes(cfg["block"], prec, nrhs) * V / 2
+    ar = "f64" if prec == "f64" else "f32"
+    alu_peak, alu_pub = pm.ALU_PEAK_TFLOPS[ar], pm.ALU_PEAK_PUBLISHED_TFLOPS[ar]
     traffic = profiled_traffic(f"sap_half_kernel {'x'.join(map(str, cfg['dims']))} {'x'.join(map(str, cfg['block']))} "
-                               f"{prec}") if cfg["nrhs_active"] == 1 else None
+                               f"{prec} nrhs {nrhs}")
     t_alu = flops / (alu_peak * 1e12)
     t_hbm = byts / (pm.HBM_PEAK_GBS * 1e9)
     tflops, gbs = flops / avg / 1e12, byts / avg / 1e9
-    # both roofs, and whether one SAP cycle's data (both colours) fits the 256 MB
-    # Infinity Cache, in which case the HBM figure is a cache-resident one
-    both = dict(alu_TFLOP_s=round(tflops, 3), alu_frac=round(tflops / alu_peak, 4), hbm_GB_s=round(gbs, 1),
-                hbm_frac=round(gbs / pm.HBM_PEAK_GBS, 4), working_set_bytes=2 * byts,
-                cache_resident=bool(2 * byts < 256e6))
+    # one SAP cycle's data (both colours) below the 256 MB Infinity Cache makes the
+    # bandwidth figure a cache one
+    resident = bool(2 * byts < 256e6)
+    both = dict(alu_TFLOP_s=round(tflops, 3), alu_frac=round(tflops / alu_peak, 4),
+                alu_frac_of_published_157=round(tflops / alu_pub, 4),
+                mem_GB_s=round(gbs, 1), mem_frac=round(gbs / pm.HBM_PEAK_GBS, 4),
+                working_set_bytes=2 * byts, cache_resident=resident)
     common = dict(traffic=traffic, avg_launch_us=round(avg * 1e6, 2), launches=k["launches"],
-                  algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts, **both)
+                  algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts,
+                  traffic_over_algorithmic=round(traffic / byts, 3) if traffic else None, **both)
     if t_alu >= t_hbm:
         return dict(kernel="sap_half_kernel", bound="alu", achieved=round(tflops, 3), peak=alu_peak,
-                    unit="TFLOP/s", frac=round(tflops / alu_peak, 4), **common)
-    return dict(kernel="sap_half_kernel", bound="hbm", achieved=round(gbs, 1), peak=pm.HBM_PEAK_GBS,
-                unit="GB/s", frac=round(gbs / pm.HBM_PEAK_GBS, 4), **common)
+                    unit="TFLOP/s", frac=round(tflops / alu_peak, 4),
+                    peak_note=f"FP32 vector peak without packed FP32 (the build disables it); the published "
+                              f"{alu_pub} TFLOP/s counts packed FMAs", **common)
+    return dict(kernel="sap_half_kernel", bound="cache" if resident else "hbm", achieved=round(gbs, 1),
+                peak=pm.HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / pm.HBM_PEAK_GBS, 4), **common)
 
 
 def dslash_bandwidth(ctx, warm=10, reps=100):
@@ -211,52 +218,60 @@ def copy_bandwidth(ctx, nbytes=1 << 31, reps=10):
     return round(2 * nbytes / (p["seconds"] / p["launches"]) / 1e9, 1)
 
 
-def cpu_baseline(cfg, iters, restarts, nmr, ncy):
-    """Time the oracle on a bounded sample: one Schwarz half-sweep and one operator
-    application at the full lattice, scaled to one solve with the GPU's iteration count."""
+def cpu_baseline(cfg, iters, restarts, nmr, ncy, nrhs):
+    """Time the oracle on a bounded sample of the workload: one Schwarz half-sweep (the
+    block solves of one colour plus the residual update) and one operator application on
+    a 48 x 48 x 24 x 8 lattice drawn by the workload's recipe (same eps, kappa, c_sw and
+    domains), scaled per site to the workload's lattice and to the GPU's iteration count
+    (every outer iteration = 2 ncy half-sweeps + one operator application, plus one
+    operator application per restart), per right-hand side."""
     from threadpoolctl import threadpool_limits
 
     import synthetic
     from oracle import sap as osap
     from oracle import wilson
+    sample = (48, 48, 24, 8) if tuple(cfg["block"]) == (8, 4, 4, 4) else (32, 32, 32, 8)
+    vs = int(np.prod(sample))
+    scale = int(np.prod(cfg["dims"])) / vs
     with threadpool_limits(1):
-        u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"])
+        u = synthetic.gauge_field(sample, cfg["eps"], cfg["gauge_seed"], workers=1)
         t = wilson.clover_term(u, cfg["csw"])
-        b = synthetic.gaussian_source(cfg["dims"], 1, cfg["source_seed"])[0]
+        b = synthetic.gaussian_source(sample, 1, cfg["source_seed"], workers=1)[0]
         sysb = osap.BlockSystem(u, t, cfg["kappa"], cfg["block"])
         t0 = time.perf_counter()
-        m = wilson.apply_M(u, t, cfg["kappa"], b)
-        t_m = time.perf_counter() - t0
+        wilson.apply_M(u, t, cfg["kappa"], b)
+        t_m = (time.perf_counter() - t0) * scale
         t0 = time.perf_counter()
-        for c in (0, 1):  # one half-sweep = block solves of one colour + residual update
-            delta, _ = sysb.block_solve(b, c, nmr)
-            wilson.apply_M(u, t, cfg["kappa"], delta)
-        t_half = (time.perf_counter() - t0) / 2
-    del m
+        delta, _ = sysb.block_solve(b, 0, nmr)
+        wilson.apply_M(u, t, cfg["kappa"], delta)
+        t_half = (time.perf_counter() - t0) * scale
     t_solve = iters * (2 * ncy * t_half + t_m) + (restarts + 1) * t_m
     model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), None)
-    return dict(value=round(1.0 / t_solve, 6), unit="solves/s", cores=1, kind="oracle",
-                host_cores=len(os.sched_getaffinity(0)), cpu_model=model,
-                sample=f"two Schwarz half-sweeps (even-odd MR block solves, nmr {nmr}, plus the residual "
-                       f"update) and one operator application on the full {'x'.join(map(str, cfg['dims']))} "
-                       f"lattice, NumPy FP64 on one core ({t_half:.1f} s per half-sweep, {t_m:.2f} s per "
-                       f"operator), scaled to {iters} outer iterations x {2 * ncy} half-sweeps")
+    return dict(value=round(1.0 / t_solve, 8), unit="RHS solves/s", cores=1, kind="oracle",
+                host_cores=len(os.sched_getaffinity(0)), cpu_model=model, extrapolated=True,
+                sample=f"one Schwarz half-sweep (even-odd MR block solves of colour 0, nmr {nmr}, plus the "
+                       f"residual update) and one operator application on a {'x'.join(map(str, sample))} "
+                       f"lattice of the same recipe, NumPy FP64 on one core ({t_half / scale:.1f} s and "
+                       f"{t_m / scale:.2f} s), scaled by {scale:.0f}x to {'x'.join(map(str, cfg['dims']))} and to "
+                       f"{iters} outer iterations x {2 * ncy} half-sweeps per right-hand side "
+                       f"({t_solve:.0f} s per solve; the GPU solves {nrhs} together)")
 
 
-def run_serving(args):
+def serving_measure(n_requests, fracs, budget_gb, warm=6):
     """Serving stream: Poisson arrivals of 1-12 RHS solve requests on resident fields of
     16^3x32, 24^3x48 and 32^3x64 (4^4 domains, FP16 SAP, FP64 FGMRES(16)), kappa uniform
-    in [0.120, 0.126]; admission by HBM budget, continuous batching per volume."""
+    in [0.120, 0.126]; admission by HBM budget, continuous batching per volume. A closed
+    loop (every request at t = 0) measures the saturation rate; then n_requests arrive at
+    each fraction of it. Returns the saturation run and one run per fraction."""
     import torch
 
     import synthetic
     from paper_1502_04025_amd import serving as sv
-    torch.cuda.init()
     kw = dict(prec="f16", nmr=4, ncy=NCY, restart=16, tol=1e-10)
     vols = [sv.TorchVolume(f"{'x'.join(map(str, d))}", d, (4, 4, 4, 4), 0.3, 14 + i, 1.0, 0, kw)
             for i, d in enumerate(synthetic.SERVING_VOLUMES)]
     # 16 GB of the budget stay free for kernel scratch, graphs and the caching allocator
-    plans = sv.plan_capacity([v.plan() for v in vols], int(args.hbm_budget_gb * 1e9), max_slots=16,
+    plans = sv.plan_capacity([v.plan() for v in vols], int(budget_gb * 1e9), max_slots=16,
                              reserve_bytes=16 * 10 ** 9)
     for v, p in zip(vols, plans):
         v.start(p.capacity)
@@ -282,26 +297,35 @@ def run_serving(args):
         return [sv.Request(r["id"], r["t_arrival"] if rate < 1e8 else 0.0, r["vol"], r["kappa"], r["nrhs"],
                            r["seed"]) for r in rs]
 
-    serve(stream_of(6, 1e9, 30), False)  # warm up: graphs, clover inverses
-    sat = serve(stream_of(args.requests, 1e9, 31), False)  # closed loop: all at t = 0
+    serve(stream_of(warm, 1e9, 30), False)  # warm up: graphs, clover inverses
+    sat = serve(stream_of(n_requests, 1e9, 31), False)
     runs = {}
-    for frac in (0.5, 0.8, 0.95):
+    for frac in fracs:
         rate = frac * sat["requests_per_s"]
-        runs[str(frac)] = dict(rate_req_s=round(rate, 4), **serve(stream_of(args.requests, rate, 32), True))
+        runs[str(frac)] = dict(rate_req_s=round(rate, 4), **serve(stream_of(n_requests, rate, 32), True))
+    for v in vols:
+        v.close()
+    return dict(slots_per_volume=plans[0].capacity, hbm_budget_gb=budget_gb, warmup_requests=warm,
+                requests_per_phase=n_requests, saturation=sat, poisson=runs)
+
+
+def run_serving(args):
+    import torch
+    torch.cuda.init()
+    res = serving_measure(args.requests, (0.5, 0.8, 0.95), args.hbm_budget_gb, warm=args.serve_warmup)
+    sat = res["saturation"]
     line = {
         "metric": "Dslash HBM GB/s (% peak); SAP-FGMRES solves/s @ rel. residual 1e-10; p50/p99",
-        "value": round(sat["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.requests, "warmup": 6, "ms_per_step": None, "higher_is_better": True,
+        "value": round(sat["solves_per_s"], 4), "unit": "RHS solves/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": args.serve_warmup, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f16+f64", "data": "synthetic",
         "config": {"workload": "serving stream: Poisson arrivals, volumes 16^3x32 / 24^3x48 / 32^3x64 "
                                "(4^4 domains, links exp(i 0.3 H), c_sw 1), kappa U[0.120,0.126], 1-12 "
                                "Gaussian RHS, FP16 SAP + FP64 FGMRES(16) to 1e-10",
-                   "slots_per_volume": plans[0].capacity, "hbm_budget_gb": args.hbm_budget_gb},
-        "saturation": sat, "poisson": runs,
+                   "parallelism": "single GPU"},
+        **res,
     }
     print(json.dumps(line), flush=True)
-    for v in vols:
-        v.close()
 
 
 def run_sweep(args):
@@ -459,13 +483,85 @@ def run_mg(args):
         sys.exit(1)
 
 
+def timed_solves(field, kappa, b, x, steps, warmup, profile_families=("sap_half",), **kw):
+    """warmup untimed solves, then `steps` timed ones (HIP events on the dominant kernel's
+    family only); returns (seconds per solve, per-solve latencies, stats, profile)."""
+    import torch
+    for _ in range(warmup):
+        field.solve(kappa, b, x=x, **kw)
+    torch.cuda.synchronize()
+    ctx = field.ctx
+    ctx.profile(True, families=list(profile_families))
+    lat, r = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        r = field.solve(kappa, b, x=x, **kw)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile(False)
+    return elapsed / steps, lat, r.stats, prof
+
+
+def sub_c2(ctx, steps=10, warmup=2):
+    """16^3 x 32, 8x4x4x4 domains, one Gaussian right-hand side: FP32 SAP against the
+    all-FP64 path (working set inside the Infinity Cache)."""
+    import torch
+
+    import synthetic
+    cfg = synthetic.CONFIGS["c2_16x16x16x32_f32"]
+    _, f = make_field(ctx, cfg)
+    b = torch.from_numpy(make_source(cfg)).cuda()
+    x = torch.empty_like(b)
+    out = {"workload": "16x16x16x32, 8x4x4x4 domains, kappa 0.125, 1 gaussian RHS, FGMRES(16), nmr 4, ncy 8"}
+    for prec in ("f32", "f64"):
+        t, lat, st, _ = timed_solves(f, cfg["kappa"], b, x, steps, warmup, nmr=4, ncy=NCY, restart=16, tol=1e-10,
+                                     prec=prec)
+        out[prec] = {"solves_per_s": round(1.0 / t, 3), "ms_per_solve": round(1e3 * t, 3),
+                     "p50_ms": round(1e3 * percentile(lat, 50), 3), "p99_ms": round(1e3 * percentile(lat, 99), 3),
+                     "outer_iters": st[0]["iters"], "converged": bool(st[0]["converged"])}
+    f.free()
+    return out
+
+
+def sub_mixed_vs_fp64(ctx, steps=3, warmup=1):
+    """32^3 x 64, 4^4 domains, kappa 0.126: the mixed-precision multi-RHS form (12 point
+    sources solved together, FP16 SAP, FP64 FGMRES(16)) against plain FP64 single-RHS
+    solves (one Gaussian right-hand side, FP64 SAP), in RHS solves per second."""
+    import torch
+
+    import synthetic
+    cfg = synthetic.CONFIGS["c3_32x32x32x64_f16"]
+    _, f = make_field(ctx, cfg)
+    kw = dict(nmr=4, ncy=NCY, restart=16, tol=1e-10)
+    b = torch.from_numpy(synthetic.point_sources(cfg["dims"])).cuda()
+    x = torch.empty_like(b)
+    t12, _, st12, _ = timed_solves(f, cfg["kappa"], b, x, steps, warmup, prec="f16", **kw)
+    del b, x
+    b1 = torch.from_numpy(synthetic.gaussian_source(cfg["dims"], 1, cfg["source_seed"])).cuda()
+    x1 = torch.empty_like(b1)
+    t1, _, st1, _ = timed_solves(f, cfg["kappa"], b1, x1, steps, warmup, prec="f64", **kw)
+    f.free()
+    mixed, plain = 12 / t12, 1 / t1
+    return {"workload": "32x32x32x64, 4x4x4x4 domains, kappa 0.126, c_sw 1, links exp(i 0.25 H)",
+            "mixed_12rhs_f16": {"rhs_solves_per_s": round(mixed, 3), "s_per_step": round(t12, 4),
+                                "outer_iters": [s_["iters"] for s_ in st12],
+                                "converged": all(s_["converged"] for s_ in st12)},
+            "plain_f64_1rhs": {"rhs_solves_per_s": round(plain, 3), "s_per_step": round(t1, 4),
+                               "outer_iters": st1[0]["iters"], "converged": bool(st1[0]["converged"])},
+            "speedup": round(mixed / plain, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve", "mg"])
-    ap.add_argument("--requests", type=int, default=60, help="serve: requests per arrival rate")
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["serve", "mg"])
+    ap.add_argument("--requests", type=int, default=500, help="serve: requests per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=50, help="serve: warm-up requests")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="serve: HBM budget for admission")
     ap.add_argument("--nmr", type=int, default=4, help="MR iterations per block solve")
     ap.add_argument("--ncy", type=int, default=None,
@@ -476,25 +572,20 @@ def main():
     ap.add_argument("--sweep-nmr", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8])
     ap.add_argument("--sweep-ncy", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8, 12, 16])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the Dslash/copy/FP64 side measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip the sub-benchmarks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
-
-    import torch
-
-    import synthetic
-    from paper_1502_04025_amd import Context
-    from paper_1502_04025_amd import perfmodel as pm
-
     if args.sweep:
         return run_sweep(args)
     if args.workload == "serve":
         return run_serving(args)
     if args.workload == "mg":
         return run_mg(args)
+
+    import synthetic
     name, prec, over = WORKLOADS[args.workload]
     cfg = dict(synthetic.CONFIGS[name])
     cfg.update(over)
@@ -502,12 +593,21 @@ def main():
     restart = args.restart if args.restart is not None else cfg.get("restart", 16)
     deflate = args.deflate
     ncy = args.ncy if args.ncy is not None else cfg.get("ncy", 5)
+    # inputs first: worker processes draw them before this process touches the GPU
+    t0 = time.perf_counter()
+    u = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"])
+    b = make_source(cfg)
+    print(f"# inputs {'x'.join(map(str, cfg['dims']))}: {time.perf_counter() - t0:.1f} s", flush=True)
+
+    import torch
+
+    from paper_1502_04025_amd import Context
     torch.cuda.init()
     stream = torch.cuda.Stream()  # a real stream: the SAP sweep replays from HIP graphs
     torch.cuda.set_stream(stream)
     ctx = Context(0, stream=stream)
-    u, field = make_field(ctx, cfg)
-    b = make_source(cfg)
+    _, field = make_field(ctx, cfg, u)
+    del u
     if cfg.get("host_io"):
         x = np.empty_like(b)
     else:
@@ -515,102 +615,78 @@ def main():
         x = torch.empty_like(b)
     nrhs = b.shape[0]
     cfg["nrhs_active"] = nrhs
-
-    def step():
-        return field.solve(cfg["kappa"], b, x=x, nmr=nmr, ncy=ncy, restart=restart, deflate=deflate, tol=tol,
-                           prec=prec)
-
-    for _ in range(args.warmup):
-        r = step()
-    torch.cuda.synchronize()
-    # timed steps; HIP events record only the dominant kernel (one event pair per SAP
-    # application) so the instrumentation stays out of the step time
-    ctx.profile(True, families=["sap_half"])
-    lat = []
-    stats = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        r = step()
-        lat.append(time.perf_counter() - ts)
-        stats = r.stats
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile(False)
+    kw = dict(nmr=nmr, ncy=ncy, restart=restart, deflate=deflate, tol=tol, prec=prec)
+    t_step, lat, stats, prof = timed_solves(field, cfg["kappa"], b, x, args.steps, args.warmup, **kw)
     # one more step with every kernel family recorded, for the time breakdown
     ctx.profile(True)
-    step()
+    field.solve(cfg["kappa"], b, x=x, **kw)
     prof_all = ctx.profile(False)
-    elapsed = t1 - t0
-    solves_per_s = args.steps * nrhs / elapsed
-    iters = [s["iters"] for s in stats]
-    relres = [s["true_relres"] for s in stats]
-    ok = all(s["converged"] for s in stats)
-
-    # oracle check of the last solution's residual (first right-hand side); above 4M sites
-    # the NumPy operator needs minutes and tens of GB, so it is left to the parity tests
+    iters = [s_["iters"] for s_ in stats]
+    relres = [s_["true_relres"] for s_ in stats]
+    ok = all(s_["converged"] for s_ in stats)
+    # above 4M sites the oracle's residual recheck (minutes, ~66 GB of host memory) is the
+    # job of tests/test_gpu_c5.py
     oracle_relres = None
     if int(np.prod(cfg["dims"])) <= 4_000_000:
         from oracle import wilson
-        t_or = wilson.clover_term(u, cfg["csw"])
+        uo = synthetic.gauge_field(cfg["dims"], cfg["eps"], cfg["gauge_seed"])
+        t_or = wilson.clover_term(uo, cfg["csw"])
         x0 = x[0] if isinstance(x, np.ndarray) else x[0].cpu().numpy()
         b0 = b[0] if isinstance(b, np.ndarray) else b[0].cpu().numpy()
-        oracle_relres = float(np.linalg.norm(b0 - wilson.apply_M(u, t_or, cfg["kappa"], x0)) / np.linalg.norm(b0))
-        del t_or
-
+        oracle_relres = float(np.linalg.norm(b0 - wilson.apply_M(uo, t_or, cfg["kappa"], x0)) / np.linalg.norm(b0))
+        del t_or, uo
     line = {
         "metric": "Dslash HBM GB/s (% peak); SAP-FGMRES solves/s @ rel. residual 1e-10; p50/p99",
-        "value": round(solves_per_s, 4),
-        "unit": "solves/s",
+        "value": round(nrhs / t_step, 4),
+        "unit": "RHS solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": round(1e3 * t_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec == "f32" else ("f16+f64" if prec == "f16" else "f64"),
+        "dtype": {"f32": "f32+f64", "f16": "f16+f64", "f16l": "f16/f32+f64"}.get(prec, "f64"),
         "data": "synthetic",
         "config": {"workload": f"{name}: {'x'.join(map(str, cfg['dims']))} lattice, {'x'.join(map(str, cfg['block']))} "
                                f"domains, kappa {cfg['kappa']}, c_sw {cfg['csw']}, links exp(i {cfg['eps']} H), "
-                               f"{nrhs} {cfg['source']} RHS, SAP {prec} storage (nmr {nmr}, ncy {ncy}), "
-                               f"FP64 FGMRES({restart}){f' with {deflate} deflated vectors' if deflate else ''} to {tol}",
+                               f"{nrhs} {cfg['source']} RHS solved together, SAP {prec} storage (nmr {nmr}, ncy {ncy}), "
+                               f"FP64 FGMRES({restart}){f' with {deflate} deflated vectors' if deflate else ''} "
+                               f"to {tol}, b and x {'in host memory' if cfg.get('host_io') else 'resident in HBM'}",
                    "parallelism": "single GPU"},
-        "latency_ms": {"p50": round(1e3 * percentile(lat, 50), 3), "p99": round(1e3 * percentile(lat, 99), 3)},
+        "step_latency_ms": {"p50": round(1e3 * percentile(lat, 50), 3), "p99": round(1e3 * percentile(lat, 99), 3)},
         "solve": {"outer_iters": iters, "true_relres": relres, "oracle_relres_rhs0": oracle_relres,
                   "converged": ok},
         "kernel_time_one_step_s": {k: round(v["seconds"], 6) for k, v in prof_all.items() if v["launches"]},
         "roofline": roofline_sap(prof, cfg, prec, nmr),
     }
-    if not args.no_extras:
-        try:
-            line["dslash"] = dslash_bandwidth(ctx)
-        except Exception as e:  # report, do not hide the main number
-            line["dslash"] = {"error": str(e)}
-        line["copy_GB_s"] = copy_bandwidth(ctx)
-        try:
-            line["mg_near_critical"] = mg_extra(ctx)
-        except Exception as e:  # report, do not hide the main number
-            line["mg_near_critical"] = {"error": str(e)}
-        for key in ("f16", "f32", "f16_links12", "f32_links12"):  # also as a fraction of the copy bandwidth
-            if isinstance(line["dslash"].get(key), dict):
-                line["dslash"][key]["frac_of_copy"] = round(line["dslash"][key]["GB_s"] / line["copy_GB_s"], 4)
-        if prec != "f64":
-            t0 = time.perf_counter()
-            n64 = 3
-            r64 = None
-            for _ in range(n64):
-                r64 = field.solve(cfg["kappa"], b, x=x, nmr=nmr, ncy=ncy, restart=restart, tol=tol, prec="f64")
-            torch.cuda.synchronize()
-            t64 = (time.perf_counter() - t0) / n64
-            line["fp64_path"] = {"solves_per_s": round(nrhs / t64, 4),
-                                 "outer_iters": [s["iters"] for s in r64.stats]}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, int(np.mean(iters)), int(np.mean([s["restarts"] for s in stats])), nmr,
-                                            ncy)
-    print(json.dumps(line), flush=True)
     field.free()
+    del b, x
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        def extra(key, fn):
+            t0 = time.perf_counter()
+            try:
+                line[key] = fn()
+            except Exception as e:  # report, do not hide the main number
+                line[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+            print(f"# {key}: {time.perf_counter() - t0:.1f} s", flush=True)
+        extra("dslash", lambda: dslash_bandwidth(ctx))
+        extra("copy_GB_s", lambda: copy_bandwidth(ctx))
+        for key in ("f16", "f32", "f16_links12", "f32_links12"):  # also as a fraction of the copy bandwidth
+            if isinstance(line["dslash"].get(key), dict) and isinstance(line["copy_GB_s"], float):
+                line["dslash"][key]["frac_of_copy"] = round(line["dslash"][key]["GB_s"] / line["copy_GB_s"], 4)
+        extra("c2_16x16x16x32", lambda: sub_c2(ctx))
+        extra("mixed_vs_fp64_32x32x32x64", lambda: sub_mixed_vs_fp64(ctx))
+        extra("serving", lambda: serving_measure(40, (0.8,), 200.0, warm=6))
+        extra("mg_near_critical", lambda: mg_extra(ctx))
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(cfg, int(np.mean(iters)), int(np.mean([s_["restarts"] for s_ in stats])),
+                                            nmr, ncy, nrhs)
+        print(f"# cpu_baseline: {time.perf_counter() - t0:.1f} s", flush=True)
+    print(json.dumps(line), flush=True)
     ctx.close()
     if not ok:
         sys.exit(1)

@@ -61,7 +61,11 @@ enum {
     SAPDD_EFULL = -7      /* no free slot in a batch                                */
 };
 
-enum { SAPDD_F64 = 0, SAPDD_F32 = 1, SAPDD_F16 = 2 }; /* storage precisions */
+/* Storage precisions. SAPDD_F16 stores every site with one FP32 scale (max |value| of the
+ * site). sap_prec additionally takes SAPDD_F16_LINKS: links and clover in FP16 (with the
+ * site scale), the Schwarz residual and corrections in FP32 - the half-precision mode of
+ * Sec. 3.3, which keeps the spinors in single precision. */
+enum { SAPDD_F64 = 0, SAPDD_F32 = 1, SAPDD_F16 = 2, SAPDD_F16_LINKS = 3 };
 
 enum {
     SAPDD_DEVICE_PTRS = 1, /* array arguments are device pointers              */
@@ -81,7 +85,9 @@ typedef struct {
     int restart;    /* FGMRES restart length m (1..16)                             */
     int max_iter;   /* cap on outer iterations (preconditioner applications)       */
     double tol;     /* target true relative residual |b - M x| / |b|               */
-    int sap_prec;   /* storage precision inside SAP: SAPDD_F64, SAPDD_F32, SAPDD_F16 */
+    int sap_prec;   /* storage inside SAP: SAPDD_F64, SAPDD_F32, SAPDD_F16 (links,
+                     * clover and spinors) or SAPDD_F16_LINKS (FP16 links and clover,
+                     * FP32 spinors)                                                   */
     int flags;      /* SAPDD_DEVICE_PTRS | SAPDD_USE_X0 | SAPDD_NO_GRAPH          */
     int deflate;    /* deflated restarts (Sec. 3.1, flexible GMRES with deflated
                      * restarts): k harmonic Ritz vectors of the cycle's Hessenberg

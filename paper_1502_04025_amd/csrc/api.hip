@@ -23,6 +23,7 @@
 
 #include "../../include/sapdd.h"
 #include "dense.hpp"
+#include "elastic.hpp"
 #include "kernels.hpp"
 
 using namespace sapdd;
@@ -35,6 +36,10 @@ struct DevBuf {
 };
 
 size_t prec_bytes(int prec) { return prec == P64 ? 8 : prec == P32 ? 4 : 2; }
+// Storage precisions of a Schwarz mode (sapdd_params.sap_prec): links and clover X, and
+// the Schwarz spinors (residual, correction). SAPDD_F16_LINKS keeps the spinors in FP32.
+int lprec(int mode) { return mode == SAPDD_F16_LINKS ? P16 : mode; }
+int sprec(int mode) { return mode == SAPDD_F16_LINKS ? P32 : mode; }
 
 struct XEntry {  // SAP clover X for one (kappa, precision)
     double kappa;
@@ -344,7 +349,7 @@ int check_params(sapdd_ctx *c, const sapdd_field *f, const sapdd_params *p) {
             if (p->block[mu] != f->geo.B[mu])
                 return fail(c, SAPDD_EINVAL, "params.block differs from the field's blocking");
     if (p->nmr < 1 || p->ncy < 1) return fail(c, SAPDD_EINVAL, "nmr and ncy must be >= 1");
-    if (p->sap_prec < SAPDD_F64 || p->sap_prec > SAPDD_F16) return fail(c, SAPDD_EINVAL, "bad sap_prec");
+    if (p->sap_prec < SAPDD_F64 || p->sap_prec > SAPDD_F16_LINKS) return fail(c, SAPDD_EINVAL, "bad sap_prec");
     if (!(p->gap >= 0)) return fail(c, SAPDD_EINVAL, "gap must be >= 0 (0 = the default 10)");
     return SAPDD_OK;
 }
@@ -358,15 +363,16 @@ struct SapState {
     double *kappa;
 };
 
-// Upload per-rhs kappa and clover pointers; prepare rres/delta buffers.
-int sap_prepare(sapdd_ctx *c, sapdd_field *f, const double *kappa, int nrhs, int prec, SapState *s) {
+// Upload per-rhs kappa and clover pointers; prepare rres/delta buffers (mode: sap_prec).
+int sap_prepare(sapdd_ctx *c, sapdd_field *f, const double *kappa, int nrhs, int mode, SapState *s) {
     const Geom &g = f->geo;
-    CHK(lo_copies(c, f, prec));
-    s->links = links_of(f, prec);
+    const int lp = lprec(mode), sp = sprec(mode);
+    CHK(lo_copies(c, f, lp));
+    s->links = links_of(f, lp);
     std::vector<Fld> xs(nrhs);
-    for (int r = 0; r < nrhs; ++r) CHK(sap_clover(c, f, kappa[r], prec, &xs[r]));
-    CHK(spinor_buf(c, "sap_rres", g, nrhs, prec, 12, &s->rres));
-    CHK(spinor_buf(c, "sap_delta", g, nrhs, prec, 24, &s->delta));
+    for (int r = 0; r < nrhs; ++r) CHK(sap_clover(c, f, kappa[r], lp, &xs[r]));
+    CHK(spinor_buf(c, "sap_rres", g, nrhs, sp, 12, &s->rres));
+    CHK(spinor_buf(c, "sap_delta", g, nrhs, sp, 24, &s->delta));
     // rres scales are indexed per half lattice: spinor_buf allotted V per field, enough.
     void *meta;
     const size_t mbytes = (size_t)nrhs * (2 * sizeof(void *) + sizeof(double));
@@ -692,15 +698,15 @@ long long sapdd_solve_footprint(const sapdd_field *f, const sapdd_params *p, int
     if (!f || !p || nrhs < 1) return -1;
     const long long V = f->geo.V;
     const int m = std::max(1, p->restart);
-    const int prec = p->sap_prec;
-    const long long sb = prec == P64 ? 8 : prec == P32 ? 4 : 2;
+    const int prec = p->sap_prec, lp = lprec(prec), sp = sprec(prec);
+    const long long lb = (long long)prec_bytes(lp), sb = (long long)prec_bytes(sp);
     const long long zb = prec == P64 || p->deflate > 0 ? 8 : 4;
     long long per_rhs = (m + 1) * V * 24 * 8     // Krylov basis V
                         + (long long)m * V * 24 * zb  // preconditioned vectors Z
                         + 2 * V * 24 * 8              // b and x in the device layout
-                        + V * 24 * sb + V * 12 * sb + (prec == P16 ? 2 * V * 4 : 0)  // SAP delta, residual
-                        + V * 72 * sb + (prec == P16 ? V * 4 : 0);                     // clover X per kappa
-    long long fixed = prec == P64 ? 0 : 2 * V * 72 * sb + (prec == P16 ? 2 * V * 4 : 0);  // low-precision links, T
+                        + V * 24 * sb + V * 12 * sb + (sp == P16 ? 2 * V * 4 : 0)  // SAP delta, residual
+                        + V * 72 * lb + (lp == P16 ? V * 4 : 0);                    // clover X per kappa
+    long long fixed = lp == P64 ? 0 : 2 * V * 72 * lb + (lp == P16 ? 2 * V * 4 : 0);  // low-precision links, T
     return fixed + per_rhs * nrhs;
 }
 
@@ -917,6 +923,18 @@ struct sapdd_batch {
     double t_sap = 0, t_d = 0, t_gs = 0, t_host = 0;
     sapdd_mg *mg = nullptr;  // multigrid preconditioner in place of SAP (sapdd_batch_set_mg)
     MgWork mw{};
+    // Elastic batches (SAPDD_ELASTIC): the per-slot fields are address ranges whose
+    // physical memory is committed while a slot is in use (elastic.hpp).
+    struct EField {
+        char *va = nullptr;
+        size_t reserved = 0, data_per_slot = 0, scale_off = 0, scale_per_slot = 0;
+        ElasticPlan plan;
+        // committed runs by first granule: the handle of their memory and their length
+        std::map<size_t, std::pair<hipMemGenericAllocationHandle_t, size_t>> handles;
+    };
+    bool elastic = false;
+    size_t gran = 0, fixed_bytes = 0;
+    std::vector<EField> efields;
 };
 
 static const sapdd_field *batch_field(const sapdd_batch *B) { return B->f; }
@@ -931,19 +949,117 @@ int balloc(sapdd_batch *B, size_t bytes, void **out) {
         return fail(B->c, SAPDD_ENOMEM, "hipMalloc of %zu bytes for a solver batch failed", bytes);
     }
     B->allocs.push_back(q);
+    B->fixed_bytes += bytes ? bytes : 16;
     *out = q;
     return SAPDD_OK;
 }
 
+hipMemAllocationProp vmm_prop(int device) {
+    hipMemAllocationProp prop{};
+    prop.type = hipMemAllocationTypePinned;
+    prop.location.type = hipMemLocationTypeDevice;
+    prop.location.id = device;
+    return prop;
+}
+
+// A per-slot field of nf = cap * per-slot copies: device memory (fixed batch), or in an
+// elastic batch an address range whose slots are committed on admission (commit_slot).
 int bfield(sapdd_batch *B, int nf, int prec, int ncomp, Fld *f) {
     const size_t nd = (size_t)B->g.V * ncomp * nf;
     size_t bytes = nd * prec_bytes(prec);
     const size_t sc_off = (bytes + 255) / 256 * 256;
     if (prec == P16) bytes = sc_off + (size_t)B->g.V * nf * sizeof(float);
-    void *q;
-    CHK(balloc(B, bytes, &q));
-    *f = Fld{q, prec == P16 ? (float *)((char *)q + sc_off) : nullptr, prec};
+    if (!B->elastic) {
+        void *q;
+        CHK(balloc(B, bytes, &q));
+        *f = Fld{q, prec == P16 ? (float *)((char *)q + sc_off) : nullptr, prec};
+        return SAPDD_OK;
+    }
+    sapdd_batch::EField e;
+    e.reserved = (bytes + B->gran - 1) / B->gran * B->gran;
+    void *va = nullptr;
+    hipError_t err = hipMemAddressReserve(&va, e.reserved, B->gran, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(B->c, SAPDD_ENOMEM, "reserving %zu bytes of address space failed: %s", e.reserved,
+                    hipGetErrorString(err));
+    }
+    e.va = (char *)va;
+    const int per = nf / B->cap;
+    e.data_per_slot = (size_t)B->g.V * ncomp * per * prec_bytes(prec);
+    e.scale_off = sc_off;
+    e.scale_per_slot = prec == P16 ? (size_t)B->g.V * per * sizeof(float) : 0;
+    e.plan = ElasticPlan(B->gran, e.reserved);
+    B->efields.push_back(std::move(e));
+    *f = Fld{va, prec == P16 ? (float *)((char *)va + sc_off) : nullptr, prec};
     return SAPDD_OK;
+}
+
+// Release the physical memory of the given runs of an elastic field (those it holds).
+void eunmap(sapdd_batch::EField &e, size_t gran, const std::vector<GranRun> &runs) {
+    for (const GranRun &r : runs) {
+        auto it = e.handles.find(r.g);
+        if (it == e.handles.end()) continue;
+        (void)hipMemUnmap(e.va + r.g * gran, r.n * gran);
+        (void)hipMemRelease(it->second.first);
+        e.handles.erase(it);
+    }
+}
+
+// The byte ranges of slot r in an elastic field (data, then FP16 scales).
+template <class F> void slot_ranges(const sapdd_batch::EField &e, int r, F &&fn) {
+    fn(r * e.data_per_slot, e.data_per_slot);
+    if (e.scale_per_slot) fn(e.scale_off + r * e.scale_per_slot, e.scale_per_slot);
+}
+
+// Commit slot r's memory in every elastic field; on failure nothing stays committed.
+int commit_slot(sapdd_batch *B, int r) {
+    if (!B->elastic) return SAPDD_OK;
+    const hipMemAllocationProp prop = vmm_prop(B->c->device);
+    hipMemAccessDesc acc{};
+    acc.location = prop.location;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    size_t done = 0;
+    hipError_t err = hipSuccess;
+    for (; done < B->efields.size() && err == hipSuccess; ++done) {
+        sapdd_batch::EField &e = B->efields[done];
+        std::vector<GranRun> runs;
+        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.acquire(off, len, runs); });
+        for (const GranRun &q : runs) {
+            hipMemGenericAllocationHandle_t h;
+            err = hipMemCreate(&h, q.n * B->gran, &prop, 0);
+            if (err != hipSuccess) break;
+            char *at = e.va + q.g * B->gran;
+            err = hipMemMap(at, q.n * B->gran, 0, h, 0);
+            if (err == hipSuccess) err = hipMemSetAccess(at, q.n * B->gran, &acc, 1);
+            if (err != hipSuccess) {
+                (void)hipMemUnmap(at, q.n * B->gran);
+                (void)hipMemRelease(h);
+                break;
+            }
+            e.handles[q.g] = {h, q.n};
+        }
+    }
+    if (err == hipSuccess) return SAPDD_OK;
+    (void)hipGetLastError();
+    for (size_t i = 0; i < done; ++i) {  // roll back every field this call touched
+        sapdd_batch::EField &e = B->efields[i];
+        std::vector<GranRun> runs;
+        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.release(off, len, runs); });
+        eunmap(e, B->gran, runs);
+    }
+    return fail(B->c, err == hipErrorOutOfMemory ? SAPDD_ENOMEM : SAPDD_EDEVICE,
+                "committing the memory of slot %d failed: %s", r, hipGetErrorString(err));
+}
+
+// Release slot r's memory in every elastic field (the stream must be done with it).
+void release_slot(sapdd_batch *B, int r) {
+    if (!B->elastic) return;
+    for (auto &e : B->efields) {
+        std::vector<GranRun> runs;
+        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.release(off, len, runs); });
+        eunmap(e, B->gran, runs);
+    }
 }
 
 int upload(sapdd_batch *B, int seg, const std::vector<int> &v, int **out) {
@@ -965,8 +1081,10 @@ int fetch_coef(sapdd_batch *B) {
 }
 
 // True residual r = b - M x of the listed slots into basis slot 0, |r|, vscale[0] = 1/|r|;
-// decides convergence (tol), failure (non-finite) and exhaustion (max_iter).
-int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
+// decides convergence (tol), failure (non-finite) and exhaustion (max_iter). gap_check:
+// compare with the implicit residual of the cycle that just ended (off for the second
+// pass over slots the gap rule sent back to a plain restart).
+int batch_residual(sapdd_batch *B, const std::vector<int> &list, bool gap_check = true) {
     if (list.empty()) return SAPDD_OK;
     sapdd_ctx *c = B->c;
     // Slots that continue a deflated basis keep basis vectors 0..k: their true residual
@@ -1012,7 +1130,8 @@ int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
         s.true_relres = s.beta / s.bnorm;
         s.ready = false;
         double implicit = -1;
-        if (s.deflated) {
+        if (!gap_check) {
+        } else if (s.deflated) {
             double q = 0;
             for (const cd &v : s.c0) q += std::norm(v);
             implicit = std::sqrt(q);
@@ -1041,7 +1160,7 @@ int batch_residual(sapdd_batch *B, const std::vector<int> &list) {
             s.ready = true;
         }
     }
-    if (!redo.empty()) return batch_residual(B, redo);
+    if (!redo.empty()) return batch_residual(B, redo, false);
     return SAPDD_OK;
 }
 
@@ -1416,8 +1535,15 @@ void batch_free(sapdd_batch *B) {
     if (B->c) (void)hipStreamSynchronize(B->c->stream);
     for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &s : B->slots)
-        if (s.used) sap_clover_release(B->f, s.kappa, B->prec);
+        if (s.used) sap_clover_release(B->f, s.kappa, lprec(B->prec));
     for (void *q : B->allocs) (void)hipFree(q);
+    for (auto &e : B->efields) {
+        for (auto &kv : e.handles) {
+            (void)hipMemUnmap(e.va + kv.first * B->gran, kv.second.second * B->gran);
+            (void)hipMemRelease(kv.second.first);
+        }
+        if (e.va) (void)hipMemAddressFree(e.va, e.reserved);
+    }
     if (B->pin) (void)hipHostFree(B->pin);
     delete B;
 }
@@ -1434,7 +1560,7 @@ bool batch_reusable(const sapdd_batch *B, const sapdd_field *f, const sapdd_para
 int batch_release_slots(sapdd_batch *B) {
     for (int r = 0; r < B->cap; ++r)
         if (B->slots[r].used) {
-            sap_clover_release(B->f, B->slots[r].kappa, B->prec);
+            sap_clover_release(B->f, B->slots[r].kappa, lprec(B->prec));
             B->slots[r].used = false;
         }
     return SAPDD_OK;
@@ -1492,18 +1618,18 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     const int nwg_b = blas_partials(B->ncx, 1);
     const size_t meta_bytes = (size_t)cap * (2 * sizeof(void *) + sizeof(double));
     do {
-        if ((r = lo_copies(c, f, B->prec)) != SAPDD_OK) break;
+        if ((r = lo_copies(c, f, lprec(B->prec))) != SAPDD_OK) break;
         if ((r = bfield(B, cap * (B->m + 1), P64, 24, &B->Vb)) != SAPDD_OK) break;
         if ((r = bfield(B, cap * B->m, B->zprec, 24, &B->Zb)) != SAPDD_OK) break;
         if ((r = bfield(B, cap, P64, 24, &B->Bb)) != SAPDD_OK) break;
         if ((r = bfield(B, cap, P64, 24, &B->Xb)) != SAPDD_OK) break;
-        if ((r = bfield(B, cap, B->prec, 12, &B->ss.rres)) != SAPDD_OK) break;
-        if ((r = bfield(B, cap, B->prec, 24, &B->ss.delta)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, sprec(B->prec), 12, &B->ss.rres)) != SAPDD_OK) break;
+        if ((r = bfield(B, cap, sprec(B->prec), 24, &B->ss.delta)) != SAPDD_OK) break;
         if ((r = balloc(B, meta_bytes, &q)) != SAPDD_OK) break;
         B->ss.X = (const void **)q;
         B->ss.Xsc = (const float **)((char *)q + cap * sizeof(void *));
         B->ss.kappa = (double *)((char *)q + 2 * cap * sizeof(void *));
-        B->ss.links = links_of(f, B->prec);
+        B->ss.links = links_of(f, lprec(B->prec));
         if ((r = balloc(B, (size_t)cap * B->CST * 8, &q)) != SAPDD_OK) break;
         B->coef = (double *)q;
         if ((r = balloc(B, (size_t)cap * (B->m + 1) * 8, &q)) != SAPDD_OK) break;
@@ -1560,7 +1686,7 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
         }
     if (r < 0) return fail(c, SAPDD_EFULL, "no free slot in the batch (capacity %d)", B->cap);
     Fld xf;
-    CHK(sap_clover(c, B->f, kappa, B->prec, &xf, true));
+    CHK(sap_clover(c, B->f, kappa, lprec(B->prec), &xf, true));
     Slot &s = B->slots[r];
     s = Slot();
     s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
@@ -1692,7 +1818,7 @@ int sapdd_batch_take(sapdd_batch *B, int slot, double *x, int flags, sapdd_stats
         HIPCHK(c, hipMemcpyAsync(x, dst, (size_t)B->NS * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int status = s.status;
-    sap_clover_release(B->f, s.kappa, B->prec);
+    sap_clover_release(B->f, s.kappa, lprec(B->prec));
     s = Slot();
     s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
     s.cs.assign(B->m, 0.0);

@@ -78,7 +78,7 @@ template <class S, class R> struct SiteLinks<S, R, true> {
         const VT *p = reinterpret_cast<const VT *>(base);
 #pragma unroll
         for (int v = 0; v < 72 / W; ++v) u[v] = ld_vec<NT>(p + vec_index<S, 72>(bp, v, s, Vbh));
-        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
+        if constexpr (Storage<S>::scaled) sc = (R)*gmem(scale + bp * Vbh + s);
         else sc = (R)1;
     }
     // Link MU without the FP16 site scale (see scale()).
@@ -132,7 +132,7 @@ template <class S, class R> struct CloverRegs {
         const VT *p = reinterpret_cast<const VT *>(base);
 #pragma unroll
         for (int v = 0; v < 72 / W; ++v) x[v] = ld_vec<NT>(p + vec_index<S, 72>(bp, v, s, Vbh));
-        if constexpr (Storage<S>::scaled) sc = (R)scale[bp * Vbh + s];
+        if constexpr (Storage<S>::scaled) sc = (R)*gmem(scale + bp * Vbh + s);
         else sc = (R)1;
     }
     // Entry k without the FP16 site scale (clover_mul applies it).

@@ -76,15 +76,23 @@ template <class S> struct CFieldPtr {
     const float *scale;
 };
 
+// Every field these helpers touch lives in device (global) memory. Pointers that pass
+// through structs lose that information in the compiler, which then emits flat
+// instructions: those also count against the LDS wait counter, so an LDS read would wait
+// for every outstanding field load. The casts below keep them global loads and stores.
+#define SAPDD_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ const SAPDD_GLOBAL T *gmem(const T *p) { return (const SAPDD_GLOBAL T *)p; }
+template <class T> __device__ __forceinline__ SAPDD_GLOBAL T *gmem(T *p) { return (SAPDD_GLOBAL T *)p; }
+
 // One 16-byte vector load / store. NT = true marks data that is streamed through once
 // (non-temporal cache hint); fields that other workgroups re-read keep the default.
 template <bool NT, class VT> __device__ __forceinline__ VT ld_vec(const VT *p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
+    if constexpr (NT) return __builtin_nontemporal_load(gmem(p));
+    else return *gmem(p);
 }
 template <bool NT, class VT> __device__ __forceinline__ void st_vec(VT *p, const VT &x) {
-    if constexpr (NT) __builtin_nontemporal_store(x, p);
-    else *p = x;
+    if constexpr (NT) __builtin_nontemporal_store(x, gmem(p));
+    else *gmem(p) = x;
 }
 
 // Reals [K0, K0 + K) of site (bp, s) of an N-real field, through whole 16-byte vectors.
@@ -97,7 +105,7 @@ __device__ __forceinline__ void load_reals(const S *__restrict__ data, const flo
     constexpr int v0 = K0 / W, v1 = (K0 + K - 1) / W;
     const VT *p = reinterpret_cast<const VT *>(data);
     R sc = (R)1;
-    if constexpr (Storage<S>::scaled && !RAW) sc = (R)scale[bp * Vbh + s];
+    if constexpr (Storage<S>::scaled && !RAW) sc = (R)*gmem(scale + bp * Vbh + s);
 #pragma unroll
     for (int v = v0; v <= v1; ++v) {
         const VT x = ld_vec<NT>(p + vec_index<S, N>(bp, v, s, Vbh));
@@ -116,7 +124,7 @@ __device__ __forceinline__ void load_reals(const S *__restrict__ data, const flo
 // FP16 per-site scale of site (bp, s) (1 for unscaled storage).
 template <class R, class S>
 __device__ __forceinline__ R site_scale(const float *__restrict__ scale, int64_t bp, int s, int Vbh) {
-    if constexpr (Storage<S>::scaled) return (R)scale[bp * Vbh + s];
+    if constexpr (Storage<S>::scaled) return (R)*gmem(scale + bp * Vbh + s);
     else return (R)1;
 }
 
@@ -144,7 +152,7 @@ __device__ __forceinline__ void store_site(S *__restrict__ data, float *__restri
 #pragma unroll
         for (int k = 0; k < N; ++k) m = fmaxf(m, fabsf((float)in[k]));
         const float inv = fp16_site_inv(m);
-        scale[bp * Vbh + s] = inv > 0.f ? m : 0.f;
+        *gmem(scale + bp * Vbh + s) = inv > 0.f ? m : 0.f;
 #pragma unroll
         for (int v = 0; v < N / W; ++v) {
             VT x;

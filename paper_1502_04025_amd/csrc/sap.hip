@@ -18,12 +18,15 @@
 //
 // Clover input X per rhs: X = kappa T on even sites (A_e = 1 + X) and
 // X = A_o^-1 - 1 on odd sites (A_o^-1 = 1 + X).
+#include <cstdlib>
+#include <cstring>
+
 #include "blockgeo.hpp"
 #include "kernels.hpp"
 
 namespace sapdd {
 
-template <class S, class P> struct SapArgs {
+template <class S, class SS, class P> struct SapArgs {  // S: links and clover, SS: spinors
     Geom geo;
     const S *links;
     const float *lscale;
@@ -34,9 +37,9 @@ template <class S, class P> struct SapArgs {
     const double *eta_scale;
     int eta_scale_stride;
     int64_t eta_stride;  // doubles per rhs
-    S *rres;
+    SS *rres;
     float *rres_sc;
-    S *delta;
+    SS *delta;
     float *delta_sc;
     P *psi;
     int64_t psi_stride;  // elements per rhs
@@ -103,9 +106,10 @@ template <class S, class R, int Vbh> struct LdsClover {
 // Hops into site x across its block faces in direction mu, from the neighbouring blocks'
 // corrections delta: rho += kappa * [ (1 - gamma) U_mu(x) delta(x + mu) on the forward
 // face, (1 + gamma) U_mu(x - mu)^+ delta(x - mu) on the backward face ].
-template <int MU, class BK, class S, class P, class R, class LK>
-__device__ __forceinline__ void gather_dir(const SapArgs<S, P> &a, const SiteInfo &si, const LK &U, const int (&g)[4],
-                                           const S *dlt, const float *dlt_sc, R kappa, R (&rho)[24]) {
+template <int MU, class BK, class S, class SS, class P, class R, class LK>
+__device__ __forceinline__ void gather_dir(const SapArgs<S, SS, P> &a, const SiteInfo &si, const LK &U,
+                                           const int (&g)[4], const SS *dlt, const float *dlt_sc, R kappa,
+                                           R (&rho)[24]) {
     constexpr int Vbh = BK::Vbh;
     const Geom &geo = a.geo;
     const int B[4] = {BK::bx, BK::by, BK::bz, BK::bt};
@@ -146,9 +150,9 @@ __device__ __forceinline__ void gather_dir(const SapArgs<S, P> &a, const SiteInf
     }
 }
 
-template <class BK, class S, class R, class P>
+template <class BK, class S, class SS, class R, class P>
 __global__ __launch_bounds__(BK::NT) __attribute__((amdgpu_waves_per_eu(SAPDD_SAP_WAVES_PER_EU)))
-void sap_half_kernel(SapArgs<S, P> a) {
+void sap_half_kernel(SapArgs<S, SS, P> a) {
     constexpr int Vbh = BK::Vbh;
     constexpr bool CACHE_L = sizeof(R) == 4 && SAPDD_SAP_CACHE_LINKS;
     constexpr bool CACHE_X = sizeof(R) == 4 && SAPDD_SAP_CACHE_CLOVER;
@@ -207,7 +211,7 @@ void sap_half_kernel(SapArgs<S, P> a) {
         else Xc.mul(in, out, (R)1);
     };
 
-    S *dlt = a.delta + (int64_t)rhs * V * 24;
+    SS *dlt = a.delta + (int64_t)rhs * V * 24;
     float *dlt_sc = a.delta_sc ? a.delta_sc + (int64_t)rhs * V : nullptr;
 
     // Per-thread spinors. Even sites: A = MR residual r, B = MR solution; odd sites:
@@ -319,9 +323,278 @@ void sap_half_kernel(SapArgs<S, P> a) {
     }
 }
 
-template <class BK, class S, class R, class P>
+// ---------------------------------------------------------------------------- pair form
+// The same half-sweep with one thread per pair of sites: thread s owns the even site and
+// the odd site with half index s of its block, so a workgroup has Vbh threads and every
+// wave works in both halves of a hop (it pushes from its site of the source parity, then
+// pulls into its site of the other parity). A workgroup then needs half the waves and
+// one hop buffer, and two (block, rhs) workgroups share a CU: while one waits at a
+// barrier or on memory, the other issues. The split-parity kernel above leaves the odd
+// waves idle while the even ones push and vice versa.
+//
+// The odd-site block residual rho_o, needed again at the end (delta_o = A_o^-1 (rho_o +
+// kappa H_oe delta_e)), is parked in the thread's own delta slots, which nobody reads
+// during this launch (the gather reads the other colour's corrections) and which the
+// thread overwrites with its final delta: 24 values of the arithmetic type fit the two
+// sites' slots in every storage precision, and no other thread touches them.
+template <class BK> struct PairBlk {
+    static constexpr int NT = BK::Vbh;
+    static constexpr int W = NT < 64 ? NT : 64;
+    static constexpr int NW = (NT + 63) / 64;
+};
+
+// In-block hop between the parities in pair form: this thread pushes `in` from its site
+// of parity SRC and receives `out` at its site of the other parity.
+template <int SRC, class BK, bool TAIL = true, class R, class LK, int WANT>
+__device__ __forceinline__ void pair_hop(const SiteInfo &se, const SiteInfo &so, const LK &Ue, const LK &Uo,
+                                         const R (&in)[24], R (&out)[24], HopLds<BK, R, WANT> &lds) {
+    constexpr int Vbh = BK::Vbh;
+    R *__restrict__ sp = lds.sp();
+    R *__restrict__ hb = lds.hb();
+    const SiteInfo &ss = SRC == 0 ? se : so;
+    const SiteInfo &sr = SRC == 0 ? so : se;
+    const LK &Us = SRC == 0 ? Ue : Uo;
+    const LK &Ur = SRC == 0 ? Uo : Ue;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) sp[k * Vbh + ss.s] = in[k];
+    push_dir<0, BK>(ss, Us, in, hb);
+    push_dir<1, BK>(ss, Us, in, hb);
+    push_dir<2, BK>(ss, Us, in, hb);
+    push_dir<3, BK>(ss, Us, in, hb);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 24; ++k) out[k] = 0;
+    pull_dir<0, BK>(sr, Ur, out, sp, hb);
+    pull_dir<1, BK>(sr, Ur, out, sp, hb);
+    pull_dir<2, BK>(sr, Ur, out, sp, hb);
+    pull_dir<3, BK>(sr, Ur, out, sp, hb);
+    if constexpr (HopLds<BK, R, WANT>::NBUF == 2) {
+        lds.cur ^= 1;
+    } else if constexpr (TAIL) {
+        __syncthreads();
+    }
+}
+
+// Park / fetch 24 values of type R in the 16-byte vectors of the thread's two delta slots
+// (even site first), in a thread-private order.
+template <class S, class R>
+__device__ __forceinline__ void park(S *dlt, int64_t b, int s, int Vbh, const R (&v)[24]) {
+    typedef typename Vec<S>::type VS;
+    typedef R VR __attribute__((ext_vector_type(16 / sizeof(R))));
+    constexpr int PER = 16 / sizeof(R);
+    constexpr int NV = 24 / PER;           // vectors to park
+    constexpr int NS = 24 / Vec<S>::W;     // vectors per site slot
+    static_assert(NV <= 2 * NS, "two delta slots hold the parked spinor");
+    VS *p = reinterpret_cast<VS *>(dlt);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        VR x;
+#pragma unroll
+        for (int w = 0; w < PER; ++w) x[w] = v[q * PER + w];
+        const int site_p = q / NS, vv = q % NS;
+        *gmem(reinterpret_cast<VR *>(p + vec_index<S, 24>(2 * b + site_p, vv, s, Vbh))) = x;
+    }
+}
+template <class S, class R>
+__device__ __forceinline__ void fetch(const S *dlt, int64_t b, int s, int Vbh, R (&v)[24]) {
+    typedef typename Vec<S>::type VS;
+    typedef R VR __attribute__((ext_vector_type(16 / sizeof(R))));
+    constexpr int PER = 16 / sizeof(R);
+    constexpr int NV = 24 / PER;
+    constexpr int NS = 24 / Vec<S>::W;
+    const VS *p = reinterpret_cast<const VS *>(dlt);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int site_p = q / NS, vv = q % NS;
+        const VR x = *gmem(reinterpret_cast<const VR *>(p + vec_index<S, 24>(2 * b + site_p, vv, s, Vbh)));
+#pragma unroll
+        for (int w = 0; w < PER; ++w) v[q * PER + w] = x[w];
+    }
+}
+
+#ifndef SAPDD_SAP_PAIR_WAVES_PER_EU
+#define SAPDD_SAP_PAIR_WAVES_PER_EU 2
+#endif
+
+template <class BK, class S, class SS, class R, class P>
+__global__ __launch_bounds__(PairBlk<BK>::NT) __attribute__((amdgpu_waves_per_eu(SAPDD_SAP_PAIR_WAVES_PER_EU)))
+void sap_pair_kernel(SapArgs<S, SS, P> a) {
+    constexpr int Vbh = BK::Vbh;
+    typedef PairBlk<BK> PB;
+    // one hop buffer: two workgroups per CU need their LDS to fit twice
+    __shared__ R lds_hop[HopLds<BK, R, 1>::PER];
+    __shared__ R red[3 * PB::NW];
+    HopLds<BK, R, 1> lds{lds_hop, 0};
+
+    const Geom &geo = a.geo;
+    const int s = threadIdx.x;
+    const SiteInfo se = site_info<BK>(s);
+    const SiteInfo so = site_info<BK>(Vbh + s);
+    // (block, rhs) numbering as in the split-parity kernel: the rhs of one block follow
+    // each other on one XCD, so its links and clover come from that XCD's L2
+    const int64_t w = blockIdx.x;
+    const int64_t kq = w >> 3;
+    const int slot = (int)(kq % a.nact);
+    const int64_t kb = (kq / a.nact) * 8 + (w & 7);
+    if (kb >= a.nblk) return;  // padding of the last group of 8 (uniform per workgroup)
+    const int64_t b = colour_block(geo.G, a.colour, kb);
+    const int rhs = a.active[slot];
+    const R kappa = (R)a.kappa[rhs];
+    const int64_t V = geo.V;
+
+    SiteLinks<S, R, false> Ue, Uo;
+    Ue.init(a.links, a.lscale, 2 * b, s, Vbh);
+    Uo.init(a.links, a.lscale, 2 * b + 1, s, Vbh);
+    SiteClover<S, R, false> Xe, Xo;  // X = kappa T (even: A_e = 1 + X), A_o^-1 - 1 (odd)
+    const S *Xr = (const S *)a.X[rhs];
+    const float *Xs = a.Xsc ? a.Xsc[rhs] : nullptr;
+    Xe.init(Xr, Xs, 2 * b, s, Vbh);
+    Xo.init(Xr, Xs, 2 * b + 1, s, Vbh);
+
+    SS *dlt = a.delta + (int64_t)rhs * V * 24;
+    float *dlt_sc = a.delta_sc ? a.delta_sc + (int64_t)rhs * V : nullptr;
+    SS *rr = a.rres + (int64_t)rhs * V * 12;
+    float *rr_sc = a.rres_sc ? a.rres_sc + (int64_t)rhs * (V / 2) : nullptr;
+
+    // A: even rho, then the MR residual r; B: odd rho, then the MR solution x (even);
+    // T, H: scratch
+    R A[24], B[24], T[24], H[24];
+
+    // ---- 1. block residual rho (even into A, odd into B)
+    if (a.mode < 2) {
+        const double *eta = a.eta + rhs * a.eta_stride;
+        const double f = a.eta_scale ? a.eta_scale[(int64_t)rhs * a.eta_scale_stride] : 1.0;
+        double e[24];
+        load_site<double, 24>(eta, nullptr, 2 * b, s, Vbh, e);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) A[k] = (R)(e[k] * f);
+        load_site<double, 24>(eta, nullptr, 2 * b + 1, s, Vbh, e);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) B[k] = (R)(e[k] * f);
+    } else {
+        load_site<R, 24>(rr, rr_sc, b, s, Vbh, A);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) B[k] = 0;
+    }
+    if (a.mode >= 1) {
+        int g[4];
+        block_coords(geo.G, b, g);
+        gather_dir<0, BK>(a, se, Ue, g, dlt, dlt_sc, kappa, A);
+        gather_dir<1, BK>(a, se, Ue, g, dlt, dlt_sc, kappa, A);
+        gather_dir<2, BK>(a, se, Ue, g, dlt, dlt_sc, kappa, A);
+        gather_dir<3, BK>(a, se, Ue, g, dlt, dlt_sc, kappa, A);
+        gather_dir<0, BK>(a, so, Uo, g, dlt, dlt_sc, kappa, B);
+        gather_dir<1, BK>(a, so, Uo, g, dlt, dlt_sc, kappa, B);
+        gather_dir<2, BK>(a, so, Uo, g, dlt, dlt_sc, kappa, B);
+        gather_dir<3, BK>(a, so, Uo, g, dlt, dlt_sc, kappa, B);
+    }
+    // rho_o is needed again at the end: park it in this thread's delta slots
+    park<SS, R>(dlt, b, s, Vbh, B);
+
+    // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o
+    Xo.mul(B, T, (R)1);
+    pair_hop<1, BK>(se, so, Ue, Uo, T, H, lds);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        A[k] = fmac(kappa, H[k], A[k]);
+        B[k] = 0;
+    }
+
+    // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
+    const R k2 = kappa * kappa;
+    for (int it = 0; it < a.nmr; ++it) {
+        pair_hop<0, BK>(se, so, Ue, Uo, A, H, lds);  // odd: H = H_oe r
+        Xo.mul(H, T, (R)1);                          // odd: T = A_o^-1 H_oe r
+        // even: H = H_eo T; the reduction's barrier below separates these reads from the
+        // next hop's writes
+        pair_hop<1, BK, false>(se, so, Ue, Uo, T, H, lds);
+        Xe.mul(A, T, (R)1);  // even: T = A_e r, then p = T - kappa^2 H
+        R pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) T[k] = fmac(-k2, H[k], T[k]);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            pr_re = fmac(T[2 * k], A[2 * k], pr_re);
+            pr_re = fmac(T[2 * k + 1], A[2 * k + 1], pr_re);
+            pr_im = fmac(T[2 * k], A[2 * k + 1], pr_im);
+            pr_im = fmac(-T[2 * k + 1], A[2 * k], pr_im);
+            pp = fmac(T[2 * k], T[2 * k], pp);
+            pp = fmac(T[2 * k + 1], T[2 * k + 1], pp);
+        }
+        block_sum3<PB>(pr_re, pr_im, pp, red);
+        R ar = 0, ai = 0;
+        if (pp > 0) {
+            ar = pr_re / pp;
+            ai = pr_im / pp;
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const R rr_ = A[2 * k], ri = A[2 * k + 1];
+            const R qr = T[2 * k], qi = T[2 * k + 1];
+            B[2 * k] = fmac(ar, rr_, fmac(-ai, ri, B[2 * k]));
+            B[2 * k + 1] = fmac(ar, ri, fmac(ai, rr_, B[2 * k + 1]));
+            A[2 * k] = fmac(-ar, qr, fmac(ai, qi, rr_));
+            A[2 * k + 1] = fmac(-ar, qi, fmac(-ai, qr, ri));
+        }
+    }
+
+    // ---- 4. delta: even B, odd A_o^-1 (rho_o + kappa H_oe delta_e)
+    pair_hop<0, BK>(se, so, Ue, Uo, B, H, lds);
+    fetch<SS, R>(dlt, b, s, Vbh, T);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) T[k] = fmac(kappa, H[k], T[k]);
+    Xo.mul(T, H, (R)1);  // H = delta_o
+
+    // ---- 5. outputs: psi += delta, keep delta and the even-site residual
+    P *ps = a.psi + rhs * a.psi_stride;
+    if (a.mode == 2) {
+        R old[24];
+        load_site<R, 24>(ps, nullptr, 2 * b, s, Vbh, old);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) old[k] += B[k];
+        store_site<R, 24>(ps, nullptr, 2 * b, s, Vbh, old);
+        load_site<R, 24>(ps, nullptr, 2 * b + 1, s, Vbh, old);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) old[k] += H[k];
+        store_site<R, 24>(ps, nullptr, 2 * b + 1, s, Vbh, old);
+    } else {
+        store_site<R, 24>(ps, nullptr, 2 * b, s, Vbh, B);
+        store_site<R, 24>(ps, nullptr, 2 * b + 1, s, Vbh, H);
+    }
+    if (a.write_state) {
+        store_site<R, 24>(dlt, dlt_sc, 2 * b, s, Vbh, B);
+        store_site<R, 24>(dlt, dlt_sc, 2 * b + 1, s, Vbh, H);
+        store_site<R, 24>(rr, rr_sc, b, s, Vbh, A);
+    }
+}
+
+// Which form runs a half-sweep (both compute the same half-sweep, each in its own fixed
+// order; both are checked against the oracle). The pair form needs two workgroups per CU to pay off, and its FP32-storage variants
+// spill registers: measured on 48^3 x 96 (FP16 storage, 12 RHS, 124416 workgroups) it
+// takes 23.5 ms per half-sweep against 29.3 ms, on 16^3 x 32 (FP32 storage, one RHS, 128
+// workgroups) 142 us against 73 us. So: the pair form for FP16 links and clover on
+// lattices with at least one block of each colour per CU, the split-parity form otherwise
+// (it also serves FP64 and 2^4 blocks). The choice depends on the geometry only, never on
+// how many right-hand sides share the launch, so a right-hand side gets the same bits
+// alone and in any batch. SAPDD_SAP_KERNEL=pair or =split in the environment forces one.
+static int sap_form_override() {
+    static const int v = [] {
+        const char *e = getenv("SAPDD_SAP_KERNEL");
+        if (e && strcmp(e, "split") == 0) return 1;
+        if (e && strcmp(e, "pair") == 0) return 2;
+        return 0;
+    }();
+    return v;
+}
+template <class S> static bool sap_pair_form(int64_t nblk) {
+    const int o = sap_form_override();
+    if (o) return o == 2;
+    return Storage<S>::scaled && nblk >= 256;
+}
+
+template <class BK, class S, class SS, class R, class P>
 static hipError_t sap_typed(const Geom &geo, const SapArgsHost &h, int colour, int mode, int ws, hipStream_t st) {
-    SapArgs<S, P> a;
+    SapArgs<S, SS, P> a;
     a.geo = geo;
     a.links = (const S *)h.links.data;
     a.lscale = h.links.scale;
@@ -332,9 +605,9 @@ static hipError_t sap_typed(const Geom &geo, const SapArgsHost &h, int colour, i
     a.eta_scale = h.eta_scale;
     a.eta_scale_stride = h.eta_scale_stride;
     a.eta_stride = (int64_t)h.eta_stride_rhs * geo.V * 24;
-    a.rres = (S *)h.rres.data;
+    a.rres = (SS *)h.rres.data;
     a.rres_sc = h.rres.scale;
-    a.delta = (S *)h.delta.data;
+    a.delta = (SS *)h.delta.data;
     a.delta_sc = h.delta.scale;
     a.psi = (P *)h.psi;
     a.psi_stride = (int64_t)h.psi_stride_rhs * geo.V * 24;
@@ -348,19 +621,37 @@ static hipError_t sap_typed(const Geom &geo, const SapArgsHost &h, int colour, i
     const int64_t nwg = (geo.Nd / 2 + 7) / 8 * 8 * h.nact;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid((unsigned)nwg);
-    hipLaunchKernelGGL((sap_half_kernel<BK, S, R, P>), grid, dim3(BK::NT), 0, st, a);
+    if constexpr (sizeof(R) == 4 && BK::Vbh >= 128) {
+        if (sap_pair_form<S>(a.nblk)) {
+            hipLaunchKernelGGL((sap_pair_kernel<BK, S, SS, R, P>), grid, dim3(PairBlk<BK>::NT), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((sap_half_kernel<BK, S, SS, R, P>), grid, dim3(BK::NT), 0, st, a);
     return hipGetLastError();
 }
 
+// Storage combinations: (links and clover, Schwarz spinors, output psi). FP16 links and
+// clover with FP32 spinors is the paper's half-precision mode (Sec. 3.3); FP16 spinors as
+// well halve the spinor traffic; FP64 output serves the preconditioned vectors of
+// deflated restarts.
 template <class BK>
 static hipError_t sap_shape(const Geom &geo, const SapArgsHost &h, int colour, int mode, int ws, hipStream_t st) {
-    const int sp = h.links.prec;
-    if (sp == P64 && h.psi_prec == P64) return sap_typed<BK, double, double, double>(geo, h, colour, mode, ws, st);
-    if (sp == P32 && h.psi_prec == P32) return sap_typed<BK, float, float, float>(geo, h, colour, mode, ws, st);
-    if (sp == P16 && h.psi_prec == P32) return sap_typed<BK, half_t, float, float>(geo, h, colour, mode, ws, st);
-    // FP64 output: the preconditioned vectors of deflated restarts
-    if (sp == P32 && h.psi_prec == P64) return sap_typed<BK, float, float, double>(geo, h, colour, mode, ws, st);
-    if (sp == P16 && h.psi_prec == P64) return sap_typed<BK, half_t, float, double>(geo, h, colour, mode, ws, st);
+    const int lp = h.links.prec, sp = h.rres.prec, pp = h.psi_prec;
+    if (h.delta.prec != sp) return hipErrorInvalidValue;
+    if (lp == P64 && sp == P64 && pp == P64)
+        return sap_typed<BK, double, double, double, double>(geo, h, colour, mode, ws, st);
+    if (lp == P32 && sp == P32 && pp == P32) return sap_typed<BK, float, float, float, float>(geo, h, colour, mode, ws, st);
+    if (lp == P16 && sp == P16 && pp == P32)
+        return sap_typed<BK, half_t, half_t, float, float>(geo, h, colour, mode, ws, st);
+    if (lp == P16 && sp == P32 && pp == P32)
+        return sap_typed<BK, half_t, float, float, float>(geo, h, colour, mode, ws, st);
+    if (lp == P32 && sp == P32 && pp == P64)
+        return sap_typed<BK, float, float, float, double>(geo, h, colour, mode, ws, st);
+    if (lp == P16 && sp == P16 && pp == P64)
+        return sap_typed<BK, half_t, half_t, float, double>(geo, h, colour, mode, ws, st);
+    if (lp == P16 && sp == P32 && pp == P64)
+        return sap_typed<BK, half_t, float, float, double>(geo, h, colour, mode, ws, st);
     return hipErrorInvalidValue;
 }
 

@@ -17,16 +17,19 @@ COMBINE_FLOPS = 24
 
 # bytes per site: spinor (24 reals), links (4 x 18 reals), clover (72 reals); FP16 adds
 # one FP32 scale per site to each field
-SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52}
-LINK_BYTES = {"f64": 576, "f32": 288, "f16": 148}
-CLOVER_BYTES = {"f64": 576, "f32": 288, "f16": 148}
-PSI_BYTES = {"f64": 192, "f32": 96, "f16": 96}  # the preconditioner output is FP32 below FP64
+# "f16l" is the Schwarz mode with FP16 links and clover and FP32 spinors
+SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52, "f16l": 96}
+LINK_BYTES = {"f64": 576, "f32": 288, "f16": 148, "f16l": 148}
+CLOVER_BYTES = {"f64": 576, "f32": 288, "f16": 148, "f16l": 148}
+PSI_BYTES = {"f64": 192, "f32": 96, "f16": 96, "f16l": 96}  # the preconditioner output is FP32 below FP64
 
 # MI355X published peaks (single GPU)
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz; the library is compiled without
 # packed FP32 instructions, so FP32 runs at the FP64 vector rate
 ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
+# the published FP32 vector peak counts packed (two-wide) FP32 FMAs
+ALU_PEAK_PUBLISHED_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 
 def internal_fraction(block) -> float:
@@ -56,15 +59,16 @@ def full_dslash_bytes(prec: str, nrhs: int = 1, in_prec: str | None = None) -> f
     return LINK_BYTES[prec] + CLOVER_BYTES[prec] + nrhs * (sin + SPINOR_BYTES[prec])
 
 
-def sap_half_bytes(block, prec: str) -> float:
+def sap_half_bytes(block, prec: str, nrhs: int = 1, nkappa: int = 1) -> float:
     """One Schwarz half-sweep, per site of the swept colour, in the steady state (the
-    stored-residual mode): own links plus the neighbour-owned face links, clover X, the
-    stored even-site residual (read and written), the neighbours' corrections across the
-    faces, psi read-modify-write and the new correction written."""
+    stored-residual mode), for nrhs right-hand sides solved together: own links plus the
+    neighbour-owned face links once, the clover X once per distinct kappa, and per
+    right-hand side the stored even-site residual (read and written), the neighbours'
+    corrections across the faces, psi read-modify-write and the new correction written."""
     f = internal_fraction(block)
     s = SPINOR_BYTES[prec]
-    return ((1 + (1 - f)) * LINK_BYTES[prec] + CLOVER_BYTES[prec] + s / 2 + 8 * (1 - f) * s
-            + 2 * PSI_BYTES[prec] + s + s / 2)
+    per_rhs = s / 2 + 8 * (1 - f) * s + 2 * PSI_BYTES[prec] + s + s / 2
+    return (1 + (1 - f)) * LINK_BYTES[prec] + nkappa * CLOVER_BYTES[prec] + nrhs * per_rhs
 
 
 def sap_half_flops(block, nmr: int) -> float:

@@ -22,9 +22,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsapdd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
-F64, F32, F16 = 0, 1, 2
+F64, F32, F16, F16_LINKS = 0, 1, 2, 3
 DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12 = 1, 2, 4, 8
-PRECS = {"f64": F64, "f32": F32, "f16": F16}
+# "f16l": FP16 links and clover with FP32 Schwarz spinors (Schwarz precision only)
+PRECS = {"f64": F64, "f32": F32, "f16": F16, "f16l": F16_LINKS}
 
 # Entry points declared in include/sapdd.h (the CPU tests check the library exports them).
 EXPORTS = (

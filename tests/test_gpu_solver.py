@@ -2,9 +2,9 @@
 
 SAP output against the oracle's SAP on the same input (relative 2-norm error): FP64
 storage 1e-10 (the same algorithm in the same precision, different summation order);
-FP32 storage 2e-5 and FP16 storage 2e-2 (measured errors of lower-precision storage
-of a nonlinear iteration; the paper prints no values to pin these, so they are bounds on
-measured behaviour). Solves: every right-hand side reaches a true relative residual
+FP32 storage 1e-6 and FP16 storage 1e-3 (about ten times the measured errors, 1.1e-7 and
+1.2e-4, of lower-precision storage of a nonlinear iteration; the paper prints no values
+to pin these, so they are bounds on measured behaviour). Solves: every right-hand side reaches a true relative residual
 <= 1e-10 recomputed by the oracle's FP64 operator, in every precision mode.
 """
 import numpy as np
@@ -17,7 +17,7 @@ from oracle import wilson
 
 pytestmark = pytest.mark.gpu
 
-SAP_TOL = {"f64": 1e-10, "f32": 2e-5, "f16": 2e-2}
+SAP_TOL = {"f64": 1e-10, "f32": 1e-6, "f16": 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -156,14 +156,20 @@ def test_point_sources_multi_rhs(ctx):
         assert oracle_relres(u, t, 0.126, res.x[r], b[r]) <= 1e-10
 
 
-def test_half_precision_keeps_iteration_count(ctx):
-    """Sec. 3.3: half-precision storage did not noticeably change the outer iteration count."""
-    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+@pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((16, 16, 16, 32), (8, 4, 4, 4))])
+def test_half_precision_keeps_iteration_count(ctx, dims, block):
+    """Sec. 3.3: half-precision storage did not noticeably change the outer iteration count,
+    in the paper's mode (FP16 links and clover, FP32 spinors) and with FP16 spinors as well;
+    every solve reaches 1e-10 by the oracle's operator."""
+    print(f"half precision iteration count {dims}", flush=True)
     u, t, f = setup_case(ctx, dims, block)
     b = synthetic.gaussian_source(dims, 1, 17)
-    n32 = f.solve(0.125, b, prec="f32").stats[0]["iters"]
-    n16 = f.solve(0.125, b, prec="f16").stats[0]["iters"]
-    assert abs(n16 - n32) <= 1
+    res = {p: f.solve(0.125, b, prec=p) for p in ("f32", "f16l", "f16")}
+    n = {p: r.stats[0]["iters"] for p, r in res.items()}
+    print(f"  outer iterations {n}", flush=True)
+    assert abs(n["f16l"] - n["f32"]) <= 1 and abs(n["f16"] - n["f32"]) <= 1
+    for r in res.values():
+        assert oracle_relres(u, t, 0.125, r.x[0], b[0]) <= 1e-10
 
 
 def test_start_vector_and_zero_rhs(ctx):
