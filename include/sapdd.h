@@ -176,6 +176,21 @@ int sapdd_apply_block_D(sapdd_ctx *ctx, const sapdd_field *field, double kappa, 
  * 1 + kappa T is singular on some site; ENOMEM if a workspace cannot be allocated. */
 int sapdd_sap(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa, const sapdd_params *params,
               int nrhs, const double *in, double *out);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sapdd_sap with every workspace (the
+ * packed input and output, the Schwarz residual and correction, the clover inverse per
+ * distinct kappa, low-precision links when the field has none yet, per-rhs metadata) in
+ * a fixed 256 MiB array of device memory that each GPU holds from the library's first use
+ * until the process ends. The call allocates nothing, on the device or the host, and
+ * otherwise behaves as sapdd_sap with the same arguments (bit-identical output). Limits:
+ * in and out must be device pointers (SAPDD_DEVICE_PTRS in params->flags), nrhs <= 16,
+ * and the workspaces must fit in 256 MiB (for example 16^3 x 32 with one right-hand side
+ * in any precision); beyond them it returns SAPDD_EINVAL with the size it would need.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU (two
+ * contexts, two host threads or two streams) race and must be serialised by the caller.
+ * SAPDD_EDEVICE if the array has no device address on this device. */
+int sapdd_sap_noalloc(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa,
+                      const sapdd_params *params, int nrhs, const double *in, double *out);
 /* Sec. 3.1 (the outer flexible GMRES, preconditioned by the Schwarz procedure, in FP64
  * with lower-precision preconditioning, Sec. 3.3): solve M x = b for nrhs right-hand
  * sides with SAP-preconditioned FGMRES(m) (a batch of nrhs slots stepped to completion;

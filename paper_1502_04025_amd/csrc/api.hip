@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -443,6 +444,62 @@ double now_s() {
 
 }  // namespace
 
+// ====================================================================== allocation-free SAP
+// Device memory for sapdd_sap_noalloc: a file-scope array each GPU holds until the process
+// ends. Host code never uses its name as an address (that is a host-side stand-in): the
+// device address of every GPU's copy is taken once with hipGetSymbolAddress, with that
+// device current, and kept in noalloc_ptr[device].
+#define SAPDD_NOALLOC_BYTES (256ull << 20)
+#define SAPDD_NOALLOC_MAX_RHS 16
+static __device__ __align__(256) unsigned char scratch[SAPDD_NOALLOC_BYTES];
+
+namespace {
+
+std::mutex noalloc_mu;
+void *noalloc_ptr[64] = {};
+int noalloc_status[64] = {};  // 0 not looked up, 1 ok, -1 lookup failed
+
+// Look up this device's scratch address (the device must be current).
+int noalloc_setup(int device) {
+    if (device < 0 || device >= 64) return SAPDD_EDEVICE;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (noalloc_status[device] == 0) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && ptr) {
+            noalloc_ptr[device] = ptr;
+            noalloc_status[device] = 1;
+        } else {
+            (void)hipGetLastError();
+            noalloc_status[device] = -1;
+        }
+    }
+    return noalloc_status[device] == 1 ? SAPDD_OK : SAPDD_EDEVICE;
+}
+
+struct NoallocMeta {
+    const void *X[SAPDD_NOALLOC_MAX_RHS];
+    const float *Xsc[SAPDD_NOALLOC_MAX_RHS];
+    double kappa[SAPDD_NOALLOC_MAX_RHS];
+    int n;
+};
+
+// Writes the per-rhs clover pointers, kappa and the identity slot list into the scratch
+// memory and clears the singular-pivot flag (a kernel, not a memset).
+__global__ void noalloc_meta_kernel(NoallocMeta m, const void **X, const float **Xsc, double *kappa, int *ident,
+                                    int *flag) {
+    const int i = threadIdx.x;
+    if (i < m.n) {
+        X[i] = m.X[i];
+        Xsc[i] = m.Xsc[i];
+        kappa[i] = m.kappa[i];
+        ident[i] = i;
+    }
+    if (i == 0) *flag = 0;
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -464,6 +521,9 @@ int sapdd_create(int device, void *hip_stream, sapdd_ctx **out) {
             delete c;
             return SAPDD_EDEVICE;
         }
+    // the allocation-free entry point's memory on this device (a failed lookup only
+    // disables that entry point, which then reports it)
+    (void)noalloc_setup(device);
     *out = c;
     return SAPDD_OK;
 }
@@ -691,6 +751,109 @@ int sapdd_sap(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const sa
     HIPCHK(c, launch_unpack(g, 24, nrhs, psi, dst, c->stream));
     if (!(p->flags & SAPDD_DEVICE_PTRS)) HIPCHK(c, hipMemcpyAsync(out, dst, nd * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SAPDD_OK;
+}
+
+int sapdd_sap_noalloc(sapdd_ctx *c, const sapdd_field *fc, const double *kappa, const sapdd_params *p, int nrhs,
+                      const double *in, double *out) {
+    if (!c || !fc || !kappa || !in || !out) return fail(c, SAPDD_EINVAL, "null argument");
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    const sapdd_field *f = fc;
+    CHK(check_params(c, f, p));
+    if (!(p->flags & SAPDD_DEVICE_PTRS))
+        return fail(c, SAPDD_EINVAL, "sapdd_sap_noalloc takes device pointers only (SAPDD_DEVICE_PTRS)");
+    if (nrhs < 1 || nrhs > SAPDD_NOALLOC_MAX_RHS)
+        return fail(c, SAPDD_EINVAL, "sapdd_sap_noalloc takes 1..%d right-hand sides", SAPDD_NOALLOC_MAX_RHS);
+    for (int r = 0; r < nrhs; ++r)
+        if (!(kappa[r] > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
+    if (noalloc_setup(c->device) != SAPDD_OK)
+        return fail(c, SAPDD_EDEVICE, "the scratch memory of device %d has no device address", c->device);
+    const Geom &g = f->geo;
+    const int prec = p->sap_prec, lp = lprec(prec), sp = sprec(prec);
+    const int psi_prec = prec == P64 ? P64 : P32;
+    const size_t V = (size_t)g.V;
+    auto al = [](size_t n) { return (n + 255) / 256 * 256; };
+    auto fld_bytes = [&](size_t ncomp, size_t nf, int pr) {  // data, then FP16 scales (V per field)
+        const size_t d = al(V * ncomp * nf * prec_bytes(pr));
+        return pr == P16 ? d + al(V * nf * sizeof(float)) : d;
+    };
+    // distinct kappa values get one clover X each (fixed-size host arrays: nothing here
+    // allocates, on the device or on the host)
+    double kv[SAPDD_NOALLOC_MAX_RHS];
+    int kidx[SAPDD_NOALLOC_MAX_RHS], nk = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        int q = 0;
+        while (q < nk && kv[q] != kappa[r]) ++q;
+        if (q == nk) kv[nk++] = kappa[r];
+        kidx[r] = q;
+    }
+    const bool need_links = lp != P64 && !f->links_lo[lp].data;
+    const size_t off_meta = 256;
+    const size_t meta_bytes = al(nrhs * (2 * sizeof(void *) + sizeof(double) + sizeof(int)));
+    const size_t off_x = off_meta + meta_bytes;
+    const size_t x_bytes = fld_bytes(72, 1, lp);
+    const size_t off_links = off_x + nk * x_bytes;
+    const size_t off_eta = off_links + (need_links ? fld_bytes(72, 1, lp) : 0);
+    const size_t off_psi = off_eta + fld_bytes(24, nrhs, P64);
+    const size_t off_rres = off_psi + fld_bytes(24, nrhs, psi_prec);
+    const size_t off_delta = off_rres + fld_bytes(12, nrhs, sp);
+    const size_t total = off_delta + fld_bytes(24, nrhs, sp);
+    if (total > SAPDD_NOALLOC_BYTES)
+        return fail(c, SAPDD_EINVAL,
+                    "sapdd_sap_noalloc needs %zu bytes of scratch for this lattice, precision and %d right-hand "
+                    "sides; its fixed maximum is %llu",
+                    total, nrhs, (unsigned long long)SAPDD_NOALLOC_BYTES);
+    char *base = (char *)noalloc_ptr[c->device];
+    auto fld = [&](size_t off, size_t ncomp, size_t nf, int pr) {
+        return Fld{base + off, pr == P16 ? (float *)(base + off + al(V * ncomp * nf * prec_bytes(pr))) : nullptr, pr};
+    };
+    int *flag = (int *)base;
+    const void **dX = (const void **)(base + off_meta);
+    const float **dXsc = (const float **)(base + off_meta + nrhs * sizeof(void *));
+    double *dk = (double *)(base + off_meta + 2 * nrhs * sizeof(void *));
+    int *ident = (int *)(base + off_meta + 2 * nrhs * sizeof(void *) + nrhs * sizeof(double));
+    // clover X per distinct kappa (singular pivots flagged), low-precision links if the
+    // field has none yet, per-rhs metadata
+    NoallocMeta m{};
+    m.n = nrhs;
+    Fld xs[SAPDD_NOALLOC_MAX_RHS];
+    for (int q = 0; q < nk; ++q) xs[q] = fld(off_x + q * x_bytes, 72, 1, lp);
+    for (int r = 0; r < nrhs; ++r) {
+        m.X[r] = xs[kidx[r]].data;
+        m.Xsc[r] = xs[kidx[r]].scale;
+        m.kappa[r] = kappa[r];
+    }
+    hipLaunchKernelGGL(noalloc_meta_kernel, dim3(1), dim3(64), 0, c->stream, m, dX, dXsc, dk, ident, flag);
+    HIPCHK(c, hipGetLastError());
+    for (int q = 0; q < nk; ++q) HIPCHK(c, launch_sap_clover(g, f->tclov64, kv[q], xs[q], flag, c->stream));
+    SapState s;
+    if (lp == P64) {
+        s.links = Fld{f->links64, nullptr, P64};
+    } else if (need_links) {
+        s.links = fld(off_links, 72, 1, lp);
+        HIPCHK(c, launch_convert(g, 72, 1, f->links64, s.links, c->stream));
+    } else {
+        s.links = f->links_lo[lp];
+    }
+    s.rres = fld(off_rres, 12, nrhs, sp);
+    s.delta = fld(off_delta, 24, nrhs, sp);
+    s.X = dX;
+    s.Xsc = dXsc;
+    s.kappa = dk;
+    const Fld eta = fld(off_eta, 24, nrhs, P64), psi = fld(off_psi, 24, nrhs, psi_prec);
+    HIPCHK(c, launch_pack(g, 24, nrhs, in, eta, c->stream));
+    // the kernel profiler's event pool may grow: it stays off inside this call
+    const bool prof = c->prof;
+    c->prof = false;
+    const int rs = sap_run(c, g, s, p, (const double *)eta.data, 1, nullptr, 0, psi.data, psi_prec, 1, ident, nrhs);
+    c->prof = prof;
+    CHK(rs);
+    HIPCHK(c, launch_unpack(g, 24, nrhs, psi, out, c->stream));
+    int sing = 0;
+    HIPCHK(c, hipMemcpyAsync(&sing, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (sing) return fail(c, SAPDD_ESINGULAR, "clover block 1 + kappa T is singular for one of the kappa values");
     return SAPDD_OK;
 }
 

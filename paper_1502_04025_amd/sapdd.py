@@ -31,7 +31,7 @@ PRECS = {"f64": F64, "f32": F32, "f16": F16, "f16l": F16_LINKS}
 EXPORTS = (
     "sapdd_create", "sapdd_destroy", "sapdd_last_error", "sapdd_load_gauge",
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
-    "sapdd_apply_block_D", "sapdd_sap", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
+    "sapdd_apply_block_D", "sapdd_sap", "sapdd_sap_noalloc", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
     "sapdd_profile", "sapdd_batch_create", "sapdd_batch_destroy", "sapdd_batch_add",
     "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
     "sapdd_mg_prolongator", "sapdd_mg_coarse_operator", "sapdd_mg_coarse_solve", "sapdd_mg_precond",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_apply_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
     lib.sapdd_apply_block_D.argtypes = [VP, VP, D, I, I, VP, VP, I]
     lib.sapdd_sap.argtypes = [VP, VP, P(D), P(Params), I, VP, VP]
+    lib.sapdd_sap_noalloc.argtypes = [VP, VP, P(D), P(Params), I, VP, VP]
     lib.sapdd_solve.argtypes = [VP, VP, P(D), P(Params), I, VP, VP, P(Stats)]
     lib.sapdd_solve_footprint.argtypes = [VP, P(Params), I]
     lib.sapdd_solve_footprint.restype = C.c_longlong
@@ -295,6 +296,19 @@ class Field:
             prm.flags |= DEVICE_PTRS
         self.ctx._check(self.ctx.lib.sapdd_sap(self.ctx.h, self.h, kap.ctypes.data_as(C.POINTER(C.c_double)),
                                                C.byref(prm), nrhs, pi, po))
+        return out
+
+    def sap_noalloc(self, kappa, psi, out, **kw):
+        """SAP(psi) through the allocation-free entry point (psi and out must be device tensors)."""
+        prm = self.params(**kw)
+        nrhs = self._nrhs(psi)
+        kap = np.broadcast_to(np.asarray(kappa, dtype=np.float64), (nrhs,)).copy()
+        pi, dev = _ptr(psi)
+        po, dev2 = _ptr(out, writable=True)
+        if dev and dev2:
+            prm.flags |= DEVICE_PTRS  # the library rejects host arrays itself
+        self.ctx._check(self.ctx.lib.sapdd_sap_noalloc(self.ctx.h, self.h, kap.ctypes.data_as(C.POINTER(C.c_double)),
+                                                       C.byref(prm), nrhs, pi, po))
         return out
 
     def footprint(self, nrhs=1, **kw) -> int:
