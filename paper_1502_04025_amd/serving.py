@@ -6,12 +6,19 @@ with its own context, HIP stream and solver batch (`sapdd_batch_*`). A worker ad
 waiting requests of its volume into free batch slots between FGMRES restart cycles,
 steps the batch (one restart cycle for every active slot: all right-hand sides of the
 volume in one multi-RHS launch sequence), and hands back every request whose
-right-hand sides have all converged. Workers of different volumes run concurrently,
-so their kernels overlap on the device.
+right-hand sides have all finished. Workers of different volumes run concurrently, so
+their kernels overlap on the device.
 
-Admission is by HBM footprint: the slot capacity of every volume's batch is planned
-from the memory budget (fields + per-RHS Krylov state + clover inverses), and a request
-enters only when its right-hand sides fit in free slots of its volume.
+Admission is by HBM footprint from one shared budget: the resident fields, a cache of
+clover inverses per volume and a reserve for kernel scratch are set aside first; every
+request then draws the bytes its right-hand sides need (the batch's per-slot memory,
+committed only while the slot is in use, plus the request's sources, solutions and its
+clover inverse) from what is left, whatever its volume. Memory freed by one volume's
+finished requests serves the next request of any volume. A request enters when its
+volume's batch has free slots and the budget holds its footprint; one that could never
+fit is rejected at once. A request that fails (a singular clover term, a non-finite
+residual) or misses the tolerance within the iteration cap comes back with its error
+set, and its slots and bytes are returned.
 """
 from __future__ import annotations
 
@@ -49,19 +56,59 @@ class Request:
 class VolumePlan:
     name: str
     field_bytes: int      # resident links + clover (all precisions in use)
-    per_rhs_bytes: int    # Krylov basis, preconditioned vectors, b, x, SAP state per slot
+    per_rhs_bytes: int    # one slot's solver state, plus the canonical b and x of one RHS
     kappa_bytes: int      # one clover inverse for a new kappa
-    capacity: int = 0
+    capacity: int = 0     # batch slots (address space only in an elastic batch)
+
+
+class HbmBudget:
+    """One pool of device memory shared by every served volume (thread-safe): `fixed`
+    bytes are set aside at start, requests take and give back the rest."""
+
+    def __init__(self, total_bytes: int, fixed_bytes: int = 0):
+        self.total = int(total_bytes)
+        self.fixed = int(fixed_bytes)
+        self.used = int(fixed_bytes)
+        self.peak = self.used
+        self.lock = threading.Lock()
+
+    def try_take(self, n: int) -> bool:
+        with self.lock:
+            if self.used + n <= self.total:
+                self.used += n
+                self.peak = max(self.peak, self.used)
+                return True
+            return False
+
+    def give_back(self, n: int) -> None:
+        with self.lock:
+            self.used -= n
+            assert self.used >= self.fixed
+
+    @property
+    def free(self) -> int:
+        return self.total - self.used
+
+
+def plan_budget(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: int = 16, reserve_bytes: int = 0):
+    """Set up the shared budget: the reserve (kernel scratch, graphs, allocator slack), the
+    fields and a cache of `kappa_cache` clover inverses per volume are set aside; each
+    volume's batch gets as many slots as the rest could fill with its requests alone (at
+    most max_slots). Returns the HbmBudget; raises if not even one slot fits."""
+    fixed = reserve_bytes + sum(p.field_bytes + kappa_cache * p.kappa_bytes for p in plans)
+    if fixed >= budget_bytes:
+        raise MemoryError(f"budget {budget_bytes} B cannot hold the resident fields ({fixed} B)")
+    for p in plans:
+        p.capacity = int(min(max_slots, (budget_bytes - fixed - p.kappa_bytes) // p.per_rhs_bytes))
+        if p.capacity < 1:
+            raise MemoryError(f"budget leaves no slot for volume {p.name}")
+    return HbmBudget(budget_bytes, fixed)
 
 
 def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: int = 16, reserve_bytes: int = 0):
-    """Split an HBM budget into batch capacities (slots) per volume.
-
-    `reserve_bytes` (kernel scratch, graphs, allocator slack), the fields and a cache of
-    `kappa_cache` clover inverses per volume are reserved first; the rest buys the same
-    number of slots in every volume (a slot of a large volume costs more bytes), at most
-    max_slots. Raises if not even one slot fits.
-    """
+    """Split an HBM budget into equal fixed slot counts per volume (for batches whose
+    memory is allocated at creation): the same reserve as plan_budget, then the same
+    number of slots in every volume, at most max_slots. Raises if not even one fits."""
     fixed = reserve_bytes + sum(p.field_bytes + kappa_cache * p.kappa_bytes for p in plans)
     if fixed >= budget_bytes:
         raise MemoryError(f"budget {budget_bytes} B cannot hold the resident fields ({fixed} B)")
@@ -74,27 +121,42 @@ def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: in
 
 
 class Admission:
-    """Slot bookkeeping of one volume (thread-safe)."""
+    """Admission of one volume (thread-safe): a request of n right-hand sides needs n free
+    slots of the volume's batch and, with a shared budget, n * slot_bytes +
+    request_bytes of it."""
 
-    def __init__(self, capacity: int):
+    def __init__(self, capacity: int, budget: HbmBudget | None = None, slot_bytes: int = 0,
+                 request_bytes: int = 0):
         self.capacity = capacity
         self.free = capacity
+        self.budget = budget
+        self.slot_bytes = int(slot_bytes)
+        self.request_bytes = int(request_bytes)
         self.lock = threading.Lock()
 
+    def cost(self, n: int) -> int:
+        return n * self.slot_bytes + self.request_bytes if self.budget is not None else 0
+
     def fits_ever(self, n: int) -> bool:
-        return n <= self.capacity
+        if n > self.capacity:
+            return False
+        return self.budget is None or self.cost(n) <= self.budget.total - self.budget.fixed
 
     def try_take(self, n: int) -> bool:
         with self.lock:
-            if n <= self.free:
-                self.free -= n
-                return True
-            return False
+            if n > self.free:
+                return False
+            if self.budget is not None and not self.budget.try_take(self.cost(n)):
+                return False
+            self.free -= n
+            return True
 
     def give_back(self, n: int) -> None:
         with self.lock:
             self.free += n
             assert self.free <= self.capacity
+        if self.budget is not None:
+            self.budget.give_back(self.cost(n))
 
 
 class VolumeWorker(threading.Thread):
@@ -175,9 +237,23 @@ class VolumeWorker(threading.Thread):
                     return
                 req = self.queue.popleft()
             req.t_admit = self.clock()
-            srcs = self.backend.make_source(req)
-            req.x = self.backend.make_output(req)
-            req.slots = [self.batch.add(req.kappa, b) for b in srcs]
+            req.slots = []
+            try:
+                srcs = self.backend.make_source(req)
+                req.x = self.backend.make_output(req)
+                for b in srcs:
+                    req.slots.append(self.batch.add(req.kappa, b))
+            except Exception as e:  # this request fails alone: its slots and bytes go back
+                for s, out in zip(req.slots, req.x or []):
+                    try:
+                        self.batch.take(s, out)
+                    except Exception:
+                        pass
+                self.adm.give_back(req.nrhs)
+                req.error = f"admission failed: {e}"
+                req.t_done = self.clock()
+                self.on_done(req)
+                continue
             self.active.append(req)
 
     def _harvest(self):
@@ -187,8 +263,19 @@ class VolumeWorker(threading.Thread):
             if not done:
                 still.append(req)
                 continue
-            req.stats = [self.batch.take(s, out) for s, out in zip(req.slots, req.x)]
+            stats, errs = [], []
+            for s, out in zip(req.slots, req.x):
+                try:
+                    stats.append(self.batch.take(s, out))
+                except Exception as e:  # e.g. a non-finite residual in this slot
+                    stats.append({"converged": 0, "error": str(e)})
+                    errs.append(str(e))
+            req.stats = stats
             self.adm.give_back(req.nrhs)
+            if errs:
+                req.error = "; ".join(errs)
+            elif not all(st.get("converged", 1) for st in stats):
+                req.error = "not converged within the iteration cap"
             req.t_done = self.clock()
             self.on_done(req)
         self.active = still
@@ -210,7 +297,8 @@ class VolumeWorker(threading.Thread):
                 self._harvest()
                 continue
             with self.cv:
-                if self.queue:
+                if self.queue:  # waiting for memory another volume holds: no busy spin
+                    self.cv.wait(timeout=0.002)
                     continue
                 if self.stop_when_idle:
                     return
@@ -270,9 +358,11 @@ def summarize(done, wall: float) -> dict:
 
 class TorchVolume:
     """GPU resources of one served volume: a stream, a context, the resident field, the
-    batch, and seeded Gaussian sources drawn on the device."""
+    batch, and seeded Gaussian sources drawn on the device. With elastic=True the batch
+    commits a slot's memory only while the slot is in use (its slots cost address space
+    otherwise), so volumes can share one HBM budget."""
 
-    def __init__(self, name, dims, block, eps, gauge_seed, csw, capacity, solver_kw, links=None):
+    def __init__(self, name, dims, block, eps, gauge_seed, csw, capacity, solver_kw, links=None, elastic=False):
         import torch
 
         import synthetic  # seeded input recipe shared with the tests
@@ -280,6 +370,7 @@ class TorchVolume:
         self.name = name
         self.dims = tuple(dims)
         self.solver_kw = dict(solver_kw)
+        self.elastic = elastic
         self.stream = torch.cuda.Stream()
         self.ctx = Context(0, stream=self.stream)
         u = links if links is not None else synthetic.gauge_field(dims, eps, gauge_seed)
@@ -292,20 +383,28 @@ class TorchVolume:
             self.start(capacity)
 
     def plan(self) -> VolumePlan:
-        """Memory plan of this volume: resident field, bytes per slot (the solver's state plus
-        this backend's canonical b and x of one right-hand side), per-kappa clover."""
+        """Memory plan of this volume: resident field (and, elastic, the batch's fixed part),
+        bytes per slot (the solver's state plus this backend's canonical b and x of one
+        right-hand side), per-kappa clover."""
         lx, ly, lz, lt = self.dims
         v = lx * ly * lz * lt
-        per_rhs = self.field.footprint(2, **self.solver_kw) - self.field.footprint(1, **self.solver_kw)
-        per_rhs += 2 * v * 12 * 16  # complex128 b and x
-        lo = self.field.footprint(1, **self.solver_kw) - per_rhs
-        prec_b = {"f64": 8, "f32": 4, "f16": 2}[self.solver_kw.get("prec", "f64")]
-        return VolumePlan(self.name, 2 * v * 72 * 8 + lo, per_rhs, v * 72 * prec_b + v * 4)
+        canon = 2 * v * 12 * 16  # complex128 b and x
+        one = self.field.footprint(1, **self.solver_kw)
+        per_rhs = self.field.footprint(2, **self.solver_kw) - one
+        lo = one - per_rhs
+        prec_b = {"f64": 8, "f32": 4, "f16": 2, "f16l": 2}[self.solver_kw.get("prec", "f64")]
+        kappa_bytes = v * 72 * prec_b + v * 4
+        field_bytes = 2 * v * 72 * 8 + lo
+        if self.elastic and self.batch is not None:
+            fixed, slot = self.batch.memory()
+            return VolumePlan(self.name, field_bytes + fixed, slot + canon, kappa_bytes)
+        return VolumePlan(self.name, field_bytes, per_rhs + canon, kappa_bytes)
 
     def start(self, capacity: int):
         from .sapdd import Batch
         with self.torch.cuda.stream(self.stream):
-            self.batch = Batch(self.field, capacity, **self.solver_kw)
+            extra = {"elastic": True} if self.elastic else {}
+            self.batch = Batch(self.field, capacity, **extra, **self.solver_kw)
 
     def thread_context(self):
         return self.torch.cuda.stream(self.stream)

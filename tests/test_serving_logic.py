@@ -129,3 +129,81 @@ def test_cancel_waiting_and_admitted_requests():
     w._loop()  # request 1 now runs to completion
     assert done[-1].id == 1 and done[-1].error is None
     assert not w.cancel(99)  # unknown ids are ignored
+
+
+def test_plan_budget_sets_aside_fields_and_sizes_slots():
+    plans = [sv.VolumePlan("a", 100, 10, 1), sv.VolumePlan("b", 300, 40, 2)]
+    b = sv.plan_budget(plans, 1000, max_slots=24, kappa_cache=16, reserve_bytes=50)
+    assert b.fixed == 50 + 100 + 16 + 300 + 32 and b.used == b.fixed
+    # each volume could fill the rest alone: (1000 - 498 - kappa) // per_rhs, capped
+    assert [p.capacity for p in plans] == [24, (1000 - 498 - 2) // 40]
+    with pytest.raises(MemoryError):
+        sv.plan_budget(plans, 450)
+
+
+def test_shared_budget_moves_memory_between_volumes():
+    """Two volumes draw from one budget: while volume 0 holds most of it volume 1's request
+    waits, and it enters as soon as volume 0 gives its bytes back."""
+    budget = sv.HbmBudget(100, fixed_bytes=10)
+    a0 = sv.Admission(8, budget, slot_bytes=10, request_bytes=5)
+    a1 = sv.Admission(8, budget, slot_bytes=20, request_bytes=5)
+    assert a0.fits_ever(8) and not a1.fits_ever(5)  # 5 * 20 + 5 > 90 free at best
+    assert a0.try_take(7)                # 75 bytes: used 85
+    assert not a1.try_take(1)            # needs 25
+    assert a0.free == 1 and a1.free == 8  # a refused request holds nothing
+    a0.give_back(7)                      # 75 back: used 10
+    assert a1.try_take(3) and budget.used == 75
+    assert not a0.try_take(3)            # 35 more would exceed the budget
+    assert a0.try_take(1) and budget.used == 90 and budget.peak == 90
+    a0.give_back(1)
+    a1.give_back(3)
+    assert budget.used == budget.fixed
+
+
+class FailingBatch(FakeBatch):
+    """kappa 0.5 makes add raise (a singular clover term); source value 7 makes take raise
+    (a non-finite residual); source value 5 finishes unconverged."""
+
+    def add(self, kappa, b):
+        if kappa == 0.5:
+            raise RuntimeError("singular")
+        return super().add(kappa, b)
+
+    def take(self, s, out):
+        n, b = self.slots[s]
+        if b % 10 == 7:
+            self.slots.pop(s)
+            raise RuntimeError("non-finite residual")
+        st = super().take(s, out)
+        st["converged"] = 0 if b % 10 == 5 else 1
+        return st
+
+
+class FailingBackend(FakeBackend):
+    def make_source(self, req):
+        return [req.seed * 10 + i for i in range(req.nrhs)]
+
+
+def test_failed_and_unconverged_requests_report_errors_and_return_their_slots():
+    """A request whose slot raises on take, one that finishes unconverged, and one whose
+    kappa is rejected on admission each come back with an error; the worker keeps serving
+    the others, and every slot is free at the end."""
+    batch = FailingBatch(4)
+    adm = sv.Admission(4)
+    w = sv.VolumeWorker("v", batch, FailingBackend(), adm, None, None)
+    reqs = [sv.Request(0, 0.0, 0, 0.12, 1, seed=0),       # sources 0: fine
+            sv.Request(1, 0.0, 0, 0.12, 2, seed=1),       # sources 10, 11: fine
+            sv.Request(2, 0.0, 0, 0.5, 2, seed=2),        # kappa rejected on the first add
+            sv.Request(3, 0.0, 0, 0.12, 3, seed=0),       # sources 0, 1, 2 ... fine
+            sv.Request(4, 0.0, 0, 0.12, 1, seed=0.5),     # source 5: not converged
+            sv.Request(5, 0.0, 0, 0.12, 1, seed=0.7)]     # source 7: take raises
+    done = sv.Server([w]).run(reqs, realtime=False)
+    err = {r.id: r.error for r in done}
+    assert len(done) == 6
+    assert err[0] is None and err[1] is None and err[3] is None
+    assert "admission failed" in err[2]
+    assert err[4] == "not converged within the iteration cap"
+    assert "non-finite" in err[5]
+    assert adm.free == 4 and not batch.slots
+    s = sv.summarize(done, wall=1.0)
+    assert s["requests"] == 3 and s["rejected"] == 3
