@@ -257,29 +257,32 @@ def cpu_baseline(cfg, iters, restarts, nmr, ncy, nrhs):
                        f"({t_solve:.0f} s per solve; the GPU solves {nrhs} together)")
 
 
-def serving_measure(n_requests, fracs, budget_gb, warm=6):
+def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
     """Serving stream: Poisson arrivals of 1-12 RHS solve requests on resident fields of
     16^3x32, 24^3x48 and 32^3x64 (4^4 domains, FP16 SAP, FP64 FGMRES(16)), kappa uniform
-    in [0.120, 0.126]; admission by HBM budget, continuous batching per volume. A closed
-    loop (every request at t = 0) measures the saturation rate; then n_requests arrive at
-    each fraction of it. Returns the saturation run and one run per fraction."""
+    in [0.120, 0.126], continuous batching per volume. Admission by HBM footprint from one
+    shared budget: every volume's batch is elastic (a slot's memory is committed only while
+    it is in use) and every request draws its bytes from the budget, whatever its volume.
+    A closed loop (every request at t = 0) measures the saturation rate; then n_requests
+    arrive at each fraction of it. Returns the saturation run and one run per fraction."""
     import torch
 
     import synthetic
     from paper_1502_04025_amd import serving as sv
     kw = dict(prec="f16", nmr=4, ncy=NCY, restart=16, tol=1e-10)
-    vols = [sv.TorchVolume(f"{'x'.join(map(str, d))}", d, (4, 4, 4, 4), 0.3, 14 + i, 1.0, 0, kw)
+    vols = [sv.TorchVolume(f"{'x'.join(map(str, d))}", d, (4, 4, 4, 4), 0.3, 14 + i, 1.0, max_slots, kw,
+                           elastic=True)
             for i, d in enumerate(synthetic.SERVING_VOLUMES)]
+    plans = [v.plan() for v in vols]
     # 16 GB of the budget stay free for kernel scratch, graphs and the caching allocator
-    plans = sv.plan_capacity([v.plan() for v in vols], int(budget_gb * 1e9), max_slots=16,
-                             reserve_bytes=16 * 10 ** 9)
-    for v, p in zip(vols, plans):
-        v.start(p.capacity)
+    budget = sv.plan_budget(plans, int(budget_gb * 1e9), max_slots=max_slots, reserve_bytes=16 * 10 ** 9)
 
     def serve(reqs, realtime):
-        workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity), None, None)
+        workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity, budget, p.per_rhs_bytes,
+                                                                    p.kappa_bytes), None, None)
                    for v, p in zip(vols, plans)]
         srv = sv.Server(workers)
+        budget.peak = budget.used
         t0 = time.perf_counter()
         done = srv.run(reqs, realtime=realtime)
         torch.cuda.synchronize()
@@ -289,6 +292,7 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6):
             r.x = None
         torch.cuda.empty_cache()
         out["steps"] = [w.steps for w in workers]
+        out["budget_peak_gb"] = round(budget.peak / 1e9, 2)
         out["converged"] = all(all(st["converged"] for st in r.stats) for r in done if r.error is None)
         return out
 
@@ -305,7 +309,10 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6):
         runs[str(frac)] = dict(rate_req_s=round(rate, 4), **serve(stream_of(n_requests, rate, 32), True))
     for v in vols:
         v.close()
-    return dict(slots_per_volume=plans[0].capacity, hbm_budget_gb=budget_gb, warmup_requests=warm,
+    return dict(admission="one shared HBM budget, footprint per request (elastic batches)",
+                hbm_budget_gb=budget_gb, fixed_gb=round(budget.fixed / 1e9, 2),
+                slots_per_volume=[p.capacity for p in plans],
+                slot_gb=[round(p.per_rhs_bytes / 1e9, 3) for p in plans], warmup_requests=warm,
                 requests_per_phase=n_requests, saturation=sat, poisson=runs)
 
 
@@ -573,6 +580,8 @@ def main():
     ap.add_argument("--sweep-ncy", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8, 12, 16])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sub-benchmarks")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="with --no-extras: still run the 2 GiB copy kernel (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
@@ -681,6 +690,8 @@ def main():
         extra("mixed_vs_fp64_32x32x32x64", lambda: sub_mixed_vs_fp64(ctx))
         extra("serving", lambda: serving_measure(40, (0.8,), 200.0, warm=6))
         extra("mg_near_critical", lambda: mg_extra(ctx))
+    if args.no_extras and args.copy_probe:
+        line["copy_GB_s"] = copy_bandwidth(ctx)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(cfg, int(np.mean(iters)), int(np.mean([s_["restarts"] for s_ in stats])),

@@ -71,8 +71,11 @@ enum {
     SAPDD_DEVICE_PTRS = 1, /* array arguments are device pointers              */
     SAPDD_USE_X0 = 2,      /* sapdd_solve starts from the x passed in, not 0    */
     SAPDD_NO_GRAPH = 4,    /* sapdd_solve launches the SAP sweep without a graph */
-    SAPDD_LINKS12 = 8      /* sapdd_apply_block_D: links stored as their first two
+    SAPDD_LINKS12 = 8,     /* sapdd_apply_block_D: links stored as their first two
                             * rows, the third rebuilt in the kernel (FP32/FP16)  */
+    SAPDD_ELASTIC = 16     /* sapdd_batch_create: a slot's device memory is committed
+                            * while the slot is in use and released when it is taken;
+                            * free slots cost address space only                 */
 };
 
 /* Solver parameters (Sec. 3.1 names the pieces; Sec. 3.7 uses 4-5 MR iterations and
@@ -218,8 +221,16 @@ int sapdd_solve(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa,
 int sapdd_batch_create(sapdd_ctx *ctx, const sapdd_field *field, const sapdd_params *params, int capacity,
                        sapdd_batch **out);
 int sapdd_batch_destroy(sapdd_batch *batch);
+/* Device memory the batch holds now (bytes): its fixed workspaces, plus, with
+ * SAPDD_ELASTIC, the memory committed for the slots in use. *slot_bytes (if not NULL)
+ * receives the most one more admitted slot can commit (0 for a batch allocated whole at
+ * creation). Admission by footprint across batches (the serving loop) reads these; the
+ * clover inverse of a new kappa (sapdd_solve_footprint counts it) comes on top. -1 for
+ * a NULL batch. */
+long long sapdd_batch_memory(const sapdd_batch *batch, long long *slot_bytes);
 /* Admit one right-hand side b (canonical spinor; x0 = start vector or NULL for zero;
- * flags: SAPDD_DEVICE_PTRS). Returns SAPDD_EFULL if every slot is taken. */
+ * flags: SAPDD_DEVICE_PTRS). Returns SAPDD_EFULL if every slot is taken, SAPDD_ENOMEM
+ * if an elastic batch cannot commit the slot's memory (nothing stays committed). */
 int sapdd_batch_add(sapdd_batch *batch, double kappa, const double *b, const double *x0, int flags, int *slot);
 /* One restart cycle for every unfinished slot; *running = slots still unfinished. */
 int sapdd_batch_step(sapdd_batch *batch, int *running);

@@ -5,5 +5,5 @@ module `sapdd` only marshals arguments into it.
 """
 from .sapdd import (  # noqa: F401
     Batch, Context, Field, MgParams, Multigrid, Params, SapddError, Stats, load_library,
-    F16, F16_LINKS, F32, F64, OK, EINVAL, EFULL, ENOCONV, ESINGULAR, ENAN, DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12,
+    F16, F16_LINKS, F32, F64, OK, EINVAL, EFULL, ENOCONV, ESINGULAR, ENAN, DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12, ELASTIC,
 )

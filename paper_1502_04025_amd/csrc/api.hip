@@ -24,7 +24,6 @@
 
 #include "../../include/sapdd.h"
 #include "dense.hpp"
-#include "elastic.hpp"
 #include "kernels.hpp"
 
 using namespace sapdd;
@@ -1086,14 +1085,14 @@ struct sapdd_batch {
     double t_sap = 0, t_d = 0, t_gs = 0, t_host = 0;
     sapdd_mg *mg = nullptr;  // multigrid preconditioner in place of SAP (sapdd_batch_set_mg)
     MgWork mw{};
-    // Elastic batches (SAPDD_ELASTIC): the per-slot fields are address ranges whose
-    // physical memory is committed while a slot is in use (elastic.hpp).
+    // Elastic batches (SAPDD_ELASTIC): every per-slot field is one address range of
+    // cap slot ranges, each reserved on its own (the runtime takes a second mapping inside
+    // one reservation badly) and backed by physical memory only while the slot is in use.
     struct EField {
-        char *va = nullptr;
-        size_t reserved = 0, data_per_slot = 0, scale_off = 0, scale_per_slot = 0;
-        ElasticPlan plan;
-        // committed runs by first granule: the handle of their memory and their length
-        std::map<size_t, std::pair<hipMemGenericAllocationHandle_t, size_t>> handles;
+        size_t data_per_slot = 0, scale_per_slot = 0;  // bytes; the scales follow all data
+        std::vector<void *> dres, sres;                 // per-slot reservations
+        std::vector<hipMemGenericAllocationHandle_t> dh, sh;
+        std::vector<char> committed;
     };
     bool elastic = false;
     size_t gran = 0, fixed_bytes = 0;
@@ -1138,91 +1137,106 @@ int bfield(sapdd_batch *B, int nf, int prec, int ncomp, Fld *f) {
         *f = Fld{q, prec == P16 ? (float *)((char *)q + sc_off) : nullptr, prec};
         return SAPDD_OK;
     }
+    const int per = nf / B->cap;
     sapdd_batch::EField e;
-    e.reserved = (bytes + B->gran - 1) / B->gran * B->gran;
-    void *va = nullptr;
-    hipError_t err = hipMemAddressReserve(&va, e.reserved, B->gran, nullptr, 0);
+    e.data_per_slot = (size_t)B->g.V * ncomp * per * prec_bytes(prec);
+    e.scale_per_slot = prec == P16 ? (size_t)B->g.V * per * sizeof(float) : 0;
+    if (e.data_per_slot % B->gran || e.scale_per_slot % B->gran)
+        return fail(B->c, SAPDD_EINVAL,
+                    "an elastic batch needs per-slot fields in whole pages of %zu bytes (lattice volume a "
+                    "multiple of %zu sites)", B->gran, B->gran / 4);
+    const size_t total = (size_t)B->cap * (e.data_per_slot + e.scale_per_slot);
+    // find a free range for the whole field, then hold it as cap (or 2 cap) adjacent
+    // per-slot reservations
+    void *big = nullptr;
+    hipError_t err = hipMemAddressReserve(&big, total, B->gran, nullptr, 0);
+    if (err == hipSuccess) err = hipMemAddressFree(big, total);
+    for (int r = 0; err == hipSuccess && r < 2 * B->cap; ++r) {
+        const bool scl = r >= B->cap;
+        if (scl && !e.scale_per_slot) break;
+        const size_t len = scl ? e.scale_per_slot : e.data_per_slot;
+        char *want = (char *)big + (scl ? B->cap * e.data_per_slot + (r - B->cap) * len : r * len);
+        void *got = nullptr;
+        err = hipMemAddressReserve(&got, len, B->gran, want, 0);
+        if (err == hipSuccess) (scl ? e.sres : e.dres).push_back(got);
+        if (err == hipSuccess && got != want) err = hipErrorOutOfMemory;  // the hole was taken meanwhile
+    }
     if (err != hipSuccess) {
         (void)hipGetLastError();
-        return fail(B->c, SAPDD_ENOMEM, "reserving %zu bytes of address space failed: %s", e.reserved,
+        for (void *q : e.dres) (void)hipMemAddressFree(q, e.data_per_slot);
+        for (void *q : e.sres) (void)hipMemAddressFree(q, e.scale_per_slot);
+        return fail(B->c, SAPDD_ENOMEM, "reserving %zu bytes of adjacent address space failed: %s", total,
                     hipGetErrorString(err));
     }
-    e.va = (char *)va;
-    const int per = nf / B->cap;
-    e.data_per_slot = (size_t)B->g.V * ncomp * per * prec_bytes(prec);
-    e.scale_off = sc_off;
-    e.scale_per_slot = prec == P16 ? (size_t)B->g.V * per * sizeof(float) : 0;
-    e.plan = ElasticPlan(B->gran, e.reserved);
+    e.dh.resize(B->cap);
+    e.sh.resize(B->cap);
+    e.committed.assign(B->cap, 0);
     B->efields.push_back(std::move(e));
-    *f = Fld{va, prec == P16 ? (float *)((char *)va + sc_off) : nullptr, prec};
+    *f = Fld{big, prec == P16 ? (float *)((char *)big + B->cap * B->efields.back().data_per_slot) : nullptr, prec};
     return SAPDD_OK;
 }
 
-// Release the physical memory of the given runs of an elastic field (those it holds).
-void eunmap(sapdd_batch::EField &e, size_t gran, const std::vector<GranRun> &runs) {
-    for (const GranRun &r : runs) {
-        auto it = e.handles.find(r.g);
-        if (it == e.handles.end()) continue;
-        (void)hipMemUnmap(e.va + r.g * gran, r.n * gran);
-        (void)hipMemRelease(it->second.first);
-        e.handles.erase(it);
+// Back one slot reservation with physical memory readable and writable by the device.
+hipError_t vmm_commit(void *va, size_t len, int device, hipMemGenericAllocationHandle_t *h, const char **what) {
+    const hipMemAllocationProp prop = vmm_prop(device);
+    hipMemAccessDesc acc{};
+    acc.location = prop.location;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    *what = "hipMemCreate";
+    hipError_t e = hipMemCreate(h, len, &prop, 0);
+    if (e != hipSuccess) return e;
+    *what = "hipMemMap";
+    e = hipMemMap(va, len, 0, *h, 0);
+    if (e == hipSuccess) {
+        *what = "hipMemSetAccess";
+        e = hipMemSetAccess(va, len, &acc, 1);
+        if (e != hipSuccess) (void)hipMemUnmap(va, len);
     }
+    if (e != hipSuccess) (void)hipMemRelease(*h);
+    return e;
 }
 
-// The byte ranges of slot r in an elastic field (data, then FP16 scales).
-template <class F> void slot_ranges(const sapdd_batch::EField &e, int r, F &&fn) {
-    fn(r * e.data_per_slot, e.data_per_slot);
-    if (e.scale_per_slot) fn(e.scale_off + r * e.scale_per_slot, e.scale_per_slot);
+void vmm_release(sapdd_batch::EField &e, int r) {
+    if (!e.committed[r]) return;
+    (void)hipMemUnmap(e.dres[r], e.data_per_slot);
+    (void)hipMemRelease(e.dh[r]);
+    if (e.scale_per_slot) {
+        (void)hipMemUnmap(e.sres[r], e.scale_per_slot);
+        (void)hipMemRelease(e.sh[r]);
+    }
+    e.committed[r] = 0;
 }
 
 // Commit slot r's memory in every elastic field; on failure nothing stays committed.
 int commit_slot(sapdd_batch *B, int r) {
     if (!B->elastic) return SAPDD_OK;
-    const hipMemAllocationProp prop = vmm_prop(B->c->device);
-    hipMemAccessDesc acc{};
-    acc.location = prop.location;
-    acc.flags = hipMemAccessFlagsProtReadWrite;
-    size_t done = 0;
+    const char *what = "";
     hipError_t err = hipSuccess;
-    for (; done < B->efields.size() && err == hipSuccess; ++done) {
-        sapdd_batch::EField &e = B->efields[done];
-        std::vector<GranRun> runs;
-        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.acquire(off, len, runs); });
-        for (const GranRun &q : runs) {
-            hipMemGenericAllocationHandle_t h;
-            err = hipMemCreate(&h, q.n * B->gran, &prop, 0);
-            if (err != hipSuccess) break;
-            char *at = e.va + q.g * B->gran;
-            err = hipMemMap(at, q.n * B->gran, 0, h, 0);
-            if (err == hipSuccess) err = hipMemSetAccess(at, q.n * B->gran, &acc, 1);
+    size_t i = 0;
+    for (; i < B->efields.size(); ++i) {
+        sapdd_batch::EField &e = B->efields[i];
+        err = vmm_commit(e.dres[r], e.data_per_slot, B->c->device, &e.dh[r], &what);
+        if (err == hipSuccess && e.scale_per_slot) {
+            err = vmm_commit(e.sres[r], e.scale_per_slot, B->c->device, &e.sh[r], &what);
             if (err != hipSuccess) {
-                (void)hipMemUnmap(at, q.n * B->gran);
-                (void)hipMemRelease(h);
-                break;
+                (void)hipMemUnmap(e.dres[r], e.data_per_slot);
+                (void)hipMemRelease(e.dh[r]);
             }
-            e.handles[q.g] = {h, q.n};
         }
+        if (err != hipSuccess) break;
+        e.committed[r] = 1;
     }
     if (err == hipSuccess) return SAPDD_OK;
     (void)hipGetLastError();
-    for (size_t i = 0; i < done; ++i) {  // roll back every field this call touched
-        sapdd_batch::EField &e = B->efields[i];
-        std::vector<GranRun> runs;
-        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.release(off, len, runs); });
-        eunmap(e, B->gran, runs);
-    }
+    for (size_t k = 0; k < i; ++k) vmm_release(B->efields[k], r);
     return fail(B->c, err == hipErrorOutOfMemory ? SAPDD_ENOMEM : SAPDD_EDEVICE,
-                "committing the memory of slot %d failed: %s", r, hipGetErrorString(err));
+                "committing the memory of slot %d failed: %s (%s)", r, hipGetErrorString(err), what);
 }
 
 // Release slot r's memory in every elastic field (the stream must be done with it).
 void release_slot(sapdd_batch *B, int r) {
     if (!B->elastic) return;
-    for (auto &e : B->efields) {
-        std::vector<GranRun> runs;
-        slot_ranges(e, r, [&](size_t off, size_t len) { e.plan.release(off, len, runs); });
-        eunmap(e, B->gran, runs);
-    }
+    for (auto &e : B->efields) vmm_release(e, r);
 }
 
 int upload(sapdd_batch *B, int seg, const std::vector<int> &v, int **out) {
@@ -1701,11 +1715,9 @@ void batch_free(sapdd_batch *B) {
         if (s.used) sap_clover_release(B->f, s.kappa, lprec(B->prec));
     for (void *q : B->allocs) (void)hipFree(q);
     for (auto &e : B->efields) {
-        for (auto &kv : e.handles) {
-            (void)hipMemUnmap(e.va + kv.first * B->gran, kv.second.second * B->gran);
-            (void)hipMemRelease(kv.second.first);
-        }
-        if (e.va) (void)hipMemAddressFree(e.va, e.reserved);
+        for (int r = 0; r < (int)e.committed.size(); ++r) vmm_release(e, r);
+        for (void *q : e.dres) (void)hipMemAddressFree(q, e.data_per_slot);
+        for (void *q : e.sres) (void)hipMemAddressFree(q, e.scale_per_slot);
     }
     if (B->pin) (void)hipHostFree(B->pin);
     delete B;
@@ -1724,6 +1736,7 @@ int batch_release_slots(sapdd_batch *B) {
     for (int r = 0; r < B->cap; ++r)
         if (B->slots[r].used) {
             sap_clover_release(B->f, B->slots[r].kappa, lprec(B->prec));
+            release_slot(B, r);
             B->slots[r].used = false;
         }
     return SAPDD_OK;
@@ -1769,6 +1782,18 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     B->CST = 4 * (B->m + 1) + 2;
     B->nwg_d = dslash_full_partials(B->g);
     B->use_graph = !(p->flags & SAPDD_NO_GRAPH) && c->stream != nullptr;
+    B->elastic = (p->flags & SAPDD_ELASTIC) != 0;
+    if (B->elastic) {
+        const hipMemAllocationProp prop = vmm_prop(c->device);
+        size_t g = 0;
+        const hipError_t e = hipMemGetAllocationGranularity(&g, &prop, hipMemAllocationGranularityRecommended);
+        if (e != hipSuccess || g == 0) {
+            (void)hipGetLastError();
+            delete B;
+            return fail(c, SAPDD_EDEVICE, "elastic batches need virtual memory management: %s", hipGetErrorString(e));
+        }
+        B->gran = g;
+    }
     B->slots.resize(cap);
     for (auto &s : B->slots) {
         s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
@@ -1833,6 +1858,18 @@ int sapdd_batch_destroy(sapdd_batch *B) {
     return SAPDD_OK;
 }
 
+long long sapdd_batch_memory(const sapdd_batch *B, long long *slot_bytes) {
+    if (!B) return -1;
+    long long held = (long long)B->fixed_bytes, slot = 0;
+    for (const auto &e : B->efields) {
+        const long long per = (long long)(e.data_per_slot + e.scale_per_slot);
+        for (char c : e.committed) held += c ? per : 0;
+        slot += per;
+    }
+    if (slot_bytes) *slot_bytes = slot;
+    return held;
+}
+
 int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double *x0, int flags, int *slot_out) {
     if (!B || !b || !slot_out) return SAPDD_EINVAL;
     sapdd_ctx *c = B->c;
@@ -1850,6 +1887,10 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     if (r < 0) return fail(c, SAPDD_EFULL, "no free slot in the batch (capacity %d)", B->cap);
     Fld xf;
     CHK(sap_clover(c, B->f, kappa, lprec(B->prec), &xf, true));
+    if (int rc = commit_slot(B, r); rc != SAPDD_OK) {
+        sap_clover_release(B->f, kappa, lprec(B->prec));
+        return rc;
+    }
     Slot &s = B->slots[r];
     s = Slot();
     s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
@@ -1982,6 +2023,7 @@ int sapdd_batch_take(sapdd_batch *B, int slot, double *x, int flags, sapdd_stats
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int status = s.status;
     sap_clover_release(B->f, s.kappa, lprec(B->prec));
+    release_slot(B, slot);
     s = Slot();
     s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
     s.cs.assign(B->m, 0.0);
@@ -2313,6 +2355,7 @@ int sapdd_batch_set_mg(sapdd_batch *B, sapdd_mg *mg) {
     sapdd_ctx *c = B->c;
     c->err.clear();
     if (mg->f != B->f || mg->c != c) return fail(c, SAPDD_EINVAL, "the multigrid belongs to another field or context");
+    if (B->elastic) return fail(c, SAPDD_EINVAL, "an elastic batch cannot precondition with the multigrid");
     for (const auto &s : B->slots)
         if (s.used) return fail(c, SAPDD_EINVAL, "the batch has slots in use");
     HIPCHK(c, hipSetDevice(c->device));

@@ -19,11 +19,12 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsapdd.so")
+# SAPDD_LIB points the binding at another build of the library (for comparing builds)
+LIB_PATH = os.environ.get("SAPDD_LIB") or os.path.join(HERE, "libsapdd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, ENAN, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16, F16_LINKS = 0, 1, 2, 3
-DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12 = 1, 2, 4, 8
+DEVICE_PTRS, USE_X0, NO_GRAPH, LINKS12, ELASTIC = 1, 2, 4, 8, 16
 # "f16l": FP16 links and clover with FP32 Schwarz spinors (Schwarz precision only)
 PRECS = {"f64": F64, "f32": F32, "f16": F16, "f16l": F16_LINKS}
 
@@ -33,7 +34,7 @@ EXPORTS = (
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
     "sapdd_apply_block_D", "sapdd_sap", "sapdd_sap_noalloc", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
     "sapdd_profile", "sapdd_batch_create", "sapdd_batch_destroy", "sapdd_batch_add",
-    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
+    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_memory", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
     "sapdd_mg_prolongator", "sapdd_mg_coarse_operator", "sapdd_mg_coarse_solve", "sapdd_mg_precond",
     "sapdd_mg_solve", "sapdd_batch_set_mg",
 )
@@ -114,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_batch_add.argtypes = [VP, D, VP, VP, I, P(I)]
     lib.sapdd_batch_step.argtypes = [VP, P(I)]
     lib.sapdd_batch_poll.argtypes = [VP, I, P(Stats)]
+    lib.sapdd_batch_memory.argtypes = [VP, P(C.c_longlong)]
+    lib.sapdd_batch_memory.restype = C.c_longlong
     lib.sapdd_batch_take.argtypes = [VP, I, VP, I, P(Stats)]
     lib.sapdd_mg_setup.argtypes = [VP, VP, D, P(Params), P(MgParams), VP, I, P(VP)]
     lib.sapdd_mg_destroy.argtypes = [VP]
@@ -124,7 +127,7 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_mg_solve.argtypes = [VP, P(Params), I, VP, VP, P(Stats)]
     lib.sapdd_batch_set_mg.argtypes = [VP, VP]
     for name in EXPORTS:
-        if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint"):
+        if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint", "sapdd_batch_memory"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -342,10 +345,13 @@ class Batch:
     every step() runs one FGMRES restart cycle for all unfinished slots, finished slots
     leave with take()."""
 
-    def __init__(self, field: "Field", capacity: int, **kw):
+    def __init__(self, field: "Field", capacity: int, elastic: bool = False, **kw):
+        """elastic: commit a slot's device memory only while it is in use."""
         self.field = field
         self.ctx = field.ctx
         prm = field.params(**kw)
+        if elastic:
+            prm.flags |= ELASTIC
         self.prm = prm
         h = C.c_void_p()
         self.ctx._check(self.ctx.lib.sapdd_batch_create(self.ctx.h, field.h, C.byref(prm), int(capacity),
@@ -377,6 +383,12 @@ class Batch:
         self.ctx._check(self.ctx.lib.sapdd_batch_add(self.h, float(kappa), pb, px, DEVICE_PTRS if dev else 0,
                                                      C.byref(slot)))
         return slot.value
+
+    def memory(self):
+        """(bytes the batch holds now, most bytes one more slot can commit)."""
+        slot = C.c_longlong()
+        held = self.ctx.lib.sapdd_batch_memory(self.h, C.byref(slot))
+        return int(held), int(slot.value)
 
     def step(self) -> int:
         """One restart cycle for every unfinished slot; returns how many are unfinished."""

@@ -143,3 +143,78 @@ def test_cancel_and_resume_from_the_taken_iterate(env):
         batch.close()
     assert st2["converged"]
     assert oracle_relres(env["u"], env["t"], 0.124, x2, b) <= 1e-10
+
+
+def test_elastic_batch_commits_memory_per_slot(env):
+    """An elastic batch holds only its fixed workspaces until slots are admitted, commits
+    at most slot_bytes per admitted right-hand side, gives it back when the slot is taken,
+    and computes the same bits as a batch allocated whole."""
+    from paper_1502_04025_amd import Batch
+    torch, f = env["torch"], env["f"]
+    b = synthetic.gaussian_source(env["dims"], 3, 35)
+    kap = [0.121, 0.125, 0.123]
+    with torch.cuda.stream(env["stream"]):
+        whole = [f.solve(kap[r], b[r:r + 1].copy(), prec="f16").x[0] for r in range(3)]
+        batch = Batch(f, 8, elastic=True, prec="f16")
+        held0, slot = batch.memory()
+        assert slot > 0
+        s0 = batch.add(kap[0], b[0])
+        held1, _ = batch.memory()
+        assert held0 < held1 <= held0 + slot
+        s1 = batch.add(kap[1], b[1])
+        held2, _ = batch.memory()
+        assert held1 < held2 <= held0 + 2 * slot
+        xs, pending = {}, {0: s0, 1: s1}
+        while pending:
+            batch.step()
+            for r, s in list(pending.items()):
+                if batch.poll(s)[0]:
+                    out = np.empty_like(b[r])
+                    assert batch.take(s, out)["converged"]
+                    xs[r] = out
+                    del pending[r]
+                    if r == 0:  # the freed slot's memory serves the third right-hand side
+                        pending[2] = batch.add(kap[2], b[2])
+        assert batch.memory()[0] == held0  # every slot taken: only the fixed part is left
+        batch.close()
+    for r in range(3):
+        assert np.array_equal(xs[r], whole[r])
+        assert oracle_relres(env["u"], env["t"], kap[r], xs[r], b[r]) <= 1e-10
+
+
+def test_serving_with_one_shared_budget(env):
+    """Two volumes with elastic batches draw from one HBM budget too small for both to
+    fill their slots at once: every request still completes, bit-identical to its solve
+    alone and at 1e-10 by the oracle's operator, and the budget is never exceeded."""
+    from paper_1502_04025_amd import serving as sv
+    torch = env["torch"]
+    kw = dict(prec="f16")
+    vols = [sv.TorchVolume("v0", (8, 8, 8, 8), (4, 4, 4, 4), 0.3, 5, 1.0, 8, kw, elastic=True),
+            sv.TorchVolume("v1", (8, 8, 8, 16), (4, 4, 4, 4), 0.3, 6, 1.0, 8, kw, elastic=True)]
+    plans = [v.plan() for v in vols]
+    fixed = sum(p.field_bytes + 4 * p.kappa_bytes for p in plans)
+    total = fixed + 6 * max(p.per_rhs_bytes for p in plans) + 2 * max(p.kappa_bytes for p in plans)
+    budget = sv.plan_budget(plans, total, max_slots=8, kappa_cache=4)
+    reqs = synthetic.serving_requests(12, rate=1e9, seed=36, volumes=[v.dims for v in vols], max_rhs=4)
+    reqs = [sv.Request(r["id"], 0.0, r["vol"], r["kappa"], r["nrhs"], r["seed"]) for r in reqs]
+    workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity, budget, p.per_rhs_bytes, p.kappa_bytes),
+                               None, None) for v, p in zip(vols, plans)]
+    done = sv.Server(workers).run(reqs, realtime=False)
+    assert len(done) == 12 and all(r.error is None for r in done)
+    assert budget.peak <= budget.total and budget.used == budget.fixed
+    fields = {0: ((8, 8, 8, 8), 5), 1: ((8, 8, 8, 16), 6)}
+    ops = {k: (lambda u: (u, wilson.clover_term(u, 1.0)))(synthetic.gauge_field(d, 0.3, s))
+           for k, (d, s) in fields.items()}
+    for r in done:
+        v = vols[r.vol]
+        with torch.cuda.stream(v.stream):
+            bs = v.make_source(r)
+            for i in range(r.nrhs):
+                alone = v.field.solve(r.kappa, bs[i].unsqueeze(0).contiguous(), prec="f16").x
+                torch.cuda.synchronize()
+                assert torch.equal(alone[0], r.x[i])
+        u, t = ops[r.vol]
+        for i in range(r.nrhs):
+            assert oracle_relres(u, t, r.kappa, r.x[i].cpu().numpy(), bs[i].cpu().numpy()) <= 1e-10
+    for v in vols:
+        v.close()
