@@ -97,16 +97,13 @@ template <class S, class R> struct SiteLinks<S, R, true> {
 };
 
 template <class S, class R> struct SiteLinks<S, R, false> {
-    typedef S S_t;
     const S *base;
-    const float *scl;
     R sc;
     int64_t bp;
     int s, Vbh;
-    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ scl_, int64_t bp_, int s_,
+    __device__ __forceinline__ void init(const S *__restrict__ b, const float *__restrict__ scl, int64_t bp_, int s_,
                                          int vbh) {
         base = b;
-        scl = scl_;
         bp = bp_;
         s = s_;
         Vbh = vbh;
