@@ -158,8 +158,8 @@ __device__ __forceinline__ void clover_mul(const XR &X, const R (&in)[24], R (&o
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             const R d = X.at(36 * blk + i);
-            t[2 * i] = d * in[o + 2 * i];
-            t[2 * i + 1] = d * in[o + 2 * i + 1];
+            t[2 * i] = fmac(d, in[o + 2 * i], (R)0);
+            t[2 * i + 1] = fmac(d, in[o + 2 * i + 1], (R)0);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i)
@@ -224,10 +224,19 @@ template <class S, class R> struct SiteClover<S, R, false> {
 // U_mu(x)^+ (1 + gamma_mu) in(x); the receiving threads then need only their own links.
 // Every thread of the workgroup must call this; it contains one barrier (two with a
 // single LDS buffer).
-template <int MU, class BK, class R, class LK>
+//
+// BF (branch-free): every lane does the work of every direction. The face conditions
+// differ between the lanes of a wave, so a branch issues the work for the whole wave
+// anyway; without it the compiler schedules the four directions as one stream. Lanes
+// without the in-block forward neighbour write a slot nobody reads, and receivers without
+// the neighbour accumulate it with weight zero; every slot a receiver reads has been
+// written, so the zero weights only ever meet finite values. This loads the links of the
+// face sites too, which the operator does not need: the instruction-bound SAP kernels
+// use it, the memory-bound block operator does not.
+template <int MU, class BK, bool BF, class R, class LK>
 __device__ __forceinline__ void push_dir(const SiteInfo &si, const LK &U, const R (&in)[24], R *__restrict__ hb) {
     constexpr int Vbh = BK::Vbh;
-    if (si.fin & (1u << MU)) {
+    if (BF || (si.fin & (1u << MU))) {
         R h[12], uh[12], u[18];
         project<MU, +1>(in, h);
         U.template get<MU>(u);
@@ -238,11 +247,12 @@ __device__ __forceinline__ void push_dir(const SiteInfo &si, const LK &U, const 
     }
 }
 
-template <int MU, class BK, class R, class LK>
+template <int MU, class BK, bool BF, class R, class LK>
 __device__ __forceinline__ void pull_dir(const SiteInfo &si, const LK &U, R (&out)[24], const R *__restrict__ sp,
                                          const R *__restrict__ hb) {
     constexpr int Vbh = BK::Vbh;
-    if (si.fin & (1u << MU)) {
+    const bool f = (si.fin >> MU) & 1u, b = (si.bin >> MU) & 1u;
+    if (BF || f) {
         R chi[24], h[12], uh[12], u[18];
         const int n = si.nbf[MU];
 #pragma unroll
@@ -250,14 +260,14 @@ __device__ __forceinline__ void pull_dir(const SiteInfo &si, const LK &U, R (&ou
         project<MU, -1>(chi, h);
         U.template get<MU>(u);
         su3_mul(u, h, uh);
-        accum_recon<MU, -1>(out, uh, U.scale());
+        accum_recon<MU, -1>(out, uh, f ? U.scale() : (R)0);
     }
-    if (si.bin & (1u << MU)) {
+    if (BF || b) {
         R uh[12];
         const int n = si.nbb[MU];
 #pragma unroll
         for (int k = 0; k < 12; ++k) uh[k] = hb[(MU * 12 + k) * Vbh + n];
-        accum_recon<MU, +1>(out, uh, (R)1);
+        accum_recon<MU, +1>(out, uh, b ? (R)1 : (R)0);
     }
 }
 
@@ -277,7 +287,7 @@ template <class BK, class R, int WANT = 2> struct HopLds {
 
 // TAIL = false (one LDS buffer only): the caller guarantees a barrier between the
 // receivers' reads and the next hop's writes, and the trailing barrier is left out.
-template <class BK, bool TAIL = true, class R, class LK, int WANT>
+template <class BK, bool TAIL = true, bool BF = false, class R, class LK, int WANT>
 __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK &U, const R (&in)[24], R (&out)[24],
                                           HopLds<BK, R, WANT> &lds) {
     constexpr int Vbh = BK::Vbh;
@@ -286,19 +296,19 @@ __device__ __forceinline__ void block_hop(int src, const SiteInfo &si, const LK 
     if (si.p == src) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) sp[k * Vbh + si.s] = in[k];
-        push_dir<0, BK>(si, U, in, hb);
-        push_dir<1, BK>(si, U, in, hb);
-        push_dir<2, BK>(si, U, in, hb);
-        push_dir<3, BK>(si, U, in, hb);
+        push_dir<0, BK, BF>(si, U, in, hb);
+        push_dir<1, BK, BF>(si, U, in, hb);
+        push_dir<2, BK, BF>(si, U, in, hb);
+        push_dir<3, BK, BF>(si, U, in, hb);
     }
     __syncthreads();
     if (si.p != src) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) out[k] = 0;
-        pull_dir<0, BK>(si, U, out, sp, hb);
-        pull_dir<1, BK>(si, U, out, sp, hb);
-        pull_dir<2, BK>(si, U, out, sp, hb);
-        pull_dir<3, BK>(si, U, out, sp, hb);
+        pull_dir<0, BK, BF>(si, U, out, sp, hb);
+        pull_dir<1, BK, BF>(si, U, out, sp, hb);
+        pull_dir<2, BK, BF>(si, U, out, sp, hb);
+        pull_dir<3, BK, BF>(si, U, out, sp, hb);
     }
     if constexpr (HopLds<BK, R, WANT>::NBUF == 2) {
         lds.cur ^= 1;

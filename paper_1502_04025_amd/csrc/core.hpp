@@ -259,14 +259,15 @@ __device__ __forceinline__ void accum_recon(R acc[24], const R h[12], R scale) {
 
 // ------------------------------------------------------------------ SU(3) on half spinors
 // out = U h for both spins; U has 18 reals, row major complex. Four FMAs per complex
-// multiply-add.
+// multiply-add; the first product of each sum is an FMA onto zero as well (its value,
+// except that an exact -0 becomes +0), so every term is one fused instruction.
 template <class R> __device__ __forceinline__ void su3_mul(const R u[18], const R h[12], R out[12]) {
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R re = u[2 * (3 * a)] * h[2 * (3 * sp)];
-            R im = u[2 * (3 * a)] * h[2 * (3 * sp) + 1];
+            R re = fmac(u[2 * (3 * a)], h[2 * (3 * sp)], (R)0);
+            R im = fmac(u[2 * (3 * a)], h[2 * (3 * sp) + 1], (R)0);
             re = fmac(-u[2 * (3 * a) + 1], h[2 * (3 * sp) + 1], re);
             im = fmac(u[2 * (3 * a) + 1], h[2 * (3 * sp)], im);
 #pragma unroll
@@ -289,8 +290,8 @@ template <class R> __device__ __forceinline__ void su3_dag_mul(const R u[18], co
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R re = u[2 * a] * h[2 * (3 * sp)];
-            R im = u[2 * a] * h[2 * (3 * sp) + 1];
+            R re = fmac(u[2 * a], h[2 * (3 * sp)], (R)0);
+            R im = fmac(u[2 * a], h[2 * (3 * sp) + 1], (R)0);
             re = fmac(u[2 * a + 1], h[2 * (3 * sp) + 1], re);
             im = fmac(-u[2 * a + 1], h[2 * (3 * sp)], im);
 #pragma unroll

@@ -244,7 +244,7 @@ void sap_half_kernel(SapArgs<S, SS, P> a) {
 
     // ---- 2. bhat_e = rho_e + kappa H_eo A_o^-1 rho_o (odd: T = A_o^-1 rho_o)
     if (!even) Xc.mul(A, T, (R)1);
-    block_hop<BK>(1, si, U, T, H, lds);
+    block_hop<BK, true, true>(1, si, U, T, H, lds);
     if (even) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
@@ -256,12 +256,12 @@ void sap_half_kernel(SapArgs<S, SS, P> a) {
     // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
     const R k2 = kappa * kappa;
     for (int it = 0; it < a.nmr; ++it) {
-        block_hop<BK>(0, si, U, A, H, lds);  // odd: H = H_oe r
+        block_hop<BK, true, true>(0, si, U, A, H, lds);  // odd: H = H_oe r
         if (EARLY_AE && even) mul_even(A, T);  // even: T = A_e r (needs only r)
         if (!even) Xc.mul(H, T, (R)1);           // odd: T = A_o^-1 H_oe r
         // even: H = H_eo T; the reduction's barrier below separates these reads from the
         // next hop's writes, so a single-buffer hop needs no barrier of its own at the end
-        block_hop<BK, false>(1, si, U, T, H, lds);
+        block_hop<BK, false, true>(1, si, U, T, H, lds);
         R pr_re = 0, pr_im = 0, pp = 0;
         if (even) {
             if (!EARLY_AE) mul_even(A, T);  // even: T = p = A_e r - kappa^2 H
@@ -297,7 +297,7 @@ void sap_half_kernel(SapArgs<S, SS, P> a) {
     }
 
     // ---- 4. delta: even B, odd A_o^-1 (rho_o + kappa H_oe delta_e)
-    block_hop<BK>(0, si, U, B, H, lds);
+    block_hop<BK, true, true>(0, si, U, B, H, lds);
     if (!even) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) T[k] = fmac(kappa, H[k], A[k]);
@@ -344,7 +344,8 @@ template <class BK> struct PairBlk {
 };
 
 // In-block hop between the parities in pair form: this thread pushes `in` from its site
-// of parity SRC and receives `out` at its site of the other parity.
+// of parity SRC and receives `out` at its site of the other parity. Both SAP kernels take
+// the branch-free directions: they are bound by instruction issue, not by memory.
 template <int SRC, class BK, bool TAIL = true, class R, class LK, int WANT>
 __device__ __forceinline__ void pair_hop(const SiteInfo &se, const SiteInfo &so, const LK &Ue, const LK &Uo,
                                          const R (&in)[24], R (&out)[24], HopLds<BK, R, WANT> &lds) {
@@ -357,17 +358,17 @@ __device__ __forceinline__ void pair_hop(const SiteInfo &se, const SiteInfo &so,
     const LK &Ur = SRC == 0 ? Uo : Ue;
 #pragma unroll
     for (int k = 0; k < 24; ++k) sp[k * Vbh + ss.s] = in[k];
-    push_dir<0, BK>(ss, Us, in, hb);
-    push_dir<1, BK>(ss, Us, in, hb);
-    push_dir<2, BK>(ss, Us, in, hb);
-    push_dir<3, BK>(ss, Us, in, hb);
+    push_dir<0, BK, true>(ss, Us, in, hb);
+    push_dir<1, BK, true>(ss, Us, in, hb);
+    push_dir<2, BK, true>(ss, Us, in, hb);
+    push_dir<3, BK, true>(ss, Us, in, hb);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 24; ++k) out[k] = 0;
-    pull_dir<0, BK>(sr, Ur, out, sp, hb);
-    pull_dir<1, BK>(sr, Ur, out, sp, hb);
-    pull_dir<2, BK>(sr, Ur, out, sp, hb);
-    pull_dir<3, BK>(sr, Ur, out, sp, hb);
+    pull_dir<0, BK, true>(sr, Ur, out, sp, hb);
+    pull_dir<1, BK, true>(sr, Ur, out, sp, hb);
+    pull_dir<2, BK, true>(sr, Ur, out, sp, hb);
+    pull_dir<3, BK, true>(sr, Ur, out, sp, hb);
     if constexpr (HopLds<BK, R, WANT>::NBUF == 2) {
         lds.cur ^= 1;
     } else if constexpr (TAIL) {
