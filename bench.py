@@ -94,6 +94,19 @@ def profiled_traffic(entry):
     return None
 
 
+def sap_kernel_name(cfg, prec):
+    """The SAP half-sweep kernel the library launches for this workload: the pair form for
+    FP16 links and clover with at least 256 domains of each colour and 256-site domains,
+    the split-parity form otherwise (SAPDD_SAP_KERNEL=pair/split forces one)."""
+    force = os.environ.get("SAPDD_SAP_KERNEL")
+    ndom = int(np.prod(cfg["dims"])) // int(np.prod(cfg["block"]))
+    pair = prec in ("f16", "f16l") and ndom // 2 >= 256
+    if force in ("pair", "split"):
+        pair = force == "pair"
+    pair = pair and int(np.prod(cfg["block"])) >= 256
+    return "sap_pair_kernel" if pair else "sap_half_kernel"
+
+
 def roofline_sap(prof, cfg, prec, nmr):
     """Roofline of the SAP half-sweep from the HIP-event times of the timed steps: flops
     and algorithmic bytes per launch (one colour, every right-hand side), both roofs, and
@@ -110,7 +123,8 @@ def roofline_sap(prof, cfg, prec, nmr):
     byts = pm.sap_half_bytes(cfg["block"], prec, nrhs) * V / 2
     ar = "f64" if prec == "f64" else "f32"
     alu_peak, alu_pub = pm.ALU_PEAK_TFLOPS[ar], pm.ALU_PEAK_PUBLISHED_TFLOPS[ar]
-    traffic = profiled_traffic(f"sap_half_kernel {'x'.join(map(str, cfg['dims']))} {'x'.join(map(str, cfg['block']))} "
+    kname = sap_kernel_name(cfg, prec)
+    traffic = profiled_traffic(f"{kname} {'x'.join(map(str, cfg['dims']))} {'x'.join(map(str, cfg['block']))} "
                                f"{prec} nrhs {nrhs}")
     t_alu = flops / (alu_peak * 1e12)
     t_hbm = byts / (pm.HBM_PEAK_GBS * 1e9)
@@ -126,11 +140,11 @@ def roofline_sap(prof, cfg, prec, nmr):
                   algorithmic_flops_per_launch=flops, algorithmic_bytes_per_launch=byts,
                   traffic_over_algorithmic=round(traffic / byts, 3) if traffic else None, **both)
     if t_alu >= t_hbm:
-        return dict(kernel="sap_half_kernel", bound="alu", achieved=round(tflops, 3), peak=alu_peak,
+        return dict(kernel=kname, bound="alu", achieved=round(tflops, 3), peak=alu_peak,
                     unit="TFLOP/s", frac=round(tflops / alu_peak, 4),
                     peak_note=f"FP32 vector peak without packed FP32 (the build disables it); the published "
                               f"{alu_pub} TFLOP/s counts packed FMAs", **common)
-    return dict(kernel="sap_half_kernel", bound="cache" if resident else "hbm", achieved=round(gbs, 1),
+    return dict(kernel=kname, bound="cache" if resident else "hbm", achieved=round(gbs, 1),
                 peak=pm.HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / pm.HBM_PEAK_GBS, 4), **common)
 
 
@@ -277,10 +291,12 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
     # 16 GB of the budget stay free for kernel scratch, graphs and the caching allocator
     budget = sv.plan_budget(plans, int(budget_gb * 1e9), max_slots=max_slots, reserve_bytes=16 * 10 ** 9)
 
+    # one admission state per volume for the whole run: the memory of kept slots stays
+    # charged to the budget from one phase to the next
+    adms = [sv.Admission(p.capacity, budget, p.per_rhs_bytes, p.kappa_bytes, p.warm_bytes) for p in plans]
+
     def serve(reqs, realtime):
-        workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity, budget, p.per_rhs_bytes,
-                                                                    p.kappa_bytes), None, None)
-                   for v, p in zip(vols, plans)]
+        workers = [sv.VolumeWorker(v.name, v.batch, v, a, None, None) for v, a in zip(vols, adms)]
         srv = sv.Server(workers)
         budget.peak = budget.used
         t0 = time.perf_counter()
@@ -292,6 +308,8 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
             r.x = None
         torch.cuda.empty_cache()
         out["steps"] = [w.steps for w in workers]
+        out["trims"] = [w.trims for w in workers]
+        out["worker_busy_s"] = [{k: round(v, 3) for k, v in w.busy_s.items()} for w in workers]
         out["budget_peak_gb"] = round(budget.peak / 1e9, 2)
         out["converged"] = all(all(st["converged"] for st in r.stats) for r in done if r.error is None)
         return out
@@ -561,6 +579,9 @@ def sub_mixed_vs_fp64(ctx, steps=3, warmup=1):
             "speedup": round(mixed / plain, 3)}
 
 
+EXTRAS = ("dslash", "copy_GB_s", "c2_16x16x16x32", "mixed_vs_fp64_32x32x32x64", "serving", "mg_near_critical")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,9 +601,14 @@ def main():
     ap.add_argument("--sweep-ncy", type=int, nargs="+", default=[2, 3, 4, 5, 6, 8, 12, 16])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the sub-benchmarks")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated sub-benchmarks to run (default: all of " + ", ".join(EXTRAS) + ")")
     ap.add_argument("--copy-probe", action="store_true",
                     help="with --no-extras: still run the 2 GiB copy kernel (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
+    unknown = set(args.extras.split(",")) - set(EXTRAS) - {""}
+    if unknown:
+        ap.error(f"unknown extras: {sorted(unknown)}")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
@@ -673,7 +699,11 @@ def main():
     del b, x
     torch.cuda.empty_cache()
     if not args.no_extras:
+        wanted = set(args.extras.split(","))
+
         def extra(key, fn):
+            if key not in wanted:
+                return
             t0 = time.perf_counter()
             try:
                 line[key] = fn()
@@ -684,7 +714,8 @@ def main():
         extra("dslash", lambda: dslash_bandwidth(ctx))
         extra("copy_GB_s", lambda: copy_bandwidth(ctx))
         for key in ("f16", "f32", "f16_links12", "f32_links12"):  # also as a fraction of the copy bandwidth
-            if isinstance(line["dslash"].get(key), dict) and isinstance(line["copy_GB_s"], float):
+            if (isinstance(line.get("dslash"), dict) and isinstance(line["dslash"].get(key), dict)
+                    and isinstance(line.get("copy_GB_s"), float)):
                 line["dslash"][key]["frac_of_copy"] = round(line["dslash"][key]["GB_s"] / line["copy_GB_s"], 4)
         extra("c2_16x16x16x32", lambda: sub_c2(ctx))
         extra("mixed_vs_fp64_32x32x32x64", lambda: sub_mixed_vs_fp64(ctx))

@@ -74,8 +74,10 @@ enum {
     SAPDD_LINKS12 = 8,     /* sapdd_apply_block_D: links stored as their first two
                             * rows, the third rebuilt in the kernel (FP32/FP16)  */
     SAPDD_ELASTIC = 16     /* sapdd_batch_create: a slot's device memory is committed
-                            * while the slot is in use and released when it is taken;
-                            * free slots cost address space only                 */
+                            * when the slot is first admitted, kept when it is taken
+                            * (the next add reuses it) and released by
+                            * sapdd_batch_trim; uncommitted slots cost address
+                            * space only                                          */
 };
 
 /* Solver parameters (Sec. 3.1 names the pieces; Sec. 3.7 uses 4-5 MR iterations and
@@ -222,15 +224,25 @@ int sapdd_batch_create(sapdd_ctx *ctx, const sapdd_field *field, const sapdd_par
                        sapdd_batch **out);
 int sapdd_batch_destroy(sapdd_batch *batch);
 /* Device memory the batch holds now (bytes): its fixed workspaces, plus, with
- * SAPDD_ELASTIC, the memory committed for the slots in use. *slot_bytes (if not NULL)
+ * SAPDD_ELASTIC, the memory committed for its slots (in use, or kept after a take until
+ * sapdd_batch_trim). *slot_bytes (if not NULL)
  * receives the most one more admitted slot can commit (0 for a batch allocated whole at
  * creation). Admission by footprint across batches (the serving loop) reads these; the
  * clover inverse of a new kappa (sapdd_solve_footprint counts it) comes on top. -1 for
  * a NULL batch. */
 long long sapdd_batch_memory(const sapdd_batch *batch, long long *slot_bytes);
+/* SAPDD_ELASTIC: give back the device memory of free slots that still hold it from an
+ * earlier use, keeping at most `keep` of them committed (keep = 0 releases all). Waits
+ * for the batch's stream first. Returns the bytes released (0 for a batch allocated
+ * whole), -1 for a NULL batch or keep < 0, a negative error code if the stream failed.
+ * Releasing physical memory is slow on this platform (it can stall for a second under
+ * load), so a serving loop trims only when another batch needs the memory. */
+long long sapdd_batch_trim(sapdd_batch *batch, int keep);
 /* Admit one right-hand side b (canonical spinor; x0 = start vector or NULL for zero;
- * flags: SAPDD_DEVICE_PTRS). Returns SAPDD_EFULL if every slot is taken, SAPDD_ENOMEM
- * if an elastic batch cannot commit the slot's memory (nothing stays committed). */
+ * flags: SAPDD_DEVICE_PTRS). An elastic batch takes a free slot that still holds its
+ * memory first and commits a new one only if there is none. Returns SAPDD_EFULL if every
+ * slot is taken, SAPDD_ENOMEM if an elastic batch cannot commit the slot's memory
+ * (nothing stays committed). */
 int sapdd_batch_add(sapdd_batch *batch, double kappa, const double *b, const double *x0, int flags, int *slot);
 /* One restart cycle for every unfinished slot; *running = slots still unfinished. */
 int sapdd_batch_step(sapdd_batch *batch, int *running);

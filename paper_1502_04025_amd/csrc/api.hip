@@ -1207,9 +1207,14 @@ void vmm_release(sapdd_batch::EField &e, int r) {
     e.committed[r] = 0;
 }
 
+bool slot_committed(const sapdd_batch *B, int r) {
+    return B->elastic && !B->efields.empty() && B->efields.front().committed[r];
+}
+
 // Commit slot r's memory in every elastic field; on failure nothing stays committed.
+// A slot that still holds its memory from an earlier use keeps it.
 int commit_slot(sapdd_batch *B, int r) {
-    if (!B->elastic) return SAPDD_OK;
+    if (!B->elastic || slot_committed(B, r)) return SAPDD_OK;
     const char *what = "";
     hipError_t err = hipSuccess;
     size_t i = 0;
@@ -1870,6 +1875,31 @@ long long sapdd_batch_memory(const sapdd_batch *B, long long *slot_bytes) {
     return held;
 }
 
+long long sapdd_batch_trim(sapdd_batch *B, int keep) {
+    if (!B || keep < 0) return -1;
+    sapdd_ctx *c = B->c;
+    c->err.clear();
+    if (!B->elastic) return 0;
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, SAPDD_EDEVICE, "synchronising the batch's stream failed");
+    }
+    long long per = 0;
+    for (const auto &e : B->efields) per += (long long)(e.data_per_slot + e.scale_per_slot);
+    int warm = 0;
+    long long freed = 0;
+    for (int r = 0; r < B->cap; ++r) {
+        if (B->slots[r].used || !slot_committed(B, r)) continue;
+        if (warm < keep) {
+            ++warm;
+            continue;
+        }
+        release_slot(B, r);
+        freed += per;
+    }
+    return freed;
+}
+
 int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double *x0, int flags, int *slot_out) {
     if (!B || !b || !slot_out) return SAPDD_EINVAL;
     sapdd_ctx *c = B->c;
@@ -1878,11 +1908,12 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     if (!(kappa > 0)) return fail(c, SAPDD_EINVAL, "kappa must be > 0");
     if (B->mg && kappa != B->mg->kappa)
         return fail(c, SAPDD_EINVAL, "the batch's multigrid preconditioner was built for kappa = %.17g", B->mg->kappa);
+    // a free slot whose memory an elastic batch still holds first, else the first free one
     int r = -1;
     for (int q = 0; q < B->cap; ++q)
-        if (!B->slots[q].used) {
+        if (!B->slots[q].used && (r < 0 || slot_committed(B, q))) {
             r = q;
-            break;
+            if (!B->elastic || slot_committed(B, q)) break;
         }
     if (r < 0) return fail(c, SAPDD_EFULL, "no free slot in the batch (capacity %d)", B->cap);
     Fld xf;
@@ -2023,8 +2054,7 @@ int sapdd_batch_take(sapdd_batch *B, int slot, double *x, int flags, sapdd_stats
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int status = s.status;
     sap_clover_release(B->f, s.kappa, lprec(B->prec));
-    release_slot(B, slot);
-    s = Slot();
+    s = Slot();  // an elastic slot keeps its memory for the next add (sapdd_batch_trim frees it)
     s.H.assign((size_t)(B->m + 1) * B->m, 0.0);
     s.cs.assign(B->m, 0.0);
     s.sn.assign(B->m, 0.0);

@@ -34,7 +34,7 @@ EXPORTS = (
     "sapdd_compute_clover", "sapdd_load_clover", "sapdd_free_field", "sapdd_apply_D",
     "sapdd_apply_block_D", "sapdd_sap", "sapdd_sap_noalloc", "sapdd_solve", "sapdd_solve_footprint", "sapdd_copy",
     "sapdd_profile", "sapdd_batch_create", "sapdd_batch_destroy", "sapdd_batch_add",
-    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_memory", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
+    "sapdd_batch_step", "sapdd_batch_poll", "sapdd_batch_memory", "sapdd_batch_trim", "sapdd_batch_take", "sapdd_mg_setup", "sapdd_mg_destroy",
     "sapdd_mg_prolongator", "sapdd_mg_coarse_operator", "sapdd_mg_coarse_solve", "sapdd_mg_precond",
     "sapdd_mg_solve", "sapdd_batch_set_mg",
 )
@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_batch_poll.argtypes = [VP, I, P(Stats)]
     lib.sapdd_batch_memory.argtypes = [VP, P(C.c_longlong)]
     lib.sapdd_batch_memory.restype = C.c_longlong
+    lib.sapdd_batch_trim.argtypes = [VP, I]
+    lib.sapdd_batch_trim.restype = C.c_longlong
     lib.sapdd_batch_take.argtypes = [VP, I, VP, I, P(Stats)]
     lib.sapdd_mg_setup.argtypes = [VP, VP, D, P(Params), P(MgParams), VP, I, P(VP)]
     lib.sapdd_mg_destroy.argtypes = [VP]
@@ -127,7 +129,8 @@ def load_library(path: str = LIB_PATH):
     lib.sapdd_mg_solve.argtypes = [VP, P(Params), I, VP, VP, P(Stats)]
     lib.sapdd_batch_set_mg.argtypes = [VP, VP]
     for name in EXPORTS:
-        if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint", "sapdd_batch_memory"):
+        if name not in ("sapdd_destroy", "sapdd_last_error", "sapdd_solve_footprint", "sapdd_batch_memory",
+                        "sapdd_batch_trim"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -389,6 +392,14 @@ class Batch:
         slot = C.c_longlong()
         held = self.ctx.lib.sapdd_batch_memory(self.h, C.byref(slot))
         return int(held), int(slot.value)
+
+    def trim(self, keep: int = 0) -> int:
+        """Elastic batch: release the memory of free slots kept from earlier use, keeping at
+        most `keep` of them; returns the bytes released."""
+        n = self.ctx.lib.sapdd_batch_trim(self.h, int(keep))
+        if n < 0:
+            self.ctx._check(int(n))
+        return int(n)
 
     def step(self) -> int:
         """One restart cycle for every unfinished slot; returns how many are unfinished."""

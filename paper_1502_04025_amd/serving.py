@@ -11,14 +11,17 @@ their kernels overlap on the device.
 
 Admission is by HBM footprint from one shared budget: the resident fields, a cache of
 clover inverses per volume and a reserve for kernel scratch are set aside first; every
-request then draws the bytes its right-hand sides need (the batch's per-slot memory,
-committed only while the slot is in use, plus the request's sources, solutions and its
-clover inverse) from what is left, whatever its volume. Memory freed by one volume's
-finished requests serves the next request of any volume. A request enters when its
-volume's batch has free slots and the budget holds its footprint; one that could never
-fit is rejected at once. A request that fails (a singular clover term, a non-finite
-residual) or misses the tolerance within the iteration cap comes back with its error
-set, and its slots and bytes are returned.
+request then draws the bytes its right-hand sides need (the batch's per-slot memory, plus
+the request's sources, solutions and its clover inverse) from what is left, whatever its
+volume. Elastic batches commit a slot's memory on first use and keep it after the slot is
+taken, so the volume's next request reuses it without touching the allocator; releasing
+physical memory is slow (it can stall the device for a second), so a volume gives its
+kept memory back only when another volume is waiting for budget and it has no queued
+request itself (or is stuck waiting too). Memory thereby moves to the volumes that have
+work as the load shifts. A request enters when its volume's batch has free slots and the
+budget holds its footprint; one that could never fit is rejected at once. A request
+that fails (a singular clover term, a non-finite residual) or misses the tolerance within
+the iteration cap comes back with its error set, and its slots and bytes are returned.
 """
 from __future__ import annotations
 
@@ -59,6 +62,7 @@ class VolumePlan:
     per_rhs_bytes: int    # one slot's solver state, plus the canonical b and x of one RHS
     kappa_bytes: int      # one clover inverse for a new kappa
     capacity: int = 0     # batch slots (address space only in an elastic batch)
+    warm_bytes: int = 0   # elastic: the part of per_rhs_bytes a slot keeps after a take
 
 
 class HbmBudget:
@@ -71,6 +75,30 @@ class HbmBudget:
         self.used = int(fixed_bytes)
         self.peak = self.used
         self.lock = threading.Lock()
+        self.waiting = set()  # names of the volumes whose next request waits for bytes
+        self.running = set()  # names of the workers not yet finished
+
+    def set_waiting(self, name: str, on: bool) -> None:
+        with self.lock:
+            (self.waiting.add if on else self.waiting.discard)(name)
+
+    def set_running(self, name: str, on: bool) -> None:
+        with self.lock:
+            (self.running.add if on else self.running.discard)(name)
+            if not on:
+                self.waiting.discard(name)
+
+    def others_running(self, name: str) -> bool:
+        with self.lock:
+            return bool(self.running - {name})
+
+    def is_waiting(self, name: str) -> bool:
+        with self.lock:
+            return name in self.waiting
+
+    def others_waiting(self, name: str) -> bool:
+        with self.lock:
+            return bool(self.waiting - {name})
 
     def try_take(self, n: int) -> bool:
         with self.lock:
@@ -123,32 +151,53 @@ def plan_capacity(plans, budget_bytes: int, max_slots: int = 24, kappa_cache: in
 class Admission:
     """Admission of one volume (thread-safe): a request of n right-hand sides needs n free
     slots of the volume's batch and, with a shared budget, n * slot_bytes +
-    request_bytes of it."""
+    request_bytes of it.
+
+    With warm_bytes > 0 (an elastic batch that keeps a taken slot's memory) that part of
+    a slot is charged once, when the batch first commits it, and stays charged while the
+    batch keeps it: a request pays warm_bytes only for the slots beyond those already
+    committed. `released(k)` returns the charge of k kept slots the batch has freed."""
 
     def __init__(self, capacity: int, budget: HbmBudget | None = None, slot_bytes: int = 0,
-                 request_bytes: int = 0):
+                 request_bytes: int = 0, warm_bytes: int = 0):
         self.capacity = capacity
         self.free = capacity
         self.budget = budget
         self.slot_bytes = int(slot_bytes)
         self.request_bytes = int(request_bytes)
+        self.warm_bytes = int(warm_bytes) if budget is not None else 0
+        self.committed = 0  # slots whose warm part the batch holds (in use or kept)
         self.lock = threading.Lock()
 
+    def _cost(self, n: int, new: int) -> int:
+        if self.budget is None:
+            return 0
+        return n * (self.slot_bytes - self.warm_bytes) + new * self.warm_bytes + self.request_bytes
+
     def cost(self, n: int) -> int:
-        return n * self.slot_bytes + self.request_bytes if self.budget is not None else 0
+        """Bytes n right-hand sides cost when none of their slots is kept from before."""
+        return self._cost(n, n)
 
     def fits_ever(self, n: int) -> bool:
         if n > self.capacity:
             return False
         return self.budget is None or self.cost(n) <= self.budget.total - self.budget.fixed
 
+    def kept(self) -> int:
+        """Free slots whose memory the batch still holds."""
+        with self.lock:
+            return self.committed - (self.capacity - self.free) if self.warm_bytes else 0
+
     def try_take(self, n: int) -> bool:
         with self.lock:
             if n > self.free:
                 return False
-            if self.budget is not None and not self.budget.try_take(self.cost(n)):
+            new = max(0, self.capacity - self.free + n - self.committed) if self.warm_bytes else n
+            if self.budget is not None and not self.budget.try_take(self._cost(n, new)):
                 return False
             self.free -= n
+            if self.warm_bytes:
+                self.committed += new
             return True
 
     def give_back(self, n: int) -> None:
@@ -156,7 +205,14 @@ class Admission:
             self.free += n
             assert self.free <= self.capacity
         if self.budget is not None:
-            self.budget.give_back(self.cost(n))
+            self.budget.give_back(self._cost(n, 0 if self.warm_bytes else n))
+
+    def released(self, k: int) -> None:
+        with self.lock:
+            self.committed -= k
+            assert 0 <= self.committed and self.committed >= self.capacity - self.free
+        if self.budget is not None:
+            self.budget.give_back(k * self.warm_bytes)
 
 
 class VolumeWorker(threading.Thread):
@@ -180,6 +236,8 @@ class VolumeWorker(threading.Thread):
         self.cancels = set()
         self.error = None
         self.steps = 0
+        self.trims = 0
+        self.busy_s = {"admit": 0.0, "step": 0.0, "harvest": 0.0, "trim": 0.0}  # host wall time per phase
 
     def submit(self, req: Request):
         with self.cv:
@@ -230,11 +288,38 @@ class VolumeWorker(threading.Thread):
             self.stop_when_idle = True
             self.cv.notify()
 
+    def _trim_if_wanted(self):
+        """Give the memory of kept slots back to the budget when another volume waits for
+        it and this one has no queued request, or is waiting itself with nothing running
+        (kept memory it cannot use now)."""
+        budget = self.adm.budget
+        if budget is None or not self.adm.warm_bytes or not budget.others_waiting(self.name):
+            return
+        with self.cv:
+            idle = not self.queue
+        stuck = not self.active and budget.is_waiting(self.name)
+        k = self.adm.kept()
+        if k and (idle or stuck):
+            t0 = time.perf_counter()
+            self.batch.trim(0)
+            self.adm.released(k)
+            self.trims += 1
+            self.busy_s["trim"] += time.perf_counter() - t0
+
     def _admit(self):
+        budget = self.adm.budget
         while True:
             with self.cv:
-                if not self.queue or not self.adm.try_take(self.queue[0].nrhs):
+                if not self.queue:
+                    if budget is not None:
+                        budget.set_waiting(self.name, False)
                     return
+                if not self.adm.try_take(self.queue[0].nrhs):
+                    if budget is not None:  # waiting for bytes, not for this volume's own slots
+                        budget.set_waiting(self.name, self.adm.free >= self.queue[0].nrhs)
+                    return
+                if budget is not None:
+                    budget.set_waiting(self.name, False)
                 req = self.queue.popleft()
             req.t_admit = self.clock()
             req.slots = []
@@ -280,21 +365,49 @@ class VolumeWorker(threading.Thread):
             self.on_done(req)
         self.active = still
 
+    def start(self):
+        if self.adm.budget is not None:
+            self.adm.budget.set_running(self.name, True)
+        super().start()
+
     def run(self):
         try:
             with self.backend.thread_context():
                 self._loop()
+                self._leave()
         except Exception as e:  # surfaced by Server.run
             self.error = e
+        finally:
+            if self.adm.budget is not None:
+                self.adm.budget.set_running(self.name, False)
+
+    def _leave(self):
+        """A finishing worker can no longer trim on demand, so while other workers still
+        run it gives its kept memory back (the last one keeps it for a later run)."""
+        budget = self.adm.budget
+        k = self.adm.kept()
+        if budget is not None and k and budget.others_running(self.name):
+            t0 = time.perf_counter()
+            self.batch.trim(0)
+            self.adm.released(k)
+            self.trims += 1
+            self.busy_s["trim"] += time.perf_counter() - t0
 
     def _loop(self):
         while True:
             self._cancel_active()
+            self._trim_if_wanted()
+            t0 = time.perf_counter()
             self._admit()
+            t1 = time.perf_counter()
+            self.busy_s["admit"] += t1 - t0
             if self.active:
                 self.batch.step()
                 self.steps += 1
+                t2 = time.perf_counter()
                 self._harvest()
+                self.busy_s["step"] += t2 - t1
+                self.busy_s["harvest"] += time.perf_counter() - t2
                 continue
             with self.cv:
                 if self.queue:  # waiting for memory another volume holds: no busy spin
@@ -397,7 +510,7 @@ class TorchVolume:
         field_bytes = 2 * v * 72 * 8 + lo
         if self.elastic and self.batch is not None:
             fixed, slot = self.batch.memory()
-            return VolumePlan(self.name, field_bytes + fixed, slot + canon, kappa_bytes)
+            return VolumePlan(self.name, field_bytes + fixed, slot + canon, kappa_bytes, warm_bytes=slot)
         return VolumePlan(self.name, field_bytes, per_rhs + canon, kappa_bytes)
 
     def start(self, capacity: int):

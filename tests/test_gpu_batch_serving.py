@@ -147,8 +147,9 @@ def test_cancel_and_resume_from_the_taken_iterate(env):
 
 def test_elastic_batch_commits_memory_per_slot(env):
     """An elastic batch holds only its fixed workspaces until slots are admitted, commits
-    at most slot_bytes per admitted right-hand side, gives it back when the slot is taken,
-    and computes the same bits as a batch allocated whole."""
+    at most slot_bytes per admitted right-hand side, keeps a taken slot's memory for the
+    next add, gives it back on trim, and computes the same bits as a batch allocated
+    whole."""
     from paper_1502_04025_amd import Batch
     torch, f = env["torch"], env["f"]
     b = synthetic.gaussian_source(env["dims"], 3, 35)
@@ -173,9 +174,13 @@ def test_elastic_batch_commits_memory_per_slot(env):
                     assert batch.take(s, out)["converged"]
                     xs[r] = out
                     del pending[r]
-                    if r == 0:  # the freed slot's memory serves the third right-hand side
+                    if r == 0:  # the kept slot's memory serves the third right-hand side
                         pending[2] = batch.add(kap[2], b[2])
-        assert batch.memory()[0] == held0  # every slot taken: only the fixed part is left
+                        assert pending[2] == s0 and batch.memory()[0] == held2
+        assert batch.memory()[0] == held2  # every slot taken, both kept
+        assert batch.trim(1) == held2 - held1 and batch.memory()[0] == held1
+        assert batch.trim(0) == held1 - held0 and batch.memory()[0] == held0
+        assert batch.trim(0) == 0
         batch.close()
     for r in range(3):
         assert np.array_equal(xs[r], whole[r])
@@ -197,11 +202,19 @@ def test_serving_with_one_shared_budget(env):
     budget = sv.plan_budget(plans, total, max_slots=8, kappa_cache=4)
     reqs = synthetic.serving_requests(12, rate=1e9, seed=36, volumes=[v.dims for v in vols], max_rhs=4)
     reqs = [sv.Request(r["id"], 0.0, r["vol"], r["kappa"], r["nrhs"], r["seed"]) for r in reqs]
-    workers = [sv.VolumeWorker(v.name, v.batch, v, sv.Admission(p.capacity, budget, p.per_rhs_bytes, p.kappa_bytes),
-                               None, None) for v, p in zip(vols, plans)]
+    adms = [sv.Admission(p.capacity, budget, p.per_rhs_bytes, p.kappa_bytes, p.warm_bytes) for p in plans]
+    assert all(p.warm_bytes > 0 for p in plans)
+    workers = [sv.VolumeWorker(v.name, v.batch, v, a, None, None) for v, a in zip(vols, adms)]
     done = sv.Server(workers).run(reqs, realtime=False)
     assert len(done) == 12 and all(r.error is None for r in done)
-    assert budget.peak <= budget.total and budget.used == budget.fixed
+    assert budget.peak <= budget.total
+    # what the budget still charges is exactly the memory the batches keep
+    for v, a, p in zip(vols, adms, plans):
+        with torch.cuda.stream(v.stream):
+            k = a.kept()
+            assert v.batch.trim(0) == k * p.warm_bytes
+            a.released(k)
+    assert budget.used == budget.fixed
     fields = {0: ((8, 8, 8, 8), 5), 1: ((8, 8, 8, 16), 6)}
     ops = {k: (lambda u: (u, wilson.clover_term(u, 1.0)))(synthetic.gauge_field(d, 0.3, s))
            for k, (d, s) in fields.items()}

@@ -207,3 +207,81 @@ def test_failed_and_unconverged_requests_report_errors_and_return_their_slots():
     assert adm.free == 4 and not batch.slots
     s = sv.summarize(done, wall=1.0)
     assert s["requests"] == 3 and s["rejected"] == 3
+
+
+class KeepingBatch(FakeBatch):
+    """An elastic stand-in: a slot's memory is committed on first add and kept after take
+    until trim; add prefers a slot that still holds memory (as sapdd_batch_add does)."""
+
+    def __init__(self, capacity):
+        super().__init__(capacity)
+        self.committed = set()
+        self.commits = 0
+
+    def add(self, kappa, b):
+        free = [s for s in range(self.cap) if s not in self.slots]
+        if not free:
+            raise RuntimeError("full")
+        kept = [s for s in free if s in self.committed]
+        s = kept[0] if kept else free[0]
+        if s not in self.committed:
+            self.committed.add(s)
+            self.commits += 1
+        self.slots[s] = [0, b]
+        return s
+
+    def trim(self, keep=0):
+        idle = sorted(s for s in self.committed if s not in self.slots)
+        for s in idle[keep:]:
+            self.committed.discard(s)
+        return 10 * len(idle[keep:])
+
+
+def test_kept_slots_are_charged_once():
+    """A request that reuses kept slots pays only for its sources and kappa; released()
+    returns the kept slots' bytes."""
+    budget = sv.HbmBudget(1000, fixed_bytes=100)
+    a = sv.Admission(8, budget, slot_bytes=30, request_bytes=5, warm_bytes=20)
+    assert a.try_take(3) and budget.used == 100 + 3 * 30 + 5 and a.committed == 3
+    a.give_back(3)  # the batch keeps the 3 slots: their warm part stays charged
+    assert budget.used == 100 + 3 * 20 and a.kept() == 3
+    assert a.try_take(2) and budget.used == 100 + 60 + 2 * 10 + 5  # no new slot memory
+    assert a.try_take(2) and a.committed == 4 and a.kept() == 0    # one slot more
+    a.give_back(2)
+    a.give_back(2)
+    assert a.kept() == 4 and budget.used == 100 + 4 * 20
+    a.released(4)
+    assert budget.used == budget.fixed and a.committed == 0
+
+
+def test_idle_volume_gives_kept_memory_to_a_waiting_volume():
+    """The two requests cannot hold their memory together: whichever volume runs first
+    keeps its slots after finishing, the other volume's request waits for those bytes, and
+    the first volume (nothing queued) trims them. Every request completes and the budget
+    ends with only the memory still kept."""
+    budget = sv.HbmBudget(100, fixed_bytes=10)
+    b0, b1 = KeepingBatch(8), KeepingBatch(8)
+    a0 = sv.Admission(8, budget, slot_bytes=12, request_bytes=0, warm_bytes=10)
+    a1 = sv.Admission(8, budget, slot_bytes=12, request_bytes=0, warm_bytes=10)
+    w0 = sv.VolumeWorker("v0", b0, FakeBackend(), a0, None, None)
+    w1 = sv.VolumeWorker("v1", b1, FakeBackend(), a1, None, None)
+    reqs = [sv.Request(0, 0.0, 0, 0.12, 6, seed=1),   # 72 of the 90 free bytes
+            sv.Request(1, 0.0, 1, 0.12, 5, seed=2)]   # 60: waits until volume 0 trims
+    done = sv.Server([w0, w1]).run(reqs, realtime=False)
+    assert sorted(r.id for r in done) == [0, 1] and all(r.error is None for r in done)
+    assert w0.trims + w1.trims >= 1 and bool(b0.committed) != bool(b1.committed)
+    assert budget.used == budget.fixed + 10 * (len(b0.committed) + len(b1.committed))
+    assert budget.peak <= budget.total and not budget.waiting and not budget.running
+
+
+def test_busy_volume_keeps_its_memory_between_requests():
+    """A volume with queued requests reuses its kept slots: each slot is committed once."""
+    budget = sv.HbmBudget(1000, fixed_bytes=0)
+    b = KeepingBatch(4)
+    a = sv.Admission(4, budget, slot_bytes=12, request_bytes=1, warm_bytes=10)
+    w = sv.VolumeWorker("v", b, FakeBackend(), a, None, None)
+    reqs = [sv.Request(i, 0.0, 0, 0.12, n, seed=i) for i, n in enumerate([3, 4, 2, 4, 1])]
+    done = sv.Server([w]).run(reqs, realtime=False)
+    assert len(done) == 5 and all(r.error is None for r in done)
+    assert b.commits == 4 and w.trims == 0
+    assert budget.used == 4 * 10 and a.kept() == 4
