@@ -74,8 +74,9 @@ def make_source(cfg):
 
 
 def profiled_traffic(entry):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, or
-    None if the kernel's sources changed since the counters were taken."""
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summaries, or
+    None if there is none for the kernel's current sources (changed since the counters
+    were taken)."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.txt")):
@@ -88,9 +89,8 @@ def profiled_traffic(entry):
             h = hashlib.sha256()
             for f in rec["sources"]:
                 h.update(open(os.path.join(ROOT, f), "rb").read())
-            if h.hexdigest()[:16] != rec["source_sha"]:
-                return None
-            return rec["fetch_bytes"] + rec["write_bytes"]
+            if h.hexdigest()[:16] == rec["source_sha"]:
+                return rec["fetch_bytes"] + rec["write_bytes"]
     return None
 
 
@@ -300,7 +300,8 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
         srv = sv.Server(workers)
         budget.peak = budget.used
         t0 = time.perf_counter()
-        done = srv.run(reqs, realtime=realtime)
+        done = srv.run(reqs, realtime=realtime,
+                       progress=lambda n, tot: print(f"# serving: {n}/{tot} requests done", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out = sv.summarize(done, wall)
@@ -319,12 +320,18 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
         return [sv.Request(r["id"], r["t_arrival"] if rate < 1e8 else 0.0, r["vol"], r["kappa"], r["nrhs"],
                            r["seed"]) for r in rs]
 
-    serve(stream_of(warm, 1e9, 30), False)  # warm up: graphs, clover inverses
-    sat = serve(stream_of(n_requests, 1e9, 31), False)
+    def note(phase, r):
+        print(f"# serving {phase}: {r['rhs_solves']} RHS in {r['requests']} requests, {r['solves_per_s']:.2f} RHS/s, "
+              f"p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+        return r
+
+    note("warm-up", serve(stream_of(warm, 1e9, 30), False))  # graphs, clover inverses, slot memory
+    sat = note("saturation", serve(stream_of(n_requests, 1e9, 31), False))
     runs = {}
     for frac in fracs:
         rate = frac * sat["requests_per_s"]
-        runs[str(frac)] = dict(rate_req_s=round(rate, 4), **serve(stream_of(n_requests, rate, 32), True))
+        runs[str(frac)] = dict(rate_req_s=round(rate, 4), **note(f"{frac} x saturation",
+                                                                   serve(stream_of(n_requests, rate, 32), True)))
     for v in vols:
         v.close()
     return dict(admission="one shared HBM budget, footprint per request (elastic batches)",

@@ -134,7 +134,10 @@ const char *sapdd_last_error(const sapdd_ctx *ctx);
  * sapdd_free_field) and fix its device layout: the lattice is tiled
  * by Schwarz blocks of extents block[] (each even and >= 2, dividing dims, with an even
  * number of blocks per direction so the blocks two-colour the lattice, Sec. 3.5 footnote).
- * Supported block shapes: 2x2x2x2, 4x4x4x4, 8x4x4x4. The clover term starts at zero. */
+ * Supported block shapes: 2x2x2x2, 4x4x4x4, 8x4x4x4. The clover term starts at zero.
+ * The library caches the SAP clover inverse of up to 16 kappas on the field and reuses
+ * an evicted one's memory for the next kappa in stream order, so calls that use one
+ * field must not overlap on different streams. */
 int sapdd_load_gauge(sapdd_ctx *ctx, const int dims[4], const int block[4], const double *links,
                      int antiperiodic_t, int flags, sapdd_field **out);
 /* Sec. 3.1 (the operator is Wilson-clover): build the clover term T(x) on the device from

@@ -59,6 +59,7 @@ struct sapdd_field {
     Fld tclov_lo[3] = {};
     Fld links12[3] = {};   // [P32], [P16] links as their first two rows, made on demand
     std::vector<XEntry> xcache;
+    std::vector<Fld> xspare;  // clover buffers of singular kappas, reused by the next one
     unsigned long long use_clock = 0;
     double csw = 0.0;
     // unique per loaded field: a kept batch is reused only for the very field it was
@@ -286,9 +287,11 @@ void free_fld(Fld &x) {
     x = Fld{};
 }
 
-// SAP clover X for (kappa, prec), cached on the field: at most 16 unreferenced entries
-// are kept, the least recently used one goes first. `ref` adds a reference that
-// sap_clover_release drops.
+// SAP clover X for (kappa, prec), cached on the field: at most 16 entries. A new kappa
+// recomputes into the buffer of the least recently used unreferenced entry (or of a
+// spare one) rather than freeing it: hipFree waits for the whole device, the other
+// streams' work included, which stalled concurrent serving volumes for the length of
+// their steps. `ref` adds a reference that sap_clover_release drops.
 int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, bool ref = false) {
     for (auto &e : f->xcache)
         if (e.kappa == kappa && e.prec == prec) {
@@ -298,34 +301,50 @@ int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, b
             return SAPDD_OK;
         }
     const size_t max_entries = 16;
+    Fld x{};
+    for (size_t i = 0; i < f->xspare.size(); ++i)
+        if (f->xspare[i].prec == prec) {
+            x = f->xspare[i];
+            f->xspare.erase(f->xspare.begin() + i);
+            break;
+        }
     while (f->xcache.size() >= max_entries) {
         auto it = f->xcache.end();
         for (auto q = f->xcache.begin(); q != f->xcache.end(); ++q)
             if (q->refs == 0 && (it == f->xcache.end() || q->last_use < it->last_use)) it = q;
         if (it == f->xcache.end()) break;  // every entry in use: grow instead
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        free_fld(it->x);
+        // the stream's earlier launches may still read the evicted entry; the new
+        // kappa's kernel below runs after them on the same stream
+        if (!x.data && it->prec == prec) {
+            x = it->x;
+        } else {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            free_fld(it->x);
+        }
         f->xcache.erase(it);
     }
     const Geom &g = f->geo;
+    if (!x.data) {
+        size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
+        const size_t sc_off = (bytes + 255) / 256 * 256;
+        if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
+        void *p = nullptr;
+        HIPCHK(c, hipMalloc(&p, bytes));
+        x = Fld{p, prec == P16 ? (float *)((char *)p + sc_off) : nullptr, prec};
+    }
     XEntry e;
     e.kappa = kappa;
     e.prec = prec;
     e.last_use = ++f->use_clock;
     e.refs = ref ? 1 : 0;
-    size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
-    const size_t sc_off = (bytes + 255) / 256 * 256;
-    if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
-    void *p = nullptr;
-    HIPCHK(c, hipMalloc(&p, bytes));
-    e.x = Fld{p, prec == P16 ? (float *)((char *)p + sc_off) : nullptr, prec};
+    e.x = x;
     HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
     HIPCHK(c, launch_sap_clover(g, f->tclov64, kappa, e.x, c->d_flag, c->stream));
     int sing = 0;
     HIPCHK(c, hipMemcpyAsync(&sing, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (sing) {
-        (void)hipFree(p);
+        f->xspare.push_back(x);  // kept for the next kappa
         return fail(c, SAPDD_ESINGULAR, "clover block 1 + kappa T is singular at kappa = %g", kappa);
     }
     f->xcache.push_back(e);
@@ -370,7 +389,12 @@ int sap_prepare(sapdd_ctx *c, sapdd_field *f, const double *kappa, int nrhs, int
     CHK(lo_copies(c, f, lp));
     s->links = links_of(f, lp);
     std::vector<Fld> xs(nrhs);
-    for (int r = 0; r < nrhs; ++r) CHK(sap_clover(c, f, kappa[r], lp, &xs[r]));
+    // referenced while the list is built, so a later kappa of this call never recycles
+    // the buffer of an earlier one (more than 16 distinct kappas grow the cache)
+    int rc = SAPDD_OK, got = 0;
+    for (; got < nrhs && rc == SAPDD_OK; ++got) rc = sap_clover(c, f, kappa[got], lp, &xs[got], true);
+    for (int r = 0; r < got - (rc != SAPDD_OK); ++r) sap_clover_release(f, kappa[r], lp);
+    CHK(rc);
     CHK(spinor_buf(c, "sap_rres", g, nrhs, sp, 12, &s->rres));
     CHK(spinor_buf(c, "sap_delta", g, nrhs, sp, 24, &s->delta));
     // rres scales are indexed per half lattice: spinor_buf allotted V per field, enough.
@@ -609,6 +633,8 @@ static void drop_derived(sapdd_field *f) {
     }
     for (auto &e : f->xcache) free_fld(e.x);
     f->xcache.clear();
+    for (auto &x : f->xspare) free_fld(x);
+    f->xspare.clear();
 }
 
 int sapdd_compute_clover(sapdd_ctx *c, sapdd_field *f, double csw) {

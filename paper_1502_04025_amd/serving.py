@@ -237,7 +237,8 @@ class VolumeWorker(threading.Thread):
         self.error = None
         self.steps = 0
         self.trims = 0
-        self.busy_s = {"admit": 0.0, "step": 0.0, "harvest": 0.0, "trim": 0.0}  # host wall time per phase
+        # host wall time per phase (admit_io and admit_add are parts of admit)
+        self.busy_s = {"admit": 0.0, "admit_io": 0.0, "admit_add": 0.0, "step": 0.0, "harvest": 0.0, "trim": 0.0}
 
     def submit(self, req: Request):
         with self.cv:
@@ -324,10 +325,14 @@ class VolumeWorker(threading.Thread):
             req.t_admit = self.clock()
             req.slots = []
             try:
+                t0 = time.perf_counter()
                 srcs = self.backend.make_source(req)
                 req.x = self.backend.make_output(req)
+                t1 = time.perf_counter()
                 for b in srcs:
                     req.slots.append(self.batch.add(req.kappa, b))
+                self.busy_s["admit_io"] += t1 - t0
+                self.busy_s["admit_add"] += time.perf_counter() - t1
             except Exception as e:  # this request fails alone: its slots and bytes go back
                 for s, out in zip(req.slots, req.x or []):
                     try:
@@ -434,24 +439,36 @@ class Server:
         with self.lock:
             self.done.append(req)
 
-    def run(self, requests, realtime: bool = True):
+    def run(self, requests, realtime: bool = True, progress=None, every: float = 30.0):
         """Release every request at its arrival time (or all at once if not realtime) and
-        wait for all of them. Returns the finished requests."""
+        wait for all of them. Returns the finished requests. progress(finished, total), if
+        given, is called from this thread about every `every` seconds."""
         self.t0 = time.perf_counter()
+        last = [self.t0]
+
+        def tick():
+            if progress is not None and time.perf_counter() - last[0] >= every:
+                last[0] = time.perf_counter()
+                with self.lock:
+                    n = len(self.done)
+                progress(n, len(requests))
+
         for w in self.workers:
             w.clock = self.clock
             w.on_done = self._on_done
             w.start()
         for req in sorted(requests, key=lambda r: r.t_arrival):
             if realtime:
-                dt = req.t_arrival - self.clock()
-                if dt > 0:
-                    time.sleep(dt)
+                while (dt := req.t_arrival - self.clock()) > 0:
+                    time.sleep(min(dt, 1.0))
+                    tick()
             self.workers[req.vol].submit(req)
         for w in self.workers:
             w.finish()
         for w in self.workers:
-            w.join()
+            while w.is_alive():
+                w.join(timeout=1.0)
+                tick()
         errs = [w.error for w in self.workers if w.error is not None]
         if errs:
             raise errs[0]

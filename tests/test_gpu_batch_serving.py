@@ -231,3 +231,33 @@ def test_serving_with_one_shared_budget(env):
             assert oracle_relres(u, t, r.kappa, r.x[i].cpu().numpy(), bs[i].cpu().numpy()) <= 1e-10
     for v in vols:
         v.close()
+
+
+def test_clover_cache_recycles_buffers_without_stale_values(env):
+    """More distinct kappas than the field's 16 cached clover inverses: one SAP call with
+    18 of them, then each kappa alone, must give the same bits (a later kappa of a call
+    never recycles an earlier one's buffer, and a recycled buffer holds the new kappa's
+    inverse); a batch serving 20 kappas in turn, then the first two again, too."""
+    from paper_1502_04025_amd import Batch
+    torch, f = env["torch"], env["f"]
+    kap = [0.1200 + 0.0003 * r for r in range(20)]
+    psi = synthetic.gaussian_source(env["dims"], 18, 37)
+    with torch.cuda.stream(env["stream"]):
+        together = f.sap(np.array(kap[:18]), psi, prec="f16")
+        for r in range(18):
+            alone = f.sap(kap[r], psi[r:r + 1].copy(), prec="f16")
+            assert np.array_equal(alone[0], together[r])
+        b = synthetic.gaussian_source(env["dims"], 1, 38)[0]
+        batch = Batch(f, 1, prec="f16")
+        xs = []
+        for k in kap + kap[:2]:
+            s = batch.add(k, b)
+            while not batch.poll(s)[0]:
+                batch.step()
+            out = np.empty_like(b)
+            assert batch.take(s, out)["converged"]
+            xs.append(out)
+        batch.close()
+    assert np.array_equal(xs[20], xs[0]) and np.array_equal(xs[21], xs[1])
+    assert not np.array_equal(xs[0], xs[1])
+    assert oracle_relres(env["u"], env["t"], kap[19], xs[19], b) <= 1e-10
