@@ -279,6 +279,8 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
     it is in use) and every request draws its bytes from the budget, whatever its volume.
     A closed loop (every request at t = 0) measures the saturation rate; then n_requests
     arrive at each fraction of it. Returns the saturation run and one run per fraction."""
+    import threading
+
     import torch
 
     import synthetic
@@ -299,11 +301,25 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
         workers = [sv.VolumeWorker(v.name, v.batch, v, a, None, None) for v, a in zip(vols, adms)]
         srv = sv.Server(workers)
         budget.peak = budget.used
+        # device memory actually free and held by torch's caching allocator, sampled
+        # while the phase runs (the budget covers the library's slots and fields)
+        mem = dict(free_min=float("inf"), torch_max=0.0)
+        stop = threading.Event()
+
+        def sample():
+            while not stop.wait(0.05):
+                mem["free_min"] = min(mem["free_min"], torch.cuda.mem_get_info()[0])
+                mem["torch_max"] = max(mem["torch_max"], torch.cuda.memory_reserved())
+
+        sampler = threading.Thread(target=sample, daemon=True)
+        sampler.start()
         t0 = time.perf_counter()
         done = srv.run(reqs, realtime=realtime,
                        progress=lambda n, tot: print(f"# serving: {n}/{tot} requests done", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        stop.set()
+        sampler.join()
         out = sv.summarize(done, wall)
         for r in done:  # release the results (the responses) before the next phase
             r.x = None
@@ -312,6 +328,8 @@ def serving_measure(n_requests, fracs, budget_gb, warm=6, max_slots=24):
         out["trims"] = [w.trims for w in workers]
         out["worker_busy_s"] = [{k: round(v, 3) for k, v in w.busy_s.items()} for w in workers]
         out["budget_peak_gb"] = round(budget.peak / 1e9, 2)
+        out["device_free_min_gb"] = round(mem["free_min"] / 1e9, 2)
+        out["torch_reserved_max_gb"] = round(mem["torch_max"] / 1e9, 2)
         out["converged"] = all(all(st["converged"] for st in r.stats) for r in done if r.error is None)
         return out
 

@@ -243,9 +243,13 @@ long long sapdd_batch_memory(const sapdd_batch *batch, long long *slot_bytes);
 long long sapdd_batch_trim(sapdd_batch *batch, int keep);
 /* Admit one right-hand side b (canonical spinor; x0 = start vector or NULL for zero;
  * flags: SAPDD_DEVICE_PTRS). An elastic batch takes a free slot that still holds its
- * memory first and commits a new one only if there is none. Returns SAPDD_EFULL if every
- * slot is taken, SAPDD_ENOMEM if an elastic batch cannot commit the slot's memory
- * (nothing stays committed). */
+ * memory first and commits a new one only if there is none. The call waits for the
+ * device only to check the clover term of a kappa new to the field (singular pivot) and,
+ * with host arrays, for their copy; device arrays are read on the context's stream after
+ * it returns. |b| is read back by the next sapdd_batch_step (for every slot added since,
+ * at once): a zero b finishes there with x = 0, a non-finite one with SAPDD_ENAN at
+ * take. Returns SAPDD_EFULL if every slot is taken, SAPDD_ENOMEM if an elastic batch
+ * cannot commit the slot's memory (nothing stays committed). */
 int sapdd_batch_add(sapdd_batch *batch, double kappa, const double *b, const double *x0, int flags, int *slot);
 /* One restart cycle for every unfinished slot; *running = slots still unfinished. */
 int sapdd_batch_step(sapdd_batch *batch, int *running);

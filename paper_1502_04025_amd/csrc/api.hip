@@ -507,6 +507,17 @@ struct NoallocMeta {
     int n;
 };
 
+__global__ void set_int_kernel(int *p, int v) { *p = v; }
+
+// One slot's clover pointers and kappa for the batch kernels, passed as kernel arguments
+// (no host staging buffer that a later add could overwrite before the copy ran).
+__global__ void slot_meta_kernel(const void **X, const float **Xsc, double *kappa, int r, const void *x,
+                                 const float *xs, double k) {
+    X[r] = x;
+    Xsc[r] = xs;
+    kappa[r] = k;
+}
+
 // Writes the per-rhs clover pointers, kappa and the identity slot list into the scratch
 // memory and clears the singular-pivot flag (a kernel, not a memset).
 __global__ void noalloc_meta_kernel(NoallocMeta m, const void **X, const float **Xsc, double *kappa, int *ident,
@@ -1069,7 +1080,10 @@ namespace {
 typedef std::complex<double> cd;
 
 struct Slot {
-    bool used = false, finished = false, ready = false, dirty = false, in_cycle = false;
+    // pending: added, its |b| not read back yet (the next step does that for every
+    // pending slot at once, so adding a right-hand side waits for nothing)
+    bool used = false, finished = false, ready = false, dirty = false, in_cycle = false, pending = false;
+    bool has_x0 = false;
     double kappa = 0, bnorm = 0, beta = 0, est = 0, true_relres = 0;
     int iters = 0, restarts = 0, converged = 0, nz = 0, status = SAPDD_OK, gap_restarts = 0;
     std::vector<cd> H, cs, sn, gv;  // Hessenberg matrix as the Givens rotations leave it
@@ -1082,7 +1096,7 @@ struct Slot {
     bool deflated = false;
 };
 
-enum { SEG_CHECK = 0, SEG_CHECK2 = 1, SEG_CYCLE = 2, SEG_DEFL = 3, SEG_GROUP = 4, NSEG = 10 };
+enum { SEG_CHECK = 0, SEG_CHECK2 = 1, SEG_CYCLE = 2, SEG_DEFL = 3, SEG_GROUP = 4, SEG_ADD = 5, NSEG = 10 };
 
 }  // namespace
 
@@ -1957,16 +1971,10 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     s.used = true;
     s.kappa = kappa;
     // per-slot clover pointers and kappa for the kernels
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // the pinned mirror may still feed a copy
-    const void **hx = (const void **)B->hmeta;
-    const float **hs = (const float **)(B->hmeta + B->cap * sizeof(void *));
-    double *hk = (double *)(B->hmeta + 2 * B->cap * sizeof(void *));
-    hx[r] = xf.data;
-    hs[r] = xf.scale;
-    hk[r] = kappa;
-    HIPCHK(c, hipMemcpyAsync((void *)(B->ss.X + r), hx + r, sizeof(void *), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync((void *)(B->ss.Xsc + r), hs + r, sizeof(void *), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(B->ss.kappa + r, hk + r, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(slot_meta_kernel, dim3(1), dim3(1), 0, c->stream, (const void **)B->ss.X,
+                       (const float **)B->ss.Xsc, B->ss.kappa, r, (const void *)xf.data, (const float *)xf.scale,
+                       kappa);
+    HIPCHK(c, hipGetLastError());
     // b and x into the device layout
     const double *src;
     CHK(stage_in(c, "stage_in", b, (size_t)B->NS, flags, &src));
@@ -1983,13 +1991,16 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     // with vscale[0] = 1/|b|, and no operator application is needed for it.
     double *v0slot = (double *)B->Vb.data + (size_t)r * (B->m + 1) * B->NS;
     if (!x0) HIPCHK(c, launch_copy(bslot.data, v0slot, (int64_t)B->NS * 8, c->stream));
-    std::vector<int> one(1, r);
-    int *d_one;
-    CHK(upload(B, SEG_CHECK, one, &d_one));
+    // |b|^2 into the slot's coefficient row (and 1/|b| into vscale[0] from a zero start):
+    // the slot list comes from a kernel argument too, one int of the slot's own row of
+    // the list area, so nothing here needs the stream to be idle
+    int *d_one = B->dlists + (size_t)SEG_ADD * B->cap + r;
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, c->stream, d_one, r);
+    HIPCHK(c, hipGetLastError());
     CgsArgs a{};
     a.w = (double *)B->Bb.data;
     a.wstride = B->NS;
-    a.part = B->part;
+    a.part = B->part;  // stream order separates it from the next add's use
     a.active = d_one;
     a.nact = 1;
     a.nv = 0;
@@ -1997,39 +2008,68 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
     KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
     KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, blas_partials(B->ncx, 1), 1, d_one, 1, B->coef + B->noff, B->CST,
                                          nullptr, 0, 0, x0 ? nullptr : B->vscale, B->m + 1, c->stream));
-    CHK(fetch_coef(B));
-    s.bnorm = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
-    if (s.bnorm == 0.0) {
-        HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
-        s.finished = true;
-        s.converged = 1;
-    } else if (!std::isfinite(s.bnorm)) {
-        s.finished = true;
-        s.status = SAPDD_ENAN;
-    } else if (x0) {
-        s.dirty = true;  // its first residual b - M x0 is computed by the next step
-    } else {
-        s.beta = s.bnorm;  // the residual bookkeeping of batch_residual for r = b
-        s.true_relres = 1.0;
-        if (s.true_relres <= B->p.tol) {
-            s.converged = 1;
-            s.finished = true;
-        } else if (s.iters >= B->p.max_iter) {
-            s.status = SAPDD_ENOCONV;
-            s.finished = true;
-        } else {
-            s.ready = true;
-        }
-    }
+    s.pending = true;
+    s.has_x0 = x0 != nullptr;
+    // host arrays may be pinned, and a pinned source is read by the copy after this
+    // call returns: wait for it, so the caller may reuse b and x0 at once
+    if (!(flags & SAPDD_DEVICE_PTRS)) HIPCHK(c, hipStreamSynchronize(c->stream));
     *slot_out = r;
     return SAPDD_OK;
 }
+
+}  // extern "C"
+
+namespace {
+// Read back |b| of every slot added since the last step (one wait for all of them) and
+// set each one's state: finished (b = 0 or not finite), first residual due (x0 given), or
+// ready for its first cycle.
+int resolve_pending(sapdd_batch *B) {
+    bool any = false;
+    for (auto &s : B->slots) any |= s.used && s.pending;
+    if (!any) return SAPDD_OK;
+    sapdd_ctx *c = B->c;
+    CHK(fetch_coef(B));
+    for (int r = 0; r < B->cap; ++r) {
+        Slot &s = B->slots[r];
+        if (!s.used || !s.pending) continue;
+        s.pending = false;
+        double *xslot = (double *)B->Xb.data + (size_t)r * B->NS;
+        s.bnorm = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
+        if (s.bnorm == 0.0) {
+            HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
+            s.finished = true;
+            s.converged = 1;
+        } else if (!std::isfinite(s.bnorm)) {
+            s.finished = true;
+            s.status = SAPDD_ENAN;
+        } else if (s.has_x0) {
+            s.dirty = true;  // its first residual b - M x0 is computed by this step
+        } else {
+            s.beta = s.bnorm;  // the residual bookkeeping of batch_residual for r = b
+            s.true_relres = 1.0;
+            if (s.true_relres <= B->p.tol) {
+                s.converged = 1;
+                s.finished = true;
+            } else if (s.iters >= B->p.max_iter) {
+                s.status = SAPDD_ENOCONV;
+                s.finished = true;
+            } else {
+                s.ready = true;
+            }
+        }
+    }
+    return SAPDD_OK;
+}
+}  // namespace
+
+extern "C" {
 
 int sapdd_batch_step(sapdd_batch *B, int *n_running) {
     if (!B) return SAPDD_EINVAL;
     sapdd_ctx *c = B->c;
     c->err.clear();
     HIPCHK(c, hipSetDevice(c->device));
+    CHK(resolve_pending(B));
     std::vector<int> check;
     for (int r = 0; r < B->cap; ++r)
         if (B->slots[r].used && !B->slots[r].finished && B->slots[r].dirty) check.push_back(r);
