@@ -75,9 +75,16 @@ enum {
                             * rows, the third rebuilt in the kernel (FP32/FP16)  */
     SAPDD_ELASTIC = 16     /* sapdd_batch_create: a slot's device memory is committed
                             * when the slot is first admitted, kept when it is taken
-                            * (the next add reuses it) and released by
+                            * (the next add reuses it) and given back by
                             * sapdd_batch_trim; uncommitted slots cost address
-                            * space only                                          */
+                            * space only. The physical memory comes in chunks of at
+                            * most 64 MiB from a pool the elastic batches of the
+                            * process share per device; trimmed chunks return to it
+                            * and serve any elastic batch's next commit, and the pool
+                            * frees them when the device's last elastic batch is
+                            * destroyed. An elastic batch also allocates at creation
+                            * the field's 16 clover-inverse buffers for its
+                            * precision, so admitting a new kappa allocates nothing */
 };
 
 /* Solver parameters (Sec. 3.1 names the pieces; Sec. 3.7 uses 4-5 MR iterations and
@@ -235,11 +242,11 @@ int sapdd_batch_destroy(sapdd_batch *batch);
  * a NULL batch. */
 long long sapdd_batch_memory(const sapdd_batch *batch, long long *slot_bytes);
 /* SAPDD_ELASTIC: give back the device memory of free slots that still hold it from an
- * earlier use, keeping at most `keep` of them committed (keep = 0 releases all). Waits
- * for the batch's stream first. Returns the bytes released (0 for a batch allocated
- * whole), -1 for a NULL batch or keep < 0, a negative error code if the stream failed.
- * Releasing physical memory is slow on this platform (it can stall for a second under
- * load), so a serving loop trims only when another batch needs the memory. */
+ * earlier use, keeping at most `keep` of them committed (keep = 0 releases all). The
+ * chunks go to the elastic batches' shared pool (above), not to the device: another
+ * elastic batch then commits them without allocating. Waits for the batch's stream
+ * first. Returns the bytes released (0 for a batch allocated whole), -1 for a NULL
+ * batch or keep < 0, a negative error code if the stream failed. */
 long long sapdd_batch_trim(sapdd_batch *batch, int keep);
 /* Admit one right-hand side b (canonical spinor; x0 = start vector or NULL for zero;
  * flags: SAPDD_DEVICE_PTRS). An elastic batch takes a free slot that still holds its

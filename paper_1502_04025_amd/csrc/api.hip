@@ -16,6 +16,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -287,9 +288,36 @@ void free_fld(Fld &x) {
     x = Fld{};
 }
 
+constexpr size_t XCACHE_ENTRIES = 16;
+
+int clover_buffer(sapdd_ctx *c, const Geom &g, int prec, Fld *x) {
+    size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
+    const size_t sc_off = (bytes + 255) / 256 * 256;
+    if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
+    void *p = nullptr;
+    HIPCHK(c, hipMalloc(&p, bytes));
+    *x = Fld{p, prec == P16 ? (float *)((char *)p + sc_off) : nullptr, prec};
+    return SAPDD_OK;
+}
+
+// Allocate now the buffers the field's clover cache can hold in this precision (spares
+// that the next kappas fill), so that admitting a kappa later allocates nothing.
+int reserve_clover_cache(sapdd_ctx *c, sapdd_field *f, int prec) {
+    size_t have = 0;
+    for (auto &e : f->xcache) have += e.prec == prec;
+    for (auto &x : f->xspare) have += x.prec == prec;
+    for (; have < XCACHE_ENTRIES; ++have) {
+        Fld x{};
+        CHK(clover_buffer(c, f->geo, prec, &x));
+        f->xspare.push_back(x);
+    }
+    return SAPDD_OK;
+}
+
 // SAP clover X for (kappa, prec), cached on the field: at most 16 entries. A new kappa
-// recomputes into the buffer of the least recently used unreferenced entry (or of a
-// spare one) rather than freeing it: hipFree waits for the whole device, the other
+// fills a spare buffer (reserve_clover_cache, or one a singular kappa left), else
+// recomputes into the buffer of the least recently used unreferenced entry, rather than
+// freeing one: hipFree waits for the whole device, the other
 // streams' work included, which stalled concurrent serving volumes for the length of
 // their steps. `ref` adds a reference that sap_clover_release drops.
 int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, bool ref = false) {
@@ -300,7 +328,7 @@ int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, b
             *out = e.x;
             return SAPDD_OK;
         }
-    const size_t max_entries = 16;
+    const size_t max_entries = XCACHE_ENTRIES;
     Fld x{};
     for (size_t i = 0; i < f->xspare.size(); ++i)
         if (f->xspare[i].prec == prec) {
@@ -324,14 +352,7 @@ int sap_clover(sapdd_ctx *c, sapdd_field *f, double kappa, int prec, Fld *out, b
         f->xcache.erase(it);
     }
     const Geom &g = f->geo;
-    if (!x.data) {
-        size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
-        const size_t sc_off = (bytes + 255) / 256 * 256;
-        if (prec == P16) bytes = sc_off + (size_t)g.V * sizeof(float);
-        void *p = nullptr;
-        HIPCHK(c, hipMalloc(&p, bytes));
-        x = Fld{p, prec == P16 ? (float *)((char *)p + sc_off) : nullptr, prec};
-    }
+    if (!x.data) CHK(clover_buffer(c, g, prec, &x));
     XEntry e;
     e.kappa = kappa;
     e.prec = prec;
@@ -508,6 +529,21 @@ struct NoallocMeta {
 };
 
 __global__ void set_int_kernel(int *p, int v) { *p = v; }
+
+// Zero n doubles (n even). A kernel rather than hipMemsetAsync: an elastic slot's range
+// spans several mappings, which the runtime's memset rejects.
+__global__ void zero_kernel(double2 *p, int64_t n2) {
+    const double2 z = make_double2(0.0, 0.0);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z;
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t st) {
+    const int64_t n2 = n / 2;
+    const int64_t blocks = std::min<int64_t>((n2 + 255) / 256, 65536);
+    if (blocks > 0) hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (double2 *)p, n2);
+    return hipGetLastError();
+}
 
 // One slot's clover pointers and kappa for the batch kernels, passed as kernel arguments
 // (no host staging buffer that a later add could overwrite before the copy ran).
@@ -1128,10 +1164,16 @@ struct sapdd_batch {
     // Elastic batches (SAPDD_ELASTIC): every per-slot field is one address range of
     // cap slot ranges, each reserved on its own (the runtime takes a second mapping inside
     // one reservation badly) and backed by physical memory only while the slot is in use.
+    struct Piece {  // one reservation, backed by one physical chunk while committed
+        void *va = nullptr;
+        size_t len = 0;
+        hipMemGenericAllocationHandle_t h{};
+        bool full = false;  // a full-size piece (its chunk is pooled on release)
+    };
     struct EField {
         size_t data_per_slot = 0, scale_per_slot = 0;  // bytes; the scales follow all data
-        std::vector<void *> dres, sres;                 // per-slot reservations
-        std::vector<hipMemGenericAllocationHandle_t> dh, sh;
+        int npiece = 0;                                 // pieces per slot: data, then scales
+        std::vector<Piece> pieces;                      // [slot * npiece + k]
         std::vector<char> committed;
     };
     bool elastic = false;
@@ -1164,6 +1206,62 @@ hipMemAllocationProp vmm_prop(int device) {
     return prop;
 }
 
+// Physical memory of the elastic batches of the process, per device: a slot's full-size
+// pieces take their chunks from here when committed and give them back when trimmed, so
+// memory moves between batches without being freed and allocated again (an allocation
+// right after a large free waited up to 2 s on the device, which clears freed memory
+// first). The pool frees its chunks when the device's last elastic batch is destroyed.
+struct PhysPool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<hipMemGenericAllocationHandle_t>> free;
+    std::map<int, int> batches;  // live elastic batches per device
+};
+PhysPool &phys_pool() {
+    static PhysPool p;
+    return p;
+}
+
+void pool_add_batch(int device) {
+    PhysPool &pp = phys_pool();
+    std::lock_guard<std::mutex> g(pp.mu);
+    pp.batches[device] += 1;
+}
+
+void pool_drop_batch(int device) {
+    PhysPool &pp = phys_pool();
+    std::lock_guard<std::mutex> g(pp.mu);
+    if (--pp.batches[device] > 0) return;
+    for (auto it = pp.free.begin(); it != pp.free.end();) {
+        if (it->first.first != device) {
+            ++it;
+            continue;
+        }
+        for (auto h : it->second) (void)hipMemRelease(h);
+        it = pp.free.erase(it);
+    }
+}
+
+// Pieces of at most 64 MiB: full pieces are interchangeable between batches of any
+// lattice, only the last piece of a field has a size of its own. SAPDD_ELASTIC_PIECE_KB
+// in the environment sets another size (tests use small pieces so that small lattices
+// span many).
+size_t piece_bytes() {
+    static const size_t v = [] {
+        const char *e = getenv("SAPDD_ELASTIC_PIECE_KB");
+        const long long kb = e ? atoll(e) : 0;
+        return kb > 0 ? (size_t)kb << 10 : (size_t)64 << 20;
+    }();
+    return v;
+}
+
+size_t full_piece(size_t gran) { return std::max(gran, piece_bytes() / gran * gran); }
+
+void split_pieces(size_t len, size_t gran, std::vector<size_t> &out) {
+    const size_t piece = full_piece(gran);
+    for (; len > piece; len -= piece) out.push_back(piece);
+    if (len) out.push_back(len);
+}
+
 // A per-slot field of nf = cap * per-slot copies: device memory (fixed batch), or in an
 // elastic batch an address range whose slots are committed on admission (commit_slot).
 int bfield(sapdd_batch *B, int nf, int prec, int ncomp, Fld *f) {
@@ -1185,65 +1283,100 @@ int bfield(sapdd_batch *B, int nf, int prec, int ncomp, Fld *f) {
         return fail(B->c, SAPDD_EINVAL,
                     "an elastic batch needs per-slot fields in whole pages of %zu bytes (lattice volume a "
                     "multiple of %zu sites)", B->gran, B->gran / 4);
+    std::vector<size_t> dl, sl;
+    split_pieces(e.data_per_slot, B->gran, dl);
+    split_pieces(e.scale_per_slot, B->gran, sl);
+    e.npiece = (int)(dl.size() + sl.size());
     const size_t total = (size_t)B->cap * (e.data_per_slot + e.scale_per_slot);
-    // find a free range for the whole field, then hold it as cap (or 2 cap) adjacent
-    // per-slot reservations
+    // find a free range for the whole field, then hold it as adjacent reservations, one
+    // per piece (one mapping per reservation: a second mapping inside one reservation
+    // made hipMemSetAccess fail on this runtime)
     void *big = nullptr;
     hipError_t err = hipMemAddressReserve(&big, total, B->gran, nullptr, 0);
     if (err == hipSuccess) err = hipMemAddressFree(big, total);
-    for (int r = 0; err == hipSuccess && r < 2 * B->cap; ++r) {
-        const bool scl = r >= B->cap;
-        if (scl && !e.scale_per_slot) break;
-        const size_t len = scl ? e.scale_per_slot : e.data_per_slot;
-        char *want = (char *)big + (scl ? B->cap * e.data_per_slot + (r - B->cap) * len : r * len);
-        void *got = nullptr;
-        err = hipMemAddressReserve(&got, len, B->gran, want, 0);
-        if (err == hipSuccess) (scl ? e.sres : e.dres).push_back(got);
-        if (err == hipSuccess && got != want) err = hipErrorOutOfMemory;  // the hole was taken meanwhile
+    for (int r = 0; err == hipSuccess && r < B->cap; ++r) {
+        for (int part = 0; part < 2 && err == hipSuccess; ++part) {
+            char *want = (char *)big + (part == 0 ? r * e.data_per_slot
+                                                  : B->cap * e.data_per_slot + r * e.scale_per_slot);
+            for (size_t len : part == 0 ? dl : sl) {
+                void *got = nullptr;
+                err = hipMemAddressReserve(&got, len, B->gran, want, 0);
+                if (err != hipSuccess) break;
+                e.pieces.push_back({got, len, {}, len == full_piece(B->gran)});
+                if (got != want) {  // the hole was taken meanwhile
+                    err = hipErrorOutOfMemory;
+                    break;
+                }
+                want += len;
+            }
+        }
     }
     if (err != hipSuccess) {
         (void)hipGetLastError();
-        for (void *q : e.dres) (void)hipMemAddressFree(q, e.data_per_slot);
-        for (void *q : e.sres) (void)hipMemAddressFree(q, e.scale_per_slot);
+        for (auto &q : e.pieces) (void)hipMemAddressFree(q.va, q.len);
         return fail(B->c, SAPDD_ENOMEM, "reserving %zu bytes of adjacent address space failed: %s", total,
                     hipGetErrorString(err));
     }
-    e.dh.resize(B->cap);
-    e.sh.resize(B->cap);
     e.committed.assign(B->cap, 0);
     B->efields.push_back(std::move(e));
     *f = Fld{big, prec == P16 ? (float *)((char *)big + B->cap * B->efields.back().data_per_slot) : nullptr, prec};
     return SAPDD_OK;
 }
 
-// Back one slot reservation with physical memory readable and writable by the device.
-hipError_t vmm_commit(void *va, size_t len, int device, hipMemGenericAllocationHandle_t *h, const char **what) {
+// Back one piece with a chunk (from the pool, else new) readable and writable by the
+// device.
+hipError_t piece_commit(sapdd_batch::Piece &q, int device, const char **what) {
     const hipMemAllocationProp prop = vmm_prop(device);
     hipMemAccessDesc acc{};
     acc.location = prop.location;
     acc.flags = hipMemAccessFlagsProtReadWrite;
-    *what = "hipMemCreate";
-    hipError_t e = hipMemCreate(h, len, &prop, 0);
-    if (e != hipSuccess) return e;
+    bool pooled = false;
+    {
+        PhysPool &pp = phys_pool();
+        std::lock_guard<std::mutex> g(pp.mu);
+        auto it = pp.free.find({device, q.len});
+        if (it != pp.free.end() && !it->second.empty()) {
+            q.h = it->second.back();
+            it->second.pop_back();
+            pooled = true;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!pooled) {
+        *what = "hipMemCreate";
+        e = hipMemCreate(&q.h, q.len, &prop, 0);
+        if (e != hipSuccess) return e;
+    }
     *what = "hipMemMap";
-    e = hipMemMap(va, len, 0, *h, 0);
+    e = hipMemMap(q.va, q.len, 0, q.h, 0);
     if (e == hipSuccess) {
         *what = "hipMemSetAccess";
-        e = hipMemSetAccess(va, len, &acc, 1);
-        if (e != hipSuccess) (void)hipMemUnmap(va, len);
+        e = hipMemSetAccess(q.va, q.len, &acc, 1);
+        if (e != hipSuccess) (void)hipMemUnmap(q.va, q.len);
     }
-    if (e != hipSuccess) (void)hipMemRelease(*h);
+    if (e != hipSuccess) (void)hipMemRelease(q.h);
     return e;
 }
 
-void vmm_release(sapdd_batch::EField &e, int r) {
-    if (!e.committed[r]) return;
-    (void)hipMemUnmap(e.dres[r], e.data_per_slot);
-    (void)hipMemRelease(e.dh[r]);
-    if (e.scale_per_slot) {
-        (void)hipMemUnmap(e.sres[r], e.scale_per_slot);
-        (void)hipMemRelease(e.sh[r]);
+// Unmap one piece (the stream must be done with it). A full-size chunk goes to the pool,
+// where any elastic batch's next commit finds it before allocating anew, so the memory
+// held by mapped slots and the pool together never exceeds the most the slots had mapped
+// at once. The last piece of a field has a size of its own, fits no other batch's
+// pieces, and is freed (at most 64 MiB, quick to clear).
+void piece_release(sapdd_batch::Piece &q, int device) {
+    (void)hipMemUnmap(q.va, q.len);
+    if (!q.full) {
+        (void)hipMemRelease(q.h);
+        return;
     }
+    PhysPool &pp = phys_pool();
+    std::lock_guard<std::mutex> g(pp.mu);
+    pp.free[{device, q.len}].push_back(q.h);
+}
+
+void vmm_release(sapdd_batch::EField &e, int r, int device) {
+    if (!e.committed[r]) return;
+    for (int k = 0; k < e.npiece; ++k) piece_release(e.pieces[(size_t)r * e.npiece + k], device);
     e.committed[r] = 0;
 }
 
@@ -1255,33 +1388,33 @@ bool slot_committed(const sapdd_batch *B, int r) {
 // A slot that still holds its memory from an earlier use keeps it.
 int commit_slot(sapdd_batch *B, int r) {
     if (!B->elastic || slot_committed(B, r)) return SAPDD_OK;
+    const int dev = B->c->device;
     const char *what = "";
     hipError_t err = hipSuccess;
     size_t i = 0;
     for (; i < B->efields.size(); ++i) {
         sapdd_batch::EField &e = B->efields[i];
-        err = vmm_commit(e.dres[r], e.data_per_slot, B->c->device, &e.dh[r], &what);
-        if (err == hipSuccess && e.scale_per_slot) {
-            err = vmm_commit(e.sres[r], e.scale_per_slot, B->c->device, &e.sh[r], &what);
-            if (err != hipSuccess) {
-                (void)hipMemUnmap(e.dres[r], e.data_per_slot);
-                (void)hipMemRelease(e.dh[r]);
-            }
+        int k = 0;
+        for (; k < e.npiece; ++k)
+            if ((err = piece_commit(e.pieces[(size_t)r * e.npiece + k], dev, &what)) != hipSuccess) break;
+        if (err != hipSuccess) {
+            for (int q = 0; q < k; ++q) piece_release(e.pieces[(size_t)r * e.npiece + q], dev);
+            break;
         }
-        if (err != hipSuccess) break;
         e.committed[r] = 1;
     }
     if (err == hipSuccess) return SAPDD_OK;
     (void)hipGetLastError();
-    for (size_t k = 0; k < i; ++k) vmm_release(B->efields[k], r);
+    for (size_t k = 0; k < i; ++k) vmm_release(B->efields[k], r, dev);
     return fail(B->c, err == hipErrorOutOfMemory ? SAPDD_ENOMEM : SAPDD_EDEVICE,
                 "committing the memory of slot %d failed: %s (%s)", r, hipGetErrorString(err), what);
 }
 
-// Release slot r's memory in every elastic field (the stream must be done with it).
+// Release slot r's memory in every elastic field to the pool (the stream must be done
+// with it).
 void release_slot(sapdd_batch *B, int r) {
     if (!B->elastic) return;
-    for (auto &e : B->efields) vmm_release(e, r);
+    for (auto &e : B->efields) vmm_release(e, r, B->c->device);
 }
 
 int upload(sapdd_batch *B, int seg, const std::vector<int> &v, int **out) {
@@ -1760,10 +1893,10 @@ void batch_free(sapdd_batch *B) {
         if (s.used) sap_clover_release(B->f, s.kappa, lprec(B->prec));
     for (void *q : B->allocs) (void)hipFree(q);
     for (auto &e : B->efields) {
-        for (int r = 0; r < (int)e.committed.size(); ++r) vmm_release(e, r);
-        for (void *q : e.dres) (void)hipMemAddressFree(q, e.data_per_slot);
-        for (void *q : e.sres) (void)hipMemAddressFree(q, e.scale_per_slot);
+        for (int r = 0; r < (int)e.committed.size(); ++r) vmm_release(e, r, B->c->device);
+        for (auto &q : e.pieces) (void)hipMemAddressFree(q.va, q.len);
     }
+    if (B->elastic) pool_drop_batch(B->c->device);
     if (B->pin) (void)hipHostFree(B->pin);
     delete B;
 }
@@ -1838,6 +1971,7 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
             return fail(c, SAPDD_EDEVICE, "elastic batches need virtual memory management: %s", hipGetErrorString(e));
         }
         B->gran = g;
+        pool_add_batch(c->device);  // batch_free drops it again
     }
     B->slots.resize(cap);
     for (auto &s : B->slots) {
@@ -1852,6 +1986,7 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
     const size_t meta_bytes = (size_t)cap * (2 * sizeof(void *) + sizeof(double));
     do {
         if ((r = lo_copies(c, f, lprec(B->prec))) != SAPDD_OK) break;
+        if (B->elastic && (r = reserve_clover_cache(c, f, lprec(B->prec))) != SAPDD_OK) break;
         if ((r = bfield(B, cap * (B->m + 1), P64, 24, &B->Vb)) != SAPDD_OK) break;
         if ((r = bfield(B, cap * B->m, B->zprec, 24, &B->Zb)) != SAPDD_OK) break;
         if ((r = bfield(B, cap, P64, 24, &B->Bb)) != SAPDD_OK) break;
@@ -1985,7 +2120,7 @@ int sapdd_batch_add(sapdd_batch *B, double kappa, const double *b, const double 
         CHK(stage_in(c, "stage_in2", x0, (size_t)B->NS, flags, &src));
         HIPCHK(c, launch_pack(B->g, 24, 1, src, Fld{xslot, nullptr, P64}, c->stream));
     } else {
-        HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
+        HIPCHK(c, launch_zero(xslot, B->NS, c->stream));
     }
     // |b|. From x0 = 0 the first residual is b itself: it goes straight into basis slot 0
     // with vscale[0] = 1/|b|, and no operator application is needed for it.
@@ -2036,7 +2171,7 @@ int resolve_pending(sapdd_batch *B) {
         double *xslot = (double *)B->Xb.data + (size_t)r * B->NS;
         s.bnorm = std::sqrt(B->hcoef[(size_t)r * B->CST + B->noff]);
         if (s.bnorm == 0.0) {
-            HIPCHK(c, hipMemsetAsync(xslot, 0, (size_t)B->NS * 8, c->stream));
+            HIPCHK(c, launch_zero(xslot, B->NS, c->stream));
             s.finished = true;
             s.converged = 1;
         } else if (!std::isfinite(s.bnorm)) {

@@ -14,11 +14,12 @@ clover inverses per volume and a reserve for kernel scratch are set aside first;
 request then draws the bytes its right-hand sides need (the batch's per-slot memory, plus
 the request's sources, solutions and its clover inverse) from what is left, whatever its
 volume. Elastic batches commit a slot's memory on first use and keep it after the slot is
-taken, so the volume's next request reuses it without touching the allocator; releasing
-physical memory is slow (it can stall the device for a second), so a volume gives its
-kept memory back only when another volume is waiting for budget and it has no queued
-request itself (or is stuck waiting too). Memory thereby moves to the volumes that have
-work as the load shifts. A request enters when its volume's batch has free slots and the
+taken, so the volume's next request reuses it without remapping anything. A volume gives
+its kept memory back only when another volume is waiting for budget and it has no queued
+request itself (or is stuck waiting too); the chunks go to the library's pool, from which
+the waiting volume's batch maps them, so memory moves to the volumes that have work as
+the load shifts without being freed and allocated again (a fresh allocation right after
+a large free can stall for seconds while the device clears the freed memory). A request enters when its volume's batch has free slots and the
 budget holds its footprint; one that could never fit is rejected at once. A request
 that fails (a singular clover term, a non-finite residual) or misses the tolerance within
 the iteration cap comes back with its error set, and its slots and bytes are returned.
@@ -75,18 +76,21 @@ class HbmBudget:
         self.used = int(fixed_bytes)
         self.peak = self.used
         self.lock = threading.Lock()
-        self.waiting = set()  # names of the volumes whose next request waits for bytes
+        self.waiting = {}  # volumes whose next request waits for bytes -> bytes it lacks
         self.running = set()  # names of the workers not yet finished
 
-    def set_waiting(self, name: str, on: bool) -> None:
+    def set_waiting(self, name: str, on: bool, short: int = 0) -> None:
         with self.lock:
-            (self.waiting.add if on else self.waiting.discard)(name)
+            if on:
+                self.waiting[name] = int(short)
+            else:
+                self.waiting.pop(name, None)
 
     def set_running(self, name: str, on: bool) -> None:
         with self.lock:
             (self.running.add if on else self.running.discard)(name)
             if not on:
-                self.waiting.discard(name)
+                self.waiting.pop(name, None)
 
     def others_running(self, name: str) -> bool:
         with self.lock:
@@ -98,7 +102,12 @@ class HbmBudget:
 
     def others_waiting(self, name: str) -> bool:
         with self.lock:
-            return bool(self.waiting - {name})
+            return any(k != name for k in self.waiting)
+
+    def others_short(self, name: str) -> int:
+        """The most bytes another waiting volume lacks."""
+        with self.lock:
+            return max((v for k, v in self.waiting.items() if k != name), default=0)
 
     def try_take(self, n: int) -> bool:
         with self.lock:
@@ -187,6 +196,14 @@ class Admission:
         """Free slots whose memory the batch still holds."""
         with self.lock:
             return self.committed - (self.capacity - self.free) if self.warm_bytes else 0
+
+    def short(self, n: int) -> int:
+        """Bytes the budget lacks for n more right-hand sides now."""
+        if self.budget is None:
+            return 0
+        with self.lock:
+            new = max(0, self.capacity - self.free + n - self.committed) if self.warm_bytes else n
+            return max(0, self._cost(n, new) - self.budget.free)
 
     def try_take(self, n: int) -> bool:
         with self.lock:
@@ -292,7 +309,8 @@ class VolumeWorker(threading.Thread):
     def _trim_if_wanted(self):
         """Give the memory of kept slots back to the budget when another volume waits for
         it and this one has no queued request, or is waiting itself with nothing running
-        (kept memory it cannot use now)."""
+        (kept memory it cannot use now): as many slots as cover what the waiting volume
+        lacks, or all of them."""
         budget = self.adm.budget
         if budget is None or not self.adm.warm_bytes or not budget.others_waiting(self.name):
             return
@@ -301,9 +319,11 @@ class VolumeWorker(threading.Thread):
         stuck = not self.active and budget.is_waiting(self.name)
         k = self.adm.kept()
         if k and (idle or stuck):
+            short = budget.others_short(self.name)
+            give = min(k, max(1, -(-short // self.adm.warm_bytes)))
             t0 = time.perf_counter()
-            self.batch.trim(0)
-            self.adm.released(k)
+            self.batch.trim(k - give)
+            self.adm.released(give)
             self.trims += 1
             self.busy_s["trim"] += time.perf_counter() - t0
 
@@ -317,7 +337,8 @@ class VolumeWorker(threading.Thread):
                     return
                 if not self.adm.try_take(self.queue[0].nrhs):
                     if budget is not None:  # waiting for bytes, not for this volume's own slots
-                        budget.set_waiting(self.name, self.adm.free >= self.queue[0].nrhs)
+                        n = self.queue[0].nrhs
+                        budget.set_waiting(self.name, self.adm.free >= n, self.adm.short(n))
                     return
                 if budget is not None:
                     budget.set_waiting(self.name, False)
@@ -424,18 +445,28 @@ class VolumeWorker(threading.Thread):
 
 
 class Server:
-    """Routes a request stream to per-volume workers and records latencies."""
+    """Routes a request stream to per-volume workers and records latencies.
 
-    def __init__(self, workers):
+    on_result(req), if given, receives every finished request's solutions (req.x) as it
+    completes, after which the server lets go of them: a server that kept every answer
+    until the end of a long stream would hold it all in device memory outside the
+    budget (the solutions of 500 requests over the three volumes are ~640 GB). Without
+    on_result the finished requests keep their solutions (tests read them)."""
+
+    def __init__(self, workers, on_result=None):
         self.workers = workers
         self.done = []
         self.lock = threading.Lock()
         self.t0 = None
+        self.on_result = on_result
 
     def clock(self) -> float:
         return time.perf_counter() - self.t0
 
     def _on_done(self, req):
+        if self.on_result is not None:
+            self.on_result(req)
+            req.x = None
         with self.lock:
             self.done.append(req)
 
@@ -539,20 +570,21 @@ class TorchVolume:
     def thread_context(self):
         return self.torch.cuda.stream(self.stream)
 
+    # One tensor per right-hand side, all of one size per volume: torch's caching
+    # allocator then reuses its blocks from request to request instead of keeping blocks
+    # of every request size (which grew its reserve to tens of GB outside the budget).
     def make_source(self, req):
         torch = self.torch
         lx, ly, lz, lt = self.dims
         g = torch.Generator(device="cuda")
         g.manual_seed(int(req.seed))
-        r = torch.randn((req.nrhs, lt, lz, ly, lx, 4, 3, 2), generator=g, dtype=torch.float64, device="cuda")
-        b = torch.view_as_complex(r).contiguous()
-        return [b[i] for i in range(req.nrhs)]
+        return [torch.view_as_complex(torch.randn((lt, lz, ly, lx, 4, 3, 2), generator=g, dtype=torch.float64,
+                                                  device="cuda")) for _ in range(req.nrhs)]
 
     def make_output(self, req):
         torch = self.torch
         lx, ly, lz, lt = self.dims
-        x = torch.empty((req.nrhs, lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device="cuda")
-        return [x[i] for i in range(req.nrhs)]
+        return [torch.empty((lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device="cuda") for _ in range(req.nrhs)]
 
     def close(self):
         self.batch.close()

@@ -261,3 +261,103 @@ def test_clover_cache_recycles_buffers_without_stale_values(env):
     assert np.array_equal(xs[20], xs[0]) and np.array_equal(xs[21], xs[1])
     assert not np.array_equal(xs[0], xs[1])
     assert oracle_relres(env["u"], env["t"], kap[19], xs[19], b) <= 1e-10
+
+
+def test_trimmed_memory_moves_to_another_elastic_batch(env):
+    """Two elastic batches on one field: the first solves, is trimmed (its chunks go to
+    the shared pool) and a second one commits that memory for its own solves; every
+    solution has the bits of a batch allocated whole, and both batches trim to their
+    fixed part."""
+    from paper_1502_04025_amd import Batch
+    torch, f = env["torch"], env["f"]
+    b = synthetic.gaussian_source(env["dims"], 4, 39)
+    kap = [0.121, 0.124, 0.122, 0.125]
+    with torch.cuda.stream(env["stream"]):
+        whole = [f.solve(kap[r], b[r:r + 1].copy(), prec="f16").x[0] for r in range(4)]
+
+        def run(batch, rs):
+            out = {}
+            slots = {r: batch.add(kap[r], b[r]) for r in rs}
+            while any(not batch.poll(s)[0] for s in slots.values()):
+                batch.step()
+            for r, s in slots.items():
+                out[r] = np.empty_like(b[r])
+                assert batch.take(s, out[r])["converged"]
+            return out
+
+        b1 = Batch(f, 2, elastic=True, prec="f16")
+        fixed1 = b1.memory()[0]
+        xs = run(b1, [0, 1])
+        assert b1.trim(0) > 0 and b1.memory()[0] == fixed1
+        b2 = Batch(f, 2, elastic=True, prec="f16")
+        fixed2 = b2.memory()[0]
+        xs.update(run(b2, [2, 3]))
+        xs.update({r + 10: x for r, x in run(b1, [0, 1]).items()})  # b1 commits again, from the pool
+        assert b2.trim(0) > 0 and b1.trim(0) > 0
+        assert b1.memory()[0] == fixed1 and b2.memory()[0] == fixed2
+        b2.close()
+        b1.close()
+    for r in range(4):
+        assert np.array_equal(xs[r], whole[r])
+    assert np.array_equal(xs[10], whole[0]) and np.array_equal(xs[11], whole[1])
+
+
+_SMALL_PIECES = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, {root!r})
+import synthetic
+from paper_1502_04025_amd import Batch, Context
+stream = torch.cuda.Stream()
+ctx = Context(0, stream=stream)
+dims = (8, 8, 8, 8)
+u = synthetic.gauge_field(dims, 0.3, 5)
+b = torch.from_numpy(synthetic.gaussian_source(dims, 3, 40)).cuda()
+kap = [0.121, 0.124, 0.122]
+with torch.cuda.stream(stream):
+    f = ctx.load_gauge(u, (4, 4, 4, 4))
+    f.compute_clover(1.0)
+    whole = Batch(f, 3, prec="f16")
+    el = [Batch(f, 3, elastic=True, prec="f16") for _ in range(2)]
+
+    def run(batch, rs):
+        slots = {{r: batch.add(kap[r], b[r]) for r in rs}}
+        while any(not batch.poll(s)[0] for s in slots.values()):
+            batch.step()
+        out = {{}}
+        for r, s in slots.items():
+            out[r] = torch.empty_like(b[r])
+            assert batch.take(s, out[r])["converged"]
+        torch.cuda.synchronize()
+        return out
+
+    ref = run(whole, [0, 1, 2])
+    got = run(el[0], [0, 1])
+    assert el[0].trim(0) > 0
+    got.update(run(el[1], [2]))
+    again = run(el[0], [0, 1])
+    for r in range(3):
+        assert torch.equal(ref[r], got[r]), r
+    assert torch.equal(again[0], ref[0]) and torch.equal(again[1], ref[1])
+    for x in el + [whole]:
+        x.close()
+    f.free()
+ctx.close()
+print("small pieces ok")
+"""
+
+
+def test_elastic_slots_spanning_many_pieces():
+    """With 64 KiB pieces every slot field of an 8^4 batch spans many mappings (zero
+    fills, packing and the solver kernels cross them): the results keep the bits of a
+    batch allocated whole, also after the memory moved to another batch and back. Runs
+    in its own process, which reads the piece size from the environment."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SAPDD_ELASTIC_PIECE_KB="64")
+    r = subprocess.run([sys.executable, "-c", _SMALL_PIECES.format(root=root)], env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0 and "small pieces ok" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]

@@ -217,6 +217,7 @@ class KeepingBatch(FakeBatch):
         super().__init__(capacity)
         self.committed = set()
         self.commits = 0
+        self.trimmed = []
 
     def add(self, kappa, b):
         free = [s for s in range(self.cap) if s not in self.slots]
@@ -234,6 +235,7 @@ class KeepingBatch(FakeBatch):
         idle = sorted(s for s in self.committed if s not in self.slots)
         for s in idle[keep:]:
             self.committed.discard(s)
+        self.trimmed.append(len(idle[keep:]))
         return 10 * len(idle[keep:])
 
 
@@ -285,3 +287,68 @@ def test_busy_volume_keeps_its_memory_between_requests():
     assert len(done) == 5 and all(r.error is None for r in done)
     assert b.commits == 4 and w.trims == 0
     assert budget.used == 4 * 10 and a.kept() == 4
+
+
+def test_idle_volume_trims_only_what_the_waiting_volume_lacks():
+    """Volume 0 keeps 6 slots (60 bytes of kept memory); volume 1's request of 3 slots
+    lacks 20 bytes of the budget, so volume 0 gives back 2 slots and keeps 4."""
+    budget = sv.HbmBudget(100, fixed_bytes=10)
+    b0, b1 = KeepingBatch(8), KeepingBatch(8)
+    a0 = sv.Admission(8, budget, slot_bytes=10, request_bytes=0, warm_bytes=10)
+    a1 = sv.Admission(8, budget, slot_bytes=10, request_bytes=0, warm_bytes=10)
+    w0 = sv.VolumeWorker("v0", b0, FakeBackend(), a0, lambda: 0.0, lambda r: None)
+    w1 = sv.VolumeWorker("v1", b1, FakeBackend(), a1, lambda: 0.0, lambda r: None)
+    w0.submit(sv.Request(0, 0.0, 0, 0.12, 6, seed=1))
+    w0._admit()
+    while w0.active:
+        w0.batch.step()
+        w0._harvest()
+    assert a0.kept() == 6 and budget.used == 10 + 60
+    w1.submit(sv.Request(1, 0.0, 1, 0.12, 5, seed=2))  # needs 50, 30 free: lacks 20
+    w1._admit()
+    assert [r.id for r in w1.queue] == [1] and budget.waiting == {w1.name: 20}
+    w0._trim_if_wanted()
+    assert b0.trimmed == [2] and a0.kept() == 4 and budget.used == 10 + 40
+    w1._admit()
+    assert [r.id for r in w1.active] == [1] and not budget.waiting
+
+
+class CountingBackend(FakeBackend):
+    """Counts the output arrays alive (made and not yet garbage)."""
+
+    def __init__(self):
+        import weakref
+        self.refs = []
+        self.weakref = weakref
+
+    def make_output(self, req):
+        class Out(list):
+            pass
+        outs = [Out() for _ in range(req.nrhs)]
+        self.refs += [self.weakref.ref(o) for o in outs]
+        return outs
+
+    def alive(self):
+        return sum(r() is not None for r in self.refs)
+
+
+def test_server_hands_results_over_and_lets_go():
+    """With on_result the server passes each finished request's solutions on and drops
+    them, so a long stream holds only the requests in flight; without it they stay."""
+    import gc
+    for keep in (False, True):
+        be = CountingBackend()
+        got = []
+        batch = FakeBatch(3)
+        w = sv.VolumeWorker("v", batch, be, sv.Admission(3), None, None)
+        srv = sv.Server([w], on_result=None if keep else (lambda r: got.append((r.id, [list(o) for o in r.x]))))
+        reqs = [sv.Request(i, 0.0, 0, 0.12, 1 + i % 3, seed=i) for i in range(12)]
+        done = srv.run(reqs, realtime=False)
+        gc.collect()
+        assert len(done) == 12 and all(r.error is None for r in done)
+        if keep:
+            assert be.alive() == sum(r.nrhs for r in reqs) and all(r.x is not None for r in done)
+        else:
+            assert be.alive() == 0 and all(r.x is None for r in done)
+            assert sorted(i for i, _ in got) == list(range(12))
+            assert all(xs[j][0] == 2 * (reqs[i].seed * 10 + j) for i, xs in got for j in range(len(xs)))
