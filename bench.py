@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Benchmark: SAP-preconditioned FGMRES solves on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c5_host_io|c2|c2_f64|c3|c3_f64_1rhs|serve|mg]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c5_f16l|c5_host_io|c2|c2_f64|c3|c3_f64_1rhs|serve|mg]
     python bench.py --sweep          # time to solution over nmr x ncy x domain shape
 
 One step = one complete solve of M x = b for every right-hand side of the workload to a
