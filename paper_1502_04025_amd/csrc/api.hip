@@ -290,6 +290,9 @@ void free_fld(Fld &x) {
 
 constexpr size_t XCACHE_ENTRIES = 16;
 
+// Gram-Schmidt: the second correction is skipped where |c|^2 <= CGS_SKIP_TOL |w'|^2.
+constexpr double CGS_SKIP_TOL = 1e-18;
+
 int clover_buffer(sapdd_ctx *c, const Geom &g, int prec, Fld *x) {
     size_t bytes = (size_t)g.V * 72 * prec_bytes(prec);
     const size_t sc_off = (bytes + 255) / 256 * 256;
@@ -1695,8 +1698,10 @@ int batch_cycle(sapdd_batch *B) {
         KLAUNCH(c, SAPDD_K_DSLASH,
                 launch_dslash_full(B->g, links_of(B->f, P64), tclov_of(B->f, P64), 0.0, w, c->stream));
         HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-        // classical Gram-Schmidt, twice: h = V^H w; w' = w - V h and c = V^H w' in one
-        // pass; w'' = w' - V c and |w''|^2 in one pass
+        // classical Gram-Schmidt, twice: h = V^H w; w' = w - V h, c = V^H w' and |w'|^2 in
+        // one pass; w'' = w' - V c and |w''|^2 in one pass, skipped for a slot whose
+        // correction is negligible, |c| <= 1e-9 |w'| (w'' = w' then, and the Hessenberg
+        // column takes h alone, so M z_j = V h + w'' holds as computed)
         CgsArgs a{};
         a.vbase = Vd;
         a.vstride = B->NS;
@@ -1717,9 +1722,10 @@ int batch_cycle(sapdd_batch *B) {
                                              B->vscale, m + 1, 0, nullptr, 0, c->stream));
         a.coef = B->coef + B->hoff;
         KLAUNCH(c, SAPDD_K_GS, launch_cgs(1, a, c->stream));
-        KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 2 * a.nv, d_cyc, ncyc, B->coef + B->coff, B->CST,
+        KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 2 * a.nv + 1, d_cyc, ncyc, B->coef + B->coff, B->CST,
                                              B->vscale, m + 1, 0, nullptr, 0, c->stream));
         a.coef = B->coef + B->coff;
+        a.skip_tol = CGS_SKIP_TOL;
         KLAUNCH(c, SAPDD_K_GS, launch_cgs(2, a, c->stream));
         KLAUNCH(c, SAPDD_K_GS, launch_reduce(B->part, nwg, 1, d_cyc, ncyc, B->coef + B->noff, B->CST, nullptr, 0, 0,
                                              B->vscale + j + 1, m + 1, c->stream));
@@ -1741,8 +1747,14 @@ int batch_cycle(sapdd_batch *B) {
             Slot &s = B->slots[r];
             const double *hc = B->hcoef + (size_t)r * B->CST;
             cd *hr = &s.Hr[(size_t)(m + 1) * j];
+            // the device's test, on the same numbers: was the second correction skipped?
+            double cc = 0;
             for (int i = 0; i <= j; ++i)
-                hr[i] = cd(hc[B->hoff + 2 * i] + hc[B->coff + 2 * i], hc[B->hoff + 2 * i + 1] + hc[B->coff + 2 * i + 1]);
+                cc += hc[B->coff + 2 * i] * hc[B->coff + 2 * i] + hc[B->coff + 2 * i + 1] * hc[B->coff + 2 * i + 1];
+            const double second = cc <= CGS_SKIP_TOL * hc[B->coff + 2 * (j + 1)] ? 0.0 : 1.0;
+            for (int i = 0; i <= j; ++i)
+                hr[i] = cd(hc[B->hoff + 2 * i] + second * hc[B->coff + 2 * i],
+                           hc[B->hoff + 2 * i + 1] + second * hc[B->coff + 2 * i + 1]);
             const double hn = std::sqrt(std::max(0.0, hc[B->noff]));
             hr[j + 1] = hn;
             if (s.deflated) {  // dense leading block: least squares from scratch
@@ -2002,7 +2014,8 @@ int sapdd_batch_create(sapdd_ctx *c, const sapdd_field *fc, const sapdd_params *
         B->coef = (double *)q;
         if ((r = balloc(B, (size_t)cap * (B->m + 1) * 8, &q)) != SAPDD_OK) break;
         B->vscale = (double *)q;
-        if ((r = balloc(B, (size_t)cap * std::max(B->nwg_d, nwg_b * 32) * 8, &q)) != SAPDD_OK) break;
+        // Gram-Schmidt partials: up to 2 * 16 + 1 values per workgroup and slot
+        if ((r = balloc(B, (size_t)cap * std::max(B->nwg_d, nwg_b * 33) * 8, &q)) != SAPDD_OK) break;
         B->part = (double *)q;
         if ((r = balloc(B, (size_t)cap * 2 * B->m * 8, &q)) != SAPDD_OK) break;
         B->ydev = (double *)q;

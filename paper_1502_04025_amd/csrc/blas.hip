@@ -65,9 +65,25 @@ __device__ __forceinline__ void wg_reduce_store(double (&v)[NVAL], double *out, 
 
 template <int MODE, int NV>
 __global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
-    constexpr int NVAL = MODE == 2 ? 1 : 2 * NV;
+    constexpr int NVAL = MODE == 2 ? 1 : MODE == 1 ? 2 * NV + 1 : 2 * NV;
     const int slot = blockIdx.y;
     const int rhs = a.active[slot];
+    if constexpr (MODE == 2 && NV > 0) {
+        // the second correction of classical Gram-Schmidt twice, where it is negligible:
+        // w keeps the first pass's result and its norm (the same test on every thread,
+        // so the whole workgroup leaves together)
+        if (a.skip_tol > 0) {
+            const double *c = a.coef + (int64_t)rhs * a.cstride;
+            double cc = 0;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) cc += c[2 * (a.v0 + i)] * c[2 * (a.v0 + i)] + c[2 * (a.v0 + i) + 1] * c[2 * (a.v0 + i) + 1];
+            const double wn = c[2 * (a.v0 + NV)];
+            if (cc <= a.skip_tol * wn) {
+                if (threadIdx.x == 0) a.part[(int64_t)slot * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? wn : 0.0;
+                return;
+            }
+        }
+    }
     const double2 *v = (const double2 *)(a.vbase + rhs * a.rstride + (int64_t)a.v0 * a.vstride);
     const int64_t vs = a.vstride / 2;
     double2 *w = (double2 *)(a.w + rhs * a.wstride);
@@ -105,6 +121,7 @@ __global__ __launch_bounds__(BLAS_WG) void cgs_kernel(CgsArgs a) {
                 acc[2 * i] += vv[i].x * ww.x + vv[i].y * ww.y;
                 acc[2 * i + 1] += vv[i].x * ww.y - vv[i].y * ww.x;
             }
+            if (MODE == 1) acc[NVAL - 1] += ww.x * ww.x + ww.y * ww.y;
         } else {
             acc[0] += ww.x * ww.x + ww.y * ww.y;
         }
@@ -139,7 +156,8 @@ hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st) {
 }
 
 // One workgroup per (slot, value): out[rhs * ostride + k] = sum over the nwg partial sums
-// of value k, added in a fixed order (times mul[rhs * mstride + v0 + k / 2] if given);
+// of value k, added in a fixed order (times mul[rhs * mstride + v0 + k / 2] if given,
+// except for the last value of an odd count);
 // for k = 0 also isq[rhs * istride] = 1 / sqrt(sum) if isq is given.
 __global__ __launch_bounds__(BLAS_WG) void reduce_kernel(const double *part, int nwg, int nval, const int *active,
                                                          double *out, int ostride, const double *mul, int mstride,
@@ -158,7 +176,7 @@ __global__ __launch_bounds__(BLAS_WG) void reduce_kernel(const double *part, int
     if (threadIdx.x == 0) {
         double s = 0;
         for (int q = 0; q < BLAS_WG / 64; ++q) s += red[q];
-        if (mul) s *= mul[(int64_t)rhs * mstride + v0 + k / 2];
+        if (mul && k < (nval & ~1)) s *= mul[(int64_t)rhs * mstride + v0 + k / 2];
         out[(int64_t)rhs * ostride + k] = s;
         if (isq && k == 0) isq[(int64_t)rhs * istride] = s > 0 ? 1.0 / sqrt(s) : 0.0;
     }

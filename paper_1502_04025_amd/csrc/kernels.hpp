@@ -110,15 +110,20 @@ struct CgsArgs {
     int nact;
     int v0, nv;          // basis vectors v0 .. v0 + nv - 1 (nv <= 16)
     int64_t n;
+    double skip_tol;     // mode 2: skip the pass where |c|^2 <= skip_tol |w|^2 (see launch_cgs)
 };
 // Workgroups per rhs slot used by the Gram-Schmidt passes.
 int blas_partials(int64_t n, int nact);
-// mode 0: partial <v_i, w>; mode 1: w -= sum_i coef_i s_i v_i, then partial <v_i, w>;
-// mode 2: w -= sum_i coef_i s_i v_i, then partial |w|^2. Coefficient i of the pass is
-// coef[2 (v0 + i)] (re, im).
+// mode 0: partial <v_i, w>; mode 1: w -= sum_i coef_i s_i v_i, then partials <v_i, w>
+// and, as value 2 nv, |w|^2; mode 2: w -= sum_i coef_i s_i v_i, then partial |w|^2.
+// Coefficient i of the pass is coef[2 (v0 + i)] (re, im). Mode 2 with skip_tol > 0 and
+// nv > 0 reads |w|^2 at coef[2 (v0 + nv)] (mode 1's last value): where the correction is
+// negligible, sum |coef_i|^2 <= skip_tol |w|^2, a slot's pass leaves w as it is and its
+// partials sum to that |w|^2 exactly.
 hipError_t launch_cgs(int mode, const CgsArgs &a, hipStream_t st);
 // For every slot: v_k = sum over wg of part[slot][k][wg] (fixed order), times
-// mul[rhs * mstride + v0 + k / 2] if mul is set; written to out[rhs * ostride + k].
+// mul[rhs * mstride + v0 + k / 2] if mul is set (for an odd nval not the last value,
+// which is a norm); written to out[rhs * ostride + k].
 // If isq is set, isq[rhs * istride] = 1 / sqrt(v_0) (0 if v_0 <= 0).
 hipError_t launch_reduce(const double *part, int nwg, int nval, const int *active, int nact, double *out,
                          int ostride, const double *mul, int mstride, int v0, double *isq, int istride,
