@@ -4,7 +4,8 @@
 // Full operator: one thread per (site, right-hand side); neighbours are read straight
 // from global memory. Workgroups are numbered so that the nact right-hand sides of one
 // chunk of sites run back to back on the same XCD (workgroup w runs on XCD w mod 8), so
-// links and clover of the chunk are re-read from that XCD's L2 rather than from HBM.
+// links and clover of the chunk are re-read from that XCD's L2 rather than from HBM, and
+// so that the chunks of one block share an XCD too.
 //
 // Block operator: one workgroup per (block, rhs), the block's spinor staged in LDS and
 // the hops through the block faces masked off.
@@ -46,6 +47,13 @@ template <class BK> struct GeoC {  // geometry with compile-time block extents
 
 constexpr int DSLASH_WG = 256;
 
+// Chunks of DSLASH_WG sites that make up one block (its even half, then its odd half):
+// they go to the same XCD, so the hops between the two halves, most of a site's
+// neighbours, find the other half in that XCD's L2.
+template <class BK> constexpr int full_chunks_per_block() {
+    return 2 * BK::Vbh > DSLASH_WG ? 2 * BK::Vbh / DSLASH_WG : 1;
+}
+
 
 
 template <class BK, class S, class TI, class TO, class R>
@@ -55,11 +63,13 @@ __global__ __launch_bounds__(DSLASH_WG) void dslash_full_kernel(Geom geo, CF<S> 
                                                                  int nchunk, int ins_, int outs_, int subs_,
                                                                  const double *kap) {
     constexpr int Vbh = BK::Vbh;
+    constexpr int G = full_chunks_per_block<BK>();
     const int w = blockIdx.x;
     const int xcd = w & 7;
     const int k = w >> 3;
     const int slot = k % nact;
-    const int chunk = (k / nact) * 8 + xcd;
+    const int q = k / nact;
+    const int chunk = ((q / G) * 8 + xcd) * G + q % G;
     const int rhs = active ? active[slot] : slot;
     const int64_t site = (int64_t)chunk * DSLASH_WG + threadIdx.x;
     const bool valid = chunk < nchunk && site < geo.V;
@@ -159,8 +169,11 @@ template <class BK, class S, class TI, class TO, class R>
 static hipError_t full_typed(const Geom &geo, Fld links, Fld tclov, double kappa, const DslashIO &io,
                              hipStream_t st) {
     const int nchunk = (int)((geo.V + DSLASH_WG - 1) / DSLASH_WG);
-    const int nch8 = (nchunk + 7) / 8 * 8;
-    const int64_t nwg = (int64_t)nch8 * io.nact;
+    constexpr int G = full_chunks_per_block<BK>();
+    // groups of G chunks dealt round-robin to the 8 XCDs; every chunk index below
+    // dslash_full_partials gets a workgroup (those past the lattice write zero partials)
+    const int ng8 = ((nchunk + G - 1) / G + 7) / 8 * 8;
+    const int64_t nwg = (int64_t)ng8 * G * io.nact;
     if (nwg == 0) return hipSuccess;
     if (nwg > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((dslash_full_kernel<BK, S, TI, TO, R>), dim3((unsigned)nwg), dim3(DSLASH_WG), 0, st, geo,
