@@ -49,14 +49,39 @@ template <class S, class SS, class P> struct SapArgs {  // S: links and clover, 
     int colour, mode, write_state, nmr;
 };
 
+// Sum of v over a full wave of 64 lanes in a fixed order, the same on every lane: DPP
+// adds within each row of 16 lanes (lane ^ 1, lane ^ 2, then rotations by 4 and 8, after
+// which every lane holds its row's sum), then the four rows' sums read from lanes 0, 16,
+// 32 and 48. Register-to-register: no LDS round trip per step as with __shfl_xor.
+template <int CTRL> __device__ __forceinline__ float dpp_add(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                     false));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ float wave64_sum(float v) {
+    v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x124>(v);  // row_ror:4
+    v = dpp_add<0x128>(v);  // row_ror:8
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
 // Sum three values over the workgroup in a fixed order; every thread gets the sums.
 template <class BK, class R>
 __device__ __forceinline__ void block_sum3(R &a, R &b, R &c, R *red) {
+    if constexpr (BK::W == 64 && sizeof(R) == 4) {
+        a = wave64_sum(a);
+        b = wave64_sum(b);
+        c = wave64_sum(c);
+    } else {
 #pragma unroll
-    for (int off = BK::W / 2; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, BK::W);
-        b += __shfl_xor(b, off, BK::W);
-        c += __shfl_xor(c, off, BK::W);
+        for (int off = BK::W / 2; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off, BK::W);
+            b += __shfl_xor(b, off, BK::W);
+            c += __shfl_xor(c, off, BK::W);
+        }
     }
     const int wv = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
