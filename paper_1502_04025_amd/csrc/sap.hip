@@ -83,19 +83,31 @@ __device__ __forceinline__ void block_sum3(R &a, R &b, R &c, R *red) {
             c += __shfl_xor(c, off, BK::W);
         }
     }
+    // the waves' sums of one value side by side (red is 16-byte aligned), so that every
+    // thread reads them with a few wide loads, all issued before the first add
+    constexpr int NW = BK::NW;
     const int wv = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
-        red[3 * wv] = a;
-        red[3 * wv + 1] = b;
-        red[3 * wv + 2] = c;
+        red[wv] = a;
+        red[NW + wv] = b;
+        red[2 * NW + wv] = c;
     }
     __syncthreads();
-    a = b = c = 0;
+    R ra[NW], rb[NW], rc[NW];
 #pragma unroll
-    for (int q = 0; q < BK::NW; ++q) {
-        a += red[3 * q];
-        b += red[3 * q + 1];
-        c += red[3 * q + 2];
+    for (int q = 0; q < NW; ++q) {
+        ra[q] = red[q];
+        rb[q] = red[NW + q];
+        rc[q] = red[2 * NW + q];
+    }
+    a = ra[0];
+    b = rb[0];
+    c = rc[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+        a += ra[q];
+        b += rb[q];
+        c += rc[q];
     }
 }
 
@@ -195,7 +207,7 @@ void sap_half_kernel(SapArgs<S, SS, P> a) {
     constexpr int HB = XL ? 1 : 2;
     __shared__ R lds_hop[HopLds<BK, R, HB>::NBUF * HopLds<BK, R, HB>::PER];
     __shared__ S xl[XL ? 72 * Vbh : 1];
-    __shared__ R red[3 * BK::NW];
+    __shared__ __align__(16) R red[3 * BK::NW];
     HopLds<BK, R, HB> lds{lds_hop, 0};
 
     const Geom &geo = a.geo;
@@ -305,8 +317,9 @@ void sap_half_kernel(SapArgs<S, SS, P> a) {
         block_sum3<BK>(pr_re, pr_im, pp, red);
         R ar = 0, ai = 0;
         if (pp > 0) {
-            ar = pr_re / pp;
-            ai = pr_im / pp;
+            const R inv = (R)1 / pp;  // one division for both parts
+            ar = pr_re * inv;
+            ai = pr_im * inv;
         }
         if (even) {
 #pragma unroll
@@ -449,7 +462,7 @@ void sap_pair_kernel(SapArgs<S, SS, P> a) {
     typedef PairBlk<BK> PB;
     // one hop buffer: two workgroups per CU need their LDS to fit twice
     __shared__ R lds_hop[HopLds<BK, R, 1>::PER];
-    __shared__ R red[3 * PB::NW];
+    __shared__ __align__(16) R red[3 * PB::NW];
     HopLds<BK, R, 1> lds{lds_hop, 0};
 
     const Geom &geo = a.geo;
@@ -550,8 +563,9 @@ void sap_pair_kernel(SapArgs<S, SS, P> a) {
         block_sum3<PB>(pr_re, pr_im, pp, red);
         R ar = 0, ai = 0;
         if (pp > 0) {
-            ar = pr_re / pp;
-            ai = pr_im / pp;
+            const R inv = (R)1 / pp;  // one division for both parts
+            ar = pr_re * inv;
+            ai = pr_im * inv;
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
