@@ -381,6 +381,62 @@ template <class BK> struct PairBlk {
     static constexpr int NW = (NT + 63) / 64;
 };
 
+#ifndef SAPDD_SAP_LINK_AHEAD
+#define SAPDD_SAP_LINK_AHEAD 1
+#endif
+
+template <class LK> struct LinkStorage;
+template <class S, class R, bool C> struct LinkStorage<SiteLinks<S, R, C>> {
+    typedef S type;
+};
+
+// The 16-byte vectors that hold link MU of a thread's site, loaded ahead of their use: a
+// load issued after a barrier cannot be hoisted above it by the compiler, and the pull's
+// first link would otherwise wait out its full cache latency right after the barrier.
+template <int MU, class S> struct LinkAhead {
+    typedef typename Vec<S>::type VT;
+    static constexpr int W = Vec<S>::W, V0 = 18 * MU / W, V1 = (18 * MU + 17) / W, N = V1 - V0 + 1;
+    VT x[N];
+    template <class LK> __device__ __forceinline__ void load(const LK &U) {
+        const VT *p = reinterpret_cast<const VT *>(U.base);
+#pragma unroll
+        for (int v = 0; v < N; ++v) x[v] = ld_vec<false>(p + vec_index<S, 72>(U.bp, V0 + v, U.s, U.Vbh));
+    }
+    template <class R> __device__ __forceinline__ void get(R out[18]) const {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            const int q = 18 * MU + k - V0 * W;
+            if constexpr (Storage<S>::scaled) out[k] = (R)(float)x[q / W][q % W];
+            else out[k] = (R)x[q / W][q % W];
+        }
+    }
+};
+
+// pull_dir (branch-free) with the link of direction MU given.
+template <int MU, class BK, class R, class LK, class LA>
+__device__ __forceinline__ void pull_dir_ahead(const SiteInfo &si, const LK &U, const LA &la, R (&out)[24],
+                                               const R *__restrict__ sp, const R *__restrict__ hb) {
+    constexpr int Vbh = BK::Vbh;
+    const bool f = (si.fin >> MU) & 1u, b = (si.bin >> MU) & 1u;
+    {
+        R chi[24], h[12], uh[12], u[18];
+        const int n = si.nbf[MU];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) chi[k] = sp[k * Vbh + n];
+        project<MU, -1>(chi, h);
+        la.get(u);
+        su3_mul(u, h, uh);
+        accum_recon<MU, -1>(out, uh, f ? U.scale() : (R)0);
+    }
+    {
+        R uh[12];
+        const int n = si.nbb[MU];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) uh[k] = hb[(MU * 12 + k) * Vbh + n];
+        accum_recon<MU, +1>(out, uh, b ? (R)1 : (R)0);
+    }
+}
+
 // In-block hop between the parities in pair form: this thread pushes `in` from its site
 // of parity SRC and receives `out` at its site of the other parity. Both SAP kernels take
 // the branch-free directions: they are bound by instruction issue, not by memory.
@@ -394,6 +450,10 @@ __device__ __forceinline__ void pair_hop(const SiteInfo &se, const SiteInfo &so,
     const SiteInfo &sr = SRC == 0 ? so : se;
     const LK &Us = SRC == 0 ? Ue : Uo;
     const LK &Ur = SRC == 0 ? Uo : Ue;
+#if SAPDD_SAP_LINK_AHEAD
+    LinkAhead<0, typename LinkStorage<LK>::type> la;
+    la.load(Ur);
+#endif
 #pragma unroll
     for (int k = 0; k < 24; ++k) sp[k * Vbh + ss.s] = in[k];
     push_dir<0, BK, true>(ss, Us, in, hb);
@@ -403,7 +463,11 @@ __device__ __forceinline__ void pair_hop(const SiteInfo &se, const SiteInfo &so,
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 24; ++k) out[k] = 0;
+#if SAPDD_SAP_LINK_AHEAD
+    pull_dir_ahead<0, BK>(sr, Ur, la, out, sp, hb);
+#else
     pull_dir<0, BK, true>(sr, Ur, out, sp, hb);
+#endif
     pull_dir<1, BK, true>(sr, Ur, out, sp, hb);
     pull_dir<2, BK, true>(sr, Ur, out, sp, hb);
     pull_dir<3, BK, true>(sr, Ur, out, sp, hb);
