@@ -222,14 +222,17 @@ int sapdd_solve(sapdd_ctx *ctx, const sapdd_field *field, const double *kappa,
  * right-hand sides on one field, each with its own kappa and its own FP64 FGMRES(m)
  * state. sapdd_batch_step runs one restart cycle for every unfinished slot: one SAP
  * launch sequence (replayed from a HIP graph captured per slot count and Arnoldi step,
- * unless SAPDD_NO_GRAPH), one operator launch and three Gram-Schmidt passes per Arnoldi
- * step serve the whole batch, and a true FP64 residual at the end of the cycle decides
- * convergence. Right-hand sides join with sapdd_batch_add and leave with
+ * unless SAPDD_NO_GRAPH), one operator launch and the Gram-Schmidt passes per Arnoldi
+ * step serve the whole batch (classical Gram-Schmidt twice; a slot skips the second
+ * correction where its coefficients are below 1e-9 of the corrected vector's norm, and
+ * its Hessenberg column then takes the first pass alone), and a true FP64 residual at
+ * the end of the cycle decides convergence. Right-hand sides join with sapdd_batch_add and leave with
  * sapdd_batch_take between steps. A slot's result does not depend on which other slots
  * share the batch (slots are processed independently, reductions in a fixed order).
  * The batch allocates its device memory at creation (sapdd_solve_footprint bytes for
- * `capacity` RHS, clover inverses per kappa excluded) and uses the context's stream; a
- * batch and its context belong to one host thread at a time. */
+ * `capacity` RHS, clover inverses per kappa excluded; with SAPDD_ELASTIC the slots'
+ * memory only as slots are admitted) and uses the context's stream; a batch and its
+ * context belong to one host thread at a time. */
 int sapdd_batch_create(sapdd_ctx *ctx, const sapdd_field *field, const sapdd_params *params, int capacity,
                        sapdd_batch **out);
 int sapdd_batch_destroy(sapdd_batch *batch);
