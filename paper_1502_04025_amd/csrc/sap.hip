@@ -606,8 +606,12 @@ void sap_pair_kernel(SapArgs<S, SS, P> a) {
     // ---- 3. MR on Dhat = A_e - kappa^2 H_eo A_o^-1 H_oe
     const R k2 = kappa * kappa;
     for (int it = 0; it < a.nmr; ++it) {
-        pair_hop<0, BK>(se, so, Ue, Uo, A, H, lds);  // odd: H = H_oe r
-        Xo.mul(H, T, (R)1);                          // odd: T = A_o^-1 H_oe r
+        // odd: H = H_oe r, then T = A_o^-1 H. The hop's closing barrier comes after the
+        // clover product (which touches no LDS), so a wave done with its pull goes on
+        // to it instead of waiting, and its clover loads are not held behind a barrier.
+        pair_hop<0, BK, false>(se, so, Ue, Uo, A, H, lds);
+        Xo.mul(H, T, (R)1);
+        __syncthreads();
         // even: H = H_eo T; the reduction's barrier below separates these reads from the
         // next hop's writes
         pair_hop<1, BK, false>(se, so, Ue, Uo, T, H, lds);
@@ -643,7 +647,7 @@ void sap_pair_kernel(SapArgs<S, SS, P> a) {
     }
 
     // ---- 4. delta: even B, odd A_o^-1 (rho_o + kappa H_oe delta_e)
-    pair_hop<0, BK>(se, so, Ue, Uo, B, H, lds);
+    pair_hop<0, BK, false>(se, so, Ue, Uo, B, H, lds);  // the last use of LDS: no closing barrier
     fetch<SS, R>(dlt, b, s, Vbh, T);
 #pragma unroll
     for (int k = 0; k < 24; ++k) T[k] = fmac(kappa, H[k], T[k]);
