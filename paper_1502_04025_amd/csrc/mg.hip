@@ -433,14 +433,17 @@ hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double 
 
 // ---------------------------------------------------------------- coarse GMRES
 
-// Workgroup tiling of the coarse kernels. The operator kernel gives every aggregate's K
-// rows eight threads each (one per neighbour group: the aggregate itself and its
-// backward t neighbour, then one neighbour each), 256 threads for 32 / K aggregates, so
-// the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. The
+// Workgroup tiling of the coarse kernels. The operator kernels give every aggregate's K
+// rows sixteen threads each, one per column group: thread g of a row takes columns g,
+// g + 16 of each of the nine blocks (the aggregate and its eight neighbours), at most 18
+// terms, all of whose loads are in flight together. 512 threads cover 32 / K aggregates,
+// so the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. The
 // Gram-Schmidt kernels take 256 / K aggregates per 256-thread workgroup: every one of
 // their workgroups re-sums all partials of the previous kernel, so their count is kept
 // small (their re-reads grow as the product of both counts).
-constexpr int MG_AWG = 256, MG_ALANES = 32, MG_GWG = 256;
+constexpr int MG_AWG = 512, MG_ALANES = 32, MG_AGRP = MG_AWG / MG_ALANES, MG_GWG = 256;
+constexpr int MG_CPG = (2 * MG_NVEC_MAX + MG_AGRP - 1) / MG_AGRP;  // columns per group and block
+static_assert(MG_IMAX <= 2 * MG_AGRP, "the operator kernel's column groups take two basis vectors each");
 void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc) {
     const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
     *nwa = (int)((geo.Nd + ta - 1) / ta);
@@ -462,18 +465,35 @@ __device__ __forceinline__ double wave_sum_parts(const double *part, int n) {
 
 // The totals of nval <= 2 MG_IMAX values (value v's n partials at part + v * pstride)
 // into h[v] in LDS in a fixed order: value v by wave v mod 4 (blockDim.x = 256), whose
-// lane l adds partials l, l + 64, ... (all of the wave's loads in flight together), then
-// one butterfly per value; then a barrier.
+// lane l adds partials l, l + 64, ... (the loads of 256 partials in flight together),
+// then one butterfly per value; then a barrier.
 __device__ __forceinline__ void load_totals(const double *part, int64_t pstride, int n, int nval, double *h) {
     constexpr int NW = MG_GWG / 64, PER = (2 * MG_IMAX + NW - 1) / NW;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) acc[u] = 0.0;
-    for (int q = lane; q < n; q += 64)
+    for (int q0 = 0; q0 < n; q0 += 4 * 64) {
+        // every load unconditional, so that all are in flight together: an index out of
+        // range reads partial 0 of value 0 (written and finite) and adds it times zero,
+        // which leaves the sum's bits unchanged
+        double x[4][PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u)
-            if (w + NW * u < nval) acc[u] += part[(int64_t)(w + NW * u) * pstride + q];
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int q = q0 + 64 * qq + lane;
+                const bool in = q < n && w + NW * u < nval;
+                x[qq][u] = part[(int64_t)(in ? w + NW * u : 0) * pstride + (in ? q : 0)];
+            }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int q = q0 + 64 * qq + lane;
+                acc[u] += x[qq][u] * (q < n && w + NW * u < nval ? 1.0 : 0.0);
+            }
+    }
 #pragma unroll
     for (int u = 0; u < PER; ++u)
         if (w + NW * u < nval) {
@@ -506,6 +526,69 @@ __device__ __forceinline__ double *pn_of(const MgGmres &G, int rhs, int i) {
     return G.pn + ((int64_t)rhs * (MG_IMAX + 1) + i) * G.pstride;
 }
 
+// Thread layout of the operator kernels: column group g (0..MG_AGRP-1) of row a of
+// aggregate b; act: the row exists.
+struct CoarseRow {
+    int g, r, a;
+    int64_t b;
+    bool act;
+    __device__ __forceinline__ CoarseRow(const MgGmres &G) {
+        const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
+        g = threadIdx.x / MG_ALANES;
+        r = threadIdx.x % MG_ALANES;
+        const int bl = r / K;
+        a = r - bl * K;
+        b = (int64_t)blockIdx.x * ta + bl;
+        act = bl < ta && b < G.Nd;
+    }
+};
+
+// This thread's part of row a of (D_c x) for aggregate b: columns g, g + MG_AGRP, ... of
+// the nine blocks in block order, added to (yr, yi). Every load is issued before the
+// sums.
+__device__ __forceinline__ void coarse_row_part(const MgGmres &G, const CoarseRow &w, const float2 *x, double &yr,
+                                                double &yi) {
+    const int K = G.K;
+    int gc[4];
+    block_coords(G.grid, w.b, gc);
+    // all loads first (unconditional, so that none waits for another: a column past K
+    // reads column 0 and is multiplied by zero), then the sums in block and column order
+    float2 m[9][MG_CPG], xv[9][MG_CPG];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        const int64_t nb = mg_neighbour(G.grid, gc, d);
+        const float2 *dcol = G.Dc + ((w.b * 9 + d) * K) * K + w.a;
+        const float2 *xn = x + nb * K;
+#pragma unroll
+        for (int t = 0; t < MG_CPG; ++t) {
+            const int c = w.g + MG_AGRP * t;
+            m[d][t] = dcol[(int64_t)(c < K ? c : 0) * K];
+            xv[d][t] = xn[c < K ? c : 0];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 9; ++d)
+#pragma unroll
+        for (int t = 0; t < MG_CPG; ++t) {
+            const float f = w.g + MG_AGRP * t < K ? 1.f : 0.f;
+            const float mr = m[d][t].x * f, mi = m[d][t].y * f;
+            yr += (double)mr * xv[d][t].x - (double)mi * xv[d][t].y;
+            yi += (double)mr * xv[d][t].y + (double)mi * xv[d][t].x;
+        }
+}
+
+// Row r of D_c x from the column groups' parts in ys (after a barrier), summed in group
+// order.
+__device__ __forceinline__ void coarse_row_total(const double (&ys)[2][MG_AGRP][MG_ALANES], int r, double &yr,
+                                                 double &yi) {
+    yr = yi = 0;
+#pragma unroll
+    for (int q = 0; q < MG_AGRP; ++q) {
+        yr += ys[0][q][r];
+        yi += ys[1][q][r];
+    }
+}
+
 }  // namespace
 
 // |v_0|^2 partials of every listed system (v_0 = the restricted right-hand side).
@@ -524,38 +607,35 @@ __global__ __launch_bounds__(MG_GWG) void mg_cinit_kernel(MgGmres G) {
 }
 
 // Arnoldi step j, pass 0: w = D_c (s_j v_j) into basis slot j + 1 and the partials of
-// <s_i v_i, w>, i <= j. s_j = 1 / |v_j| from the norm partials of v_j.
-__global__ __launch_bounds__(MG_AWG) void mg_capply_kernel(MgGmres G, int j) {
-    __shared__ double ys[2][8][MG_ALANES];
+// <v_i, w>, i <= j (the Gram-Schmidt kernel applies s_i to their totals). s_j = 1 / |v_j|
+// from the norm partials of v_j. Every thread issues its stencil loads and the rows of
+// its two basis vectors (i = g and g + MG_AGRP) at once; after one barrier each thread
+// sums its row of w from the column groups' parts, and each group's two dot products
+// are summed over the 32 rows by a half-wave butterfly.
+__global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void mg_capply_kernel(MgGmres G,
+                                                                                                      int j) {
+    __shared__ double ys[2][MG_AGRP][MG_ALANES];
     __shared__ double hn[1];
     const int rhs = G.active[blockIdx.y];
-    const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
-    const int dg = threadIdx.x / MG_ALANES, r = threadIdx.x % MG_ALANES;
-    const int bl = r / K, a = r - bl * K;
-    const int64_t b = (int64_t)blockIdx.x * ta + bl;
-    const bool act = bl < ta && b < G.Nd;
+    const int K = G.K;
+    const CoarseRow w(G);
     const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
     const float2 *vj = vb + (int64_t)j * G.vstride;
-    float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
-    double yr = 0, yi = 0;  // (D_c v_j) row a of aggregate b, this thread's neighbour group
-    if (act) {
-        int g[4];
-        block_coords(G.grid, b, g);
-        for (int d = dg; d < 9; d += 8) {
-            const int64_t nb = mg_neighbour(G.grid, g, d);
-            const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
-            const float2 *x = vj + nb * K;
-#pragma unroll 8
-            for (int c = 0; c < K; ++c) {
-                const float2 m = dcol[(int64_t)c * K], xv = x[c];
-                yr += (double)m.x * xv.x - (double)m.y * xv.y;
-                yi += (double)m.x * xv.y + (double)m.y * xv.x;
-            }
-        }
+    float2 *wout = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
+    // unconditional loads with clamped indices: for i > j or a missing row they read a
+    // stored row whose products are not kept
+    const int64_t row = w.act ? w.b * K + w.a : 0;
+    float2 v[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = w.g + MG_AGRP * u;
+        v[u] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
     }
-    ys[0][dg][r] = yr;
-    ys[1][dg][r] = yi;
-    if (threadIdx.x < 64) {  // |v_j|^2, while the other waves finish their rows
+    double yr = 0, yi = 0;  // this thread's part of (D_c v_j) row a of aggregate b
+    if (w.act) coarse_row_part(G, w, vj, yr, yi);
+    ys[0][w.g][w.r] = yr;
+    ys[1][w.g][w.r] = yi;
+    if (threadIdx.x < 64) {  // |v_j|^2 (fixed order), alongside the rows
         const double t = wave_sum_parts(pn_of(G, rhs, j), G.nwc);
         if (threadIdx.x == 0) hn[0] = t;
     }
@@ -573,41 +653,39 @@ __global__ __launch_bounds__(MG_AWG) void mg_capply_kernel(MgGmres G, int j) {
             Hc[2 * j + 1] = 0.0;
         }
     }
-    // wave 0 finishes the aggregate(s): its lanes < 32 own the rows, lanes 32..63 add
-    // zeros to the wave sums (every lane of the wave must take part in the shuffles)
-    if (threadIdx.x >= 64) return;
-    const bool own = dg == 0 && act;
-    yr = yi = 0;
-    if (own) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            yr += ys[0][q][r];
-            yi += ys[1][q][r];
-        }
-        yr *= sj;
-        yi *= sj;
-        w[b * K + a] = make_float2((float)yr, (float)yi);
-        yr = (double)(float)yr;  // the dot products see the stored vector
-        yi = (double)(float)yi;
+    coarse_row_total(ys, w.r, yr, yi);
+    yr *= sj;
+    yi *= sj;
+    if (w.act) {
+        const float2 wf = make_float2((float)yr, (float)yi);
+        if (w.g == 0) wout[w.b * K + w.a] = wf;
+        yr = wf.x;  // the dot products see the stored vector
+        yi = wf.y;
+    } else {
+        yr = yi = 0;
     }
-    double acc[2 * MG_IMAX];
 #pragma unroll
-    for (int i = 0; i < MG_IMAX; ++i) {
-        acc[2 * i] = acc[2 * i + 1] = 0.0;
-        if (i <= j && own) {
-            const double si = i == j ? sj : G.sc[(int64_t)rhs * (MG_IMAX + 1) + i];
-            const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
-            acc[2 * i] = si * ((double)v.x * yr + (double)v.y * yi);
-            acc[2 * i + 1] = si * ((double)v.x * yi - (double)v.y * yr);
+    for (int u = 0; u < 2; ++u) {
+        const int i = w.g + MG_AGRP * u;
+        double pr = (double)v[u].x * yr + (double)v[u].y * yi;
+        double pi = (double)v[u].x * yi - (double)v[u].y * yr;
+#pragma unroll
+        for (int off = MG_ALANES / 2; off > 0; off >>= 1) {  // the 32 rows of this group
+            pr += __shfl_xor(pr, off, 64);
+            pi += __shfl_xor(pi, off, 64);
+        }
+        if (w.r == 0 && i <= j) {
+            double *pd = pd_of(G, rhs, 0) + blockIdx.x;
+            pd[(int64_t)(2 * i) * G.pstride] = pr;
+            pd[(int64_t)(2 * i + 1) * G.pstride] = pi;
         }
     }
-    wave_store<2 * MG_IMAX>(acc, 2 * (j + 1), pd_of(G, rhs, 0) + blockIdx.x, G.pstride);
 }
 
-// Arnoldi step j, a correction pass: w -= sum_i h_i s_i v_i with h the totals of the
-// partials of pass `src` (0: the operator kernel's <s_i v_i, w>, 1: a second pass's);
-// then either the partials of <s_i v_i, w> for a further pass (norm = 0) or of |w|^2
-// (norm = 1). Workgroup 0 sets (src 0) or adds (src 1) h into column j of the
+// Arnoldi step j, a correction pass: w -= sum_i h_i s_i v_i with h_i = s_i t_i and t the
+// totals of the partials of pass `src` (0: the operator kernel's <v_i, w>, 1: a second
+// pass's); then either the partials of <v_i, w> for a further pass (norm = 0) or of
+// |w|^2 (norm = 1). Workgroup 0 sets (src 0) or adds (src 1) h into column j of the
 // Hessenberg matrix.
 __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int src, int norm) {
     __shared__ double h[2 * MG_IMAX];
@@ -617,39 +695,41 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int sr
     const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
     const int64_t b = (int64_t)blockIdx.x * tc + bl;
     const bool act = bl < tc && b < G.Nd;
-    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
-    if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
-        double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
-        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x];
-    }
-    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
     float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
-    double yr = 0, yi = 0;
-    if (act) {
-        const float2 w0 = w[b * K + a];
-        yr = w0.x;
-        yi = w0.y;
-#pragma unroll 4
-        for (int i = 0; i <= j; ++i) {
-            const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
-            const double cr = h[2 * i] * sc[i], ci = h[2 * i + 1] * sc[i];
-            yr -= cr * v.x - ci * v.y;
-            yi -= cr * v.y + ci * v.x;
-        }
-        w[b * K + a] = make_float2((float)yr, (float)yi);
-        yr = (double)(float)yr;
-        yi = (double)(float)yi;
+    // this thread's rows of w and of the basis, loaded before the partial sums
+    // (unconditional loads with clamped indices: for i > j or a missing row they read a
+    // stored row that enters with a zero coefficient or is not kept)
+    const int64_t row = act ? b * K + a : 0;
+    const float2 w0 = w[row];
+    float2 vi[MG_IMAX];
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) vi[i] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
+    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
+    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
+        double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
+        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x] * sc[threadIdx.x >> 1];
     }
+    double yr = w0.x, yi = w0.y;
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) {  // the terms i > j are zeros
+        const double si = i <= j ? sc[i] : 0.0;
+        const double cr = i <= j ? h[2 * i] * si * si : 0.0, ci = i <= j ? h[2 * i + 1] * si * si : 0.0;
+        yr -= cr * vi[i].x - ci * vi[i].y;
+        yi -= cr * vi[i].y + ci * vi[i].x;
+    }
+    if (act) w[b * K + a] = make_float2((float)yr, (float)yi);
+    yr = act ? (double)(float)yr : 0.0;
+    yi = act ? (double)(float)yi : 0.0;
     if (!norm) {
         double acc[2 * MG_IMAX];
 #pragma unroll
         for (int i = 0; i < MG_IMAX; ++i) {
             acc[2 * i] = acc[2 * i + 1] = 0.0;
             if (i <= j && act) {
-                const float2 v = vb[(int64_t)i * G.vstride + b * K + a];
-                acc[2 * i] = sc[i] * ((double)v.x * yr + (double)v.y * yi);
-                acc[2 * i + 1] = sc[i] * ((double)v.x * yi - (double)v.y * yr);
+                acc[2 * i] = (double)vi[i].x * yr + (double)vi[i].y * yi;
+                acc[2 * i + 1] = (double)vi[i].x * yi - (double)vi[i].y * yr;
             }
         }
         wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd_of(G, rhs, 1) + blockIdx.x, G.pstride);
@@ -753,48 +833,27 @@ __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
 
 // Start of a restart cycle: v_0 = rc - D_c xc (v_0 = rc on the first cycle, xc = 0).
 // Same tiling as the operator kernel.
-__global__ __launch_bounds__(MG_AWG) void mg_cres_kernel(MgGmres G, int first) {
-    __shared__ double ys[2][8][MG_ALANES];
+__global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void mg_cres_kernel(MgGmres G,
+                                                                                                    int first) {
+    __shared__ double ys[2][MG_AGRP][MG_ALANES];
     const int rhs = G.active[blockIdx.y];
-    const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
-    const int dg = threadIdx.x / MG_ALANES, r = threadIdx.x % MG_ALANES;
-    const int bl = r / K, a = r - bl * K;
-    const int64_t b = (int64_t)blockIdx.x * ta + bl;
-    const bool act = bl < ta && b < G.Nd;
+    const int K = G.K;
+    const CoarseRow w(G);
     const float2 *xc = G.xc + (int64_t)rhs * G.vstride;
-    const float2 rc = act ? G.rc[(int64_t)rhs * G.vstride + b * K + a] : make_float2(0.f, 0.f);
+    const float2 rc = w.act ? G.rc[(int64_t)rhs * G.vstride + w.b * K + w.a] : make_float2(0.f, 0.f);
     float2 *v0 = G.basis + (int64_t)rhs * G.bstride;
     if (first) {
-        if (act && dg == 0) v0[b * K + a] = rc;
+        if (w.act && w.g == 0) v0[w.b * K + w.a] = rc;
         return;
     }
     double yr = 0, yi = 0;
-    if (act) {
-        int g[4];
-        block_coords(G.grid, b, g);
-        for (int d = dg; d < 9; d += 8) {
-            const int64_t nb = mg_neighbour(G.grid, g, d);
-            const float2 *dcol = G.Dc + ((b * 9 + d) * K) * K + a;
-            const float2 *x = xc + nb * K;
-#pragma unroll 8
-            for (int c = 0; c < K; ++c) {
-                const float2 m = dcol[(int64_t)c * K], xv = x[c];
-                yr += (double)m.x * xv.x - (double)m.y * xv.y;
-                yi += (double)m.x * xv.y + (double)m.y * xv.x;
-            }
-        }
-    }
-    ys[0][dg][r] = yr;
-    ys[1][dg][r] = yi;
+    if (w.act) coarse_row_part(G, w, xc, yr, yi);
+    ys[0][w.g][w.r] = yr;
+    ys[1][w.g][w.r] = yi;
     __syncthreads();
-    if (dg != 0 || !act) return;
-    yr = yi = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        yr += ys[0][q][r];
-        yi += ys[1][q][r];
-    }
-    v0[b * K + a] = make_float2((float)(rc.x - yr), (float)(rc.y - yi));
+    if (w.g != 0 || !w.act) return;
+    coarse_row_total(ys, w.r, yr, yi);
+    v0[w.b * K + w.a] = make_float2((float)(rc.x - yr), (float)(rc.y - yi));
 }
 
 // End of a restart cycle: xc = (first ? 0 : xc) + sum_{i < k} coef[i] v_i.
