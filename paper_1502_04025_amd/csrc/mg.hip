@@ -456,8 +456,10 @@ namespace {
 // partials l, l + 64, ..., then a butterfly over the lanes; every lane gets the total.
 __device__ __forceinline__ double wave_sum_parts(const double *part, int n) {
     const int lane = threadIdx.x & 63;
-    double t = 0;
-    for (int q = lane; q < n; q += 64) t += part[q];
+    // partial `lane` by an unconditional load (clamped to partial 0, written and finite,
+    // and multiplied by zero past n), so that it does not wait behind a branch
+    double t = part[lane < n ? lane : 0] * (lane < n ? 1.0 : 0.0);
+    for (int q = lane + 64; q < n; q += 64) t += part[q];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     return t;
@@ -486,6 +488,7 @@ __device__ __forceinline__ void load_totals(const double *part, int64_t pstride,
                 const bool in = q < n && w + NW * u < nval;
                 x[qq][u] = part[(int64_t)(in ? w + NW * u : 0) * pstride + (in ? q : 0)];
             }
+        __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the sums
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
@@ -566,6 +569,7 @@ __device__ __forceinline__ void coarse_row_part(const MgGmres &G, const CoarseRo
             xv[d][t] = xn[c < K ? c : 0];
         }
     }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the sums
 #pragma unroll
     for (int d = 0; d < 9; ++d)
 #pragma unroll
@@ -615,7 +619,6 @@ __global__ __launch_bounds__(MG_GWG) void mg_cinit_kernel(MgGmres G) {
 __global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void mg_capply_kernel(MgGmres G,
                                                                                                       int j) {
     __shared__ double ys[2][MG_AGRP][MG_ALANES];
-    __shared__ double hn[1];
     const int rhs = G.active[blockIdx.y];
     const int K = G.K;
     const CoarseRow w(G);
@@ -631,16 +634,19 @@ __global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) 
         const int i = w.g + MG_AGRP * u;
         v[u] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
     }
+    // |v_j|^2 by every wave (fixed order, as wave_sum_parts): partial `lane` loaded with
+    // the stencil (clamped, times zero past nwc), the rest and the butterfly after it
+    const double *pnj = pn_of(G, rhs, j);
+    const int lane = threadIdx.x & 63;
+    double nj = pnj[lane < G.nwc ? lane : 0] * (lane < G.nwc ? 1.0 : 0.0);
     double yr = 0, yi = 0;  // this thread's part of (D_c v_j) row a of aggregate b
     if (w.act) coarse_row_part(G, w, vj, yr, yi);
     ys[0][w.g][w.r] = yr;
     ys[1][w.g][w.r] = yi;
-    if (threadIdx.x < 64) {  // |v_j|^2 (fixed order), alongside the rows
-        const double t = wave_sum_parts(pn_of(G, rhs, j), G.nwc);
-        if (threadIdx.x == 0) hn[0] = t;
-    }
+    for (int q = lane + 64; q < G.nwc; q += 64) nj += pnj[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
     __syncthreads();
-    const double nj = hn[0];
     const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
@@ -705,16 +711,19 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int sr
     float2 vi[MG_IMAX];
 #pragma unroll
     for (int i = 0; i < MG_IMAX; ++i) vi[i] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
-    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
+    // s_i in lane i of every wave (s_0 .. s_j are written; lanes past j read s_j)
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    const int lane = threadIdx.x & 63;
+    const double s_lane = sc[lane <= j ? lane : j];
+    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
     if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
         double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
-        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x] * sc[threadIdx.x >> 1];
+        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x] * __shfl(s_lane, threadIdx.x >> 1, 64);
     }
     double yr = w0.x, yi = w0.y;
 #pragma unroll
     for (int i = 0; i < MG_IMAX; ++i) {  // the terms i > j are zeros
-        const double si = i <= j ? sc[i] : 0.0;
+        const double si = __shfl(s_lane, i, 64);
         const double cr = i <= j ? h[2 * i] * si * si : 0.0, ci = i <= j ? h[2 * i + 1] * si * si : 0.0;
         yr -= cr * vi[i].x - ci * vi[i].y;
         yi -= cr * vi[i].y + ci * vi[i].x;
@@ -752,15 +761,21 @@ __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
     const double *Hm = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2;
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     double hr[MG_IMAX + 1], hi[MG_IMAX + 1];  // column `lane` of Hbar, rows 0..MG_IMAX
+    // Every load is unconditional and reads an entry this cycle has written (column
+    // col = lane or 0, rows 0..col, and row lane + 1 where it exists); entries outside
+    // the column are then multiplied by zero, so no load waits behind a branch.
+    const int col = lane < k ? lane : 0;
+    const bool sub = lane + 1 < k;  // h_{lane+1,lane} is stored (else it is |w_k|)
+    const double *Hcol = Hm + 2 * (int64_t)col * (MG_IMAX + 1);
+    const double hs = Hcol[2 * (sub ? lane + 1 : col)];
+    const double hk = sqrt(nk > 0 ? nk : 0.0);
 #pragma unroll
     for (int r = 0; r <= MG_IMAX; ++r) {
-        hr[r] = hi[r] = 0.0;
-        if (lane < k && r <= lane) {
-            hr[r] = Hm[2 * (lane * (MG_IMAX + 1) + r)];
-            hi[r] = Hm[2 * (lane * (MG_IMAX + 1) + r) + 1];
-        } else if (lane < k && r == lane + 1) {
-            hr[r] = lane + 1 < k ? Hm[2 * (lane * (MG_IMAX + 1) + r)] : sqrt(nk > 0 ? nk : 0.0);
-        }
+        const int rr = r <= col ? r : col;
+        const double m = lane < k && r <= lane ? 1.0 : 0.0;
+        hr[r] = Hcol[2 * rr] * m;
+        hi[r] = Hcol[2 * rr + 1] * m;
+        if (lane < k && r == lane + 1) hr[r] = hs * (sub ? 1.0 : 0.0) + hk * (sub ? 0.0 : 1.0);
     }
     double gr[MG_IMAX + 1], gi[MG_IMAX + 1];
 #pragma unroll
@@ -779,15 +794,16 @@ __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
                 c = 1.0;
                 sr = si = 0.0;
             } else if (na == 0.0) {
+                const double inb = 1.0 / nb;
                 c = 0.0;
-                sr = br / nb;
-                si = -bi / nb;
+                sr = br * inb;
+                si = -bi * inb;
             } else {
-                const double rr = sqrt(na * na + nb * nb);
-                c = na / rr;
-                const double ur = ar / na, ui = ai / na;  // s = (a / |a|) conj(b) / r
-                sr = (ur * br + ui * bi) / rr;
-                si = (ui * br - ur * bi) / rr;
+                const double irr = 1.0 / sqrt(na * na + nb * nb), ina = 1.0 / na;
+                c = na * irr;
+                const double ur = ar * ina, ui = ai * ina;  // s = (a / |a|) conj(b) / r
+                sr = (ur * br + ui * bi) * irr;
+                si = (ui * br - ur * bi) * irr;
             }
             const double xr = hr[i], xi = hi[i], yr = hr[i + 1], yi = hi[i + 1];
             hr[i] = c * xr + (sr * yr - si * yi);
@@ -818,9 +834,10 @@ __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
             }
             const double dr = __shfl(hr[i], i, 64), di = __shfl(hi[i], i, 64), dd = dr * dr + di * di;
             const double tr = gr[i] - pr, ti = gi[i] - pi;
+            const double idd = dd > 0 ? 1.0 / dd : 0.0;
             if (lane == i) {
-                ylr = dd > 0 ? (tr * dr + ti * di) / dd : 0.0;
-                yli = dd > 0 ? (ti * dr - tr * di) / dd : 0.0;
+                ylr = (tr * dr + ti * di) * idd;
+                yli = (ti * dr - tr * di) * idd;
             }
         }
     }
