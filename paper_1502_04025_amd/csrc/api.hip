@@ -1001,7 +1001,7 @@ namespace {
 
 // Workspace of one multigrid application for `cap` systems (indexed by rhs).
 struct MgWork {
-    int cap = 0, nwa = 0, nwc = 0, pstride = 0;
+    int cap = 0, nwa = 0, pstride = 0;
     double *t1 = nullptr, *t2 = nullptr;  // FP64 fields: interpolated coarse solution, residual
     float2 *cb = nullptr;                 // coarse Krylov bases
     float2 *rc = nullptr, *xc = nullptr;  // coarse right-hand sides and solutions
@@ -1013,14 +1013,14 @@ int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
     const Geom &g = mg->f->geo;
     const size_t nc = (size_t)g.Nd * mg->K;
     w->cap = cap;
-    mg_coarse_tiling(g, mg->K, &w->nwa, &w->nwc);
-    w->pstride = std::max(w->nwa, w->nwc);
+    w->nwa = mg_coarse_tiling(g, mg->K);
+    w->pstride = w->nwa;
     void *q;
     CHK(alloc("mg_t1", (size_t)cap * g.V * 24 * 8, &q));
     w->t1 = (double *)q;
     CHK(alloc("mg_t2", (size_t)cap * g.V * 24 * 8, &q));
     w->t2 = (double *)q;
-    CHK(alloc("mg_cb", (size_t)cap * (MG_IMAX + 1) * nc * sizeof(float2), &q));
+    CHK(alloc("mg_cb", (size_t)cap * MG_BASIS_SLOTS * nc * sizeof(float2), &q));
     w->cb = (float2 *)q;
     CHK(alloc("mg_rc", (size_t)cap * nc * sizeof(float2), &q));
     w->rc = (float2 *)q;
@@ -1049,11 +1049,10 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     for (int mu = 0; mu < 4; ++mu) G.grid[mu] = g.G[mu];
     G.Nd = g.Nd;
     G.nwa = w.nwa;
-    G.nwc = w.nwc;
     G.pstride = w.pstride;
     G.basis = w.cb;
     G.vstride = g.Nd * mg->K;
-    G.bstride = (MG_IMAX + 1) * G.vstride;
+    G.bstride = MG_BASIS_SLOTS * G.vstride;
     G.rc = w.rc;
     G.xc = w.xc;
     G.pn = w.pn;
@@ -1064,7 +1063,6 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     G.coef = w.coef;
     // one classical Gram-Schmidt pass per coarse step: a second pass left the outer step
     // count unchanged on 16^3 x 32 (229 / 230 steps) and cost a quarter of the coarse time
-    G.reorth = 0;
     G.active = active;
     return G;
 }

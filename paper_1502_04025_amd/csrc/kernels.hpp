@@ -181,9 +181,11 @@ struct MgGmres {
     int K;             // 2 nvec
     int grid[4];       // block grid
     int64_t Nd;        // aggregates
-    int nwa, nwc;      // workgroups per system of the operator and Gram-Schmidt kernels
-    int pstride;       // partials stride per value (>= nwa, nwc)
-    float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride
+    int nwa;           // workgroups per system of the coarse kernels (and partials per value)
+    int pstride;       // partials stride per value (>= nwa)
+    float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride, i <= MG_IMAX, then
+                       // the two slots of the unscaled operator products
+
     int64_t bstride, vstride;
     float2 *rc;        // right-hand side(rhs) at rc + rhs * vstride
     float2 *xc;        // solution(rhs) at xc + rhs * vstride
@@ -193,10 +195,10 @@ struct MgGmres {
     double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
     double *beta;      // [rhs] |rhs|
     double *coef;      // [rhs][MG_IMAX] complex: a cycle's correction = sum_i coef[i] basis[i]
-    int reorth;        // 1: classical Gram-Schmidt twice per step, 0: once
     const int *active;
 };
-void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc);
+int mg_coarse_tiling(const Geom &geo, int K);  // workgroups per system of the coarse kernels
+constexpr int MG_BASIS_SLOTS = MG_IMAX + 3;     // coarse vectors per system: basis and products
 // cycles cycles of restarted GMRES(k) from zero on D_c xc = rc for every listed system.
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st);
 // rc(rhs) = in(rhs) rounded to FP32, in complex FP64 at in + rhs * istride.

@@ -17,9 +17,9 @@
 //
 // The coarse system is solved by a fixed number of restarted GMRES cycles of a fixed
 // number of steps, from zero, entirely on the device so the whole preconditioner is one
-// static launch sequence: every Arnoldi step is two kernels (operator + the dot products
-// of classical Gram-Schmidt, then correction + norm; a second Gram-Schmidt pass is
-// available), each reduction a fixed-order sum of per-workgroup partials that every
+// static launch sequence: every Arnoldi step is one kernel (classical Gram-Schmidt
+// correction of the previous step's product, its norm, the operator and the dot products
+// of the next), each reduction a fixed-order sum of per-workgroup partials that every
 // workgroup of the next kernel repeats for itself; one wave per system solves the small
 // least squares problem at the end of a cycle, and the cycle's correction is added to
 // the coarse solution, whose residual starts the next.
@@ -65,28 +65,6 @@ __device__ __forceinline__ void wg_sum(double (&v)[N], double *lds) {
         v[k] = t;
     }
     __syncthreads();
-}
-
-// Sum of the first nval of N doubles over the workgroup, written by threads t < nval to
-// out[t * stride] (partials of one workgroup). lds holds (blockDim.x / 64) * N doubles.
-template <int N>
-__device__ __forceinline__ void wg_sum_store(double (&v)[N], double *lds, int nval, double *out, int64_t stride) {
-    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        if (k < nval)
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-            if (k < nval) lds[w * N + k] = v[k];
-    __syncthreads();
-    if ((int)threadIdx.x < nval) {
-        double t = 0;
-        for (int q = 0; q < nw; ++q) t += lds[q * N + threadIdx.x];
-        out[(int64_t)threadIdx.x * stride] = t;
-    }
 }
 
 // FP64 site component c (complex) of a block-tiled spinor field.
@@ -437,17 +415,14 @@ hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double 
 // rows sixteen threads each, one per column group: thread g of a row takes columns g,
 // g + 16 of each of the nine blocks (the aggregate and its eight neighbours), at most 18
 // terms, all of whose loads are in flight together. 512 threads cover 32 / K aggregates,
-// so the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. The
-// Gram-Schmidt kernels take 256 / K aggregates per 256-thread workgroup: every one of
-// their workgroups re-sums all partials of the previous kernel, so their count is kept
-// small (their re-reads grow as the product of both counts).
-constexpr int MG_AWG = 512, MG_ALANES = 32, MG_AGRP = MG_AWG / MG_ALANES, MG_GWG = 256;
+// so the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. Every
+// workgroup of an Arnoldi step re-sums all partials of the step before.
+constexpr int MG_AWG = 512, MG_ALANES = 32, MG_AGRP = MG_AWG / MG_ALANES;
 constexpr int MG_CPG = (2 * MG_NVEC_MAX + MG_AGRP - 1) / MG_AGRP;  // columns per group and block
 static_assert(MG_IMAX <= 2 * MG_AGRP, "the operator kernel's column groups take two basis vectors each");
-void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc) {
-    const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
-    *nwa = (int)((geo.Nd + ta - 1) / ta);
-    *nwc = (int)((geo.Nd + tc - 1) / tc);
+int mg_coarse_tiling(const Geom &geo, int K) {
+    const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
+    return (int)((geo.Nd + ta - 1) / ta);
 }
 
 namespace {
@@ -456,21 +431,27 @@ namespace {
 // partials l, l + 64, ..., then a butterfly over the lanes; every lane gets the total.
 __device__ __forceinline__ double wave_sum_parts(const double *part, int n) {
     const int lane = threadIdx.x & 63;
-    // partial `lane` by an unconditional load (clamped to partial 0, written and finite,
-    // and multiplied by zero past n), so that it does not wait behind a branch
-    double t = part[lane < n ? lane : 0] * (lane < n ? 1.0 : 0.0);
-    for (int q = lane + 64; q < n; q += 64) t += part[q];
+    // partials lane, lane + 64, lane + 128, lane + 192 by unconditional loads (clamped to
+    // partial 0, written and finite, and multiplied by zero past n), so that none waits
+    // behind a branch; then the rest
+    double x[4], t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = part[lane + 64 * q < n ? lane + 64 * q : 0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t += x[q] * (lane + 64 * q < n ? 1.0 : 0.0);
+    for (int q = lane + 4 * 64; q < n; q += 64) t += part[q];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     return t;
 }
 
 // The totals of nval <= 2 MG_IMAX values (value v's n partials at part + v * pstride)
-// into h[v] in LDS in a fixed order: value v by wave v mod 4 (blockDim.x = 256), whose
+// into h[v] in LDS in a fixed order: value v by wave v mod NW (blockDim.x = 64 NW), whose
 // lane l adds partials l, l + 64, ... (the loads of 256 partials in flight together),
 // then one butterfly per value; then a barrier.
+template <int NW, int NV = 2 * MG_IMAX>
 __device__ __forceinline__ void load_totals(const double *part, int64_t pstride, int n, int nval, double *h) {
-    constexpr int NW = MG_GWG / 64, PER = (2 * MG_IMAX + NW - 1) / NW;
+    constexpr int PER = (NV + NW - 1) / NW;  // nval <= NV
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[PER];
 #pragma unroll
@@ -505,21 +486,6 @@ __device__ __forceinline__ void load_totals(const double *part, int64_t pstride,
             if (lane == 0) h[w + NW * u] = acc[u];
         }
     __syncthreads();
-}
-
-// Wave-level fixed-order sums of N values, written by lane 0 of the wave to
-// out[k * stride] for k < nval.
-template <int N>
-__device__ __forceinline__ void wave_store(double (&v)[N], int nval, double *out, int64_t stride) {
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        if (k < nval)
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-            if (k < nval) out[(int64_t)k * stride] = v[k];
 }
 
 __device__ __forceinline__ double *pd_of(const MgGmres &G, int rhs, int pass) {
@@ -595,156 +561,192 @@ __device__ __forceinline__ void coarse_row_total(const double (&ys)[2][MG_AGRP][
 
 }  // namespace
 
-// |v_0|^2 partials of every listed system (v_0 = the restricted right-hand side).
-__global__ __launch_bounds__(MG_GWG) void mg_cinit_kernel(MgGmres G) {
-    const int rhs = G.active[blockIdx.y];
-    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
-    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
-    const int64_t b = (int64_t)blockIdx.x * tc + bl;
-    __shared__ double lds[MG_GWG / 64];
-    double n[1] = {0.0};
-    if (bl < tc && b < G.Nd) {
-        const float2 x = G.basis[(int64_t)rhs * G.bstride + b * K + a];
-        n[0] = (double)x.x * x.x + (double)x.y * x.y;
-    }
-    wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, 0) + blockIdx.x, 1);
-}
-
-// Arnoldi step j, pass 0: w = D_c (s_j v_j) into basis slot j + 1 and the partials of
-// <v_i, w>, i <= j (the Gram-Schmidt kernel applies s_i to their totals). s_j = 1 / |v_j|
-// from the norm partials of v_j. Every thread issues its stencil loads and the rows of
-// its two basis vectors (i = g and g + MG_AGRP) at once; after one barrier each thread
-// sums its row of w from the column groups' parts, and each group's two dot products
-// are summed over the 32 rows by a half-wave butterfly.
-__global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void mg_capply_kernel(MgGmres G,
-                                                                                                      int j) {
+// Arnoldi step j of a cycle in one launch (classical Gram-Schmidt, one pass). The basis
+// holds v_i (unnormalised, q_i = s_i v_i with s_i = 1 / |v_i|); u_j = D_c v_{j-1} is kept
+// unscaled in one of two slots after the basis. Step j
+//  1. sums the partials of step j - 1 (every workgroup for itself, in a fixed order):
+//     |v_{j-1}|^2, so s_{j-1}, and t_i = <v_i, u_j>, so h_{i,j-1} = s_i s_{j-1} t_i;
+//  2. forms v_j = s_{j-1} u_j - sum_{i<j} h_{i,j-1} s_i v_i (v_0: the cycle's start) at
+//     the rows of every aggregate of the workgroup and of their eight neighbours, into
+//     LDS, and stores its own rows into basis slot j;
+//  3. writes the partials of |v_j|^2 and, unless TAIL, applies the stencil to v_j from
+//     LDS: u_{j+1} = D_c v_j, stored, and the partials of <v_i, u_{j+1}>, i <= j.
+// Workgroup 0 writes s_{j-1}, column j - 1 of the Hessenberg matrix and its entry
+// h_{j-1,j-2} = |v_{j-1}| (beta for j = 1). The TAIL launch (j = k) ends the cycle: it
+// leaves |v_k|^2 in partials for the least-squares kernel. Every load of a thread is
+// issued before its sums (clamped indices; values outside the ranges are multiplied by
+// zero or not kept); JB >= j bounds the basis vectors a step loads.
+template <bool TAIL, int JB>
+__global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 2))) void mg_carnoldi_kernel(MgGmres G,
+                                                                                                       int j) {
+    constexpr int NW = MG_AWG / 64, NE = 9 * MG_ALANES;  // LDS entries: 9 blocks x 32 rows
+    __shared__ float2 xs[NE];
     __shared__ double ys[2][MG_AGRP][MG_ALANES];
+    __shared__ double h[2 * MG_IMAX];
     const int rhs = G.active[blockIdx.y];
-    const int K = G.K;
+    const int K = G.K, ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
+    const int lane = threadIdx.x & 63;
     const CoarseRow w(G);
-    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
-    const float2 *vj = vb + (int64_t)j * G.vstride;
-    float2 *wout = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
-    // unconditional loads with clamped indices: for i > j or a missing row they read a
-    // stored row whose products are not kept
+    float2 *vb = G.basis + (int64_t)rhs * G.bstride;
+    const float2 *uj = vb + (int64_t)(MG_IMAX + 1 + (j & 1)) * G.vstride;
+    float2 *un = vb + (int64_t)(MG_IMAX + 1 + ((j + 1) & 1)) * G.vstride;
+    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    const int jp = j > 0 ? j - 1 : 0;  // the previous step (clamped)
+
+    // ---- loads
+    // entry e of the LDS block: (aggregate bl, neighbour block d, row c)
+    const int e = threadIdx.x;
+    const int ebl = e / (9 * K), erem = e - ebl * 9 * K, ed = erem / K, ec = erem - ed * K;
+    const int64_t eb = (int64_t)blockIdx.x * ta + ebl;
+    const bool eact = e < NE && ebl < ta && eb < G.Nd;
+    int64_t erow = 0;
+    {  // neighbour ed of aggregate eb without indexing the grid by a per-thread direction
+        const int gg[4] = {G.grid[0], G.grid[1], G.grid[2], G.grid[3]};
+        int gc[4], hc[4];
+        block_coords(gg, eact ? eb : 0, gc);
+        const int mu = (ed - 1) >> 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int up = gc[m] + 1 == gg[m] ? 0 : gc[m] + 1, dn = gc[m] == 0 ? gg[m] - 1 : gc[m] - 1;
+            hc[m] = ed > 0 && m == mu ? ((ed & 1) ? up : dn) : gc[m];
+        }
+        erow = eact ? block_index(gg, hc) * K + ec : 0;
+    }
+    const float2 ue = j > 0 ? uj[erow] : vb[erow];  // j = 0: v_0 itself
+    float2 ve[JB];                                    // v_i at the entry, i < j
+#pragma unroll
+    for (int i = 0; i < JB; ++i) ve[i] = vb[(int64_t)(i < j ? i : jp) * G.vstride + erow];
+    const double s_lane = sc[lane < jp ? lane : 0];  // s_i in lane i (i < j - 1 are written)
     const int64_t row = w.act ? w.b * K + w.a : 0;
-    float2 v[2];
+    float2 vo[2];  // own rows of v_i, i = g and g + MG_AGRP (i < j; v_j comes from LDS)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = w.g + MG_AGRP * u;
-        v[u] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
+        vo[u] = vb[(int64_t)(i < j ? i : jp) * G.vstride + row];
     }
-    // |v_j|^2 by every wave (fixed order, as wave_sum_parts): partial `lane` loaded with
-    // the stencil (clamped, times zero past nwc), the rest and the butterfly after it
-    const double *pnj = pn_of(G, rhs, j);
-    const int lane = threadIdx.x & 63;
-    double nj = pnj[lane < G.nwc ? lane : 0] * (lane < G.nwc ? 1.0 : 0.0);
-    double yr = 0, yi = 0;  // this thread's part of (D_c v_j) row a of aggregate b
-    if (w.act) coarse_row_part(G, w, vj, yr, yi);
-    ys[0][w.g][w.r] = yr;
-    ys[1][w.g][w.r] = yi;
-    for (int q = lane + 64; q < G.nwc; q += 64) nj += pnj[q];
+    float2 m[9][MG_CPG];  // this thread's stencil columns (row a of aggregate b)
+    if constexpr (!TAIL) {
+        const int64_t bb = w.act ? w.b : 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
-    __syncthreads();
-    const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
-        const double h = sqrt(nj > 0 ? nj : 0.0);
-        if (j == 0) {
-            G.beta[rhs] = h;
-        } else {  // h_{j,j-1}
+        for (int d = 0; d < 9; ++d)
+#pragma unroll
+            for (int t = 0; t < MG_CPG; ++t) {
+                const int c = w.g + MG_AGRP * t;
+                m[d][t] = G.Dc[((bb * 9 + d) * K + (c < K ? c : 0)) * K + w.a];
+            }
+    }
+    // |v_{j-1}|^2 partials lane, lane + 64, ... (the first four per lane loaded here,
+    // clamped, and added times zero past nwa: the order of wave_sum_parts)
+    const double *pnp = pn_of(G, rhs, jp);
+    double pnr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pnr[q] = pnp[lane + 64 * q < G.nwa ? lane + 64 * q : 0];
+    double np = 0;
+    if (j > 0) {
+        load_totals<NW, 2 * JB>(pd_of(G, rhs, jp & 1), G.pstride, G.nwa, 2 * j, h);  // ends with a barrier
+#pragma unroll
+        for (int q = 0; q < 4; ++q) np += pnr[q] * (lane + 64 * q < G.nwa ? 1.0 : 0.0);
+        for (int q = lane + 4 * 64; q < G.nwa; q += 64) np += pnp[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) np += __shfl_xor(np, off, 64);
+    }
+    // ---- step j - 1's coefficients (the shuffles with every lane of the wave taking part)
+    const double sp = j > 0 && np > 0 ? 1.0 / sqrt(np) : 0.0;  // s_{j-1}
+    const double s_half = __shfl(s_lane, (lane >> 1) & 31, 64);  // s_{lane / 2}
+    double cf[JB];  // h_{i,j-1} s_i / |...| factors: s_i^2 s_{j-1} for i < j, else 0
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+        const double si = i == j - 1 ? sp : __shfl(s_lane, i, 64);
+        cf[i] = i < j ? si * si * sp : 0.0;
+    }
+    if (blockIdx.x == 0 && j > 0) {
+        if (threadIdx.x == 0) {
+            G.sc[(int64_t)rhs * (MG_IMAX + 1) + j - 1] = sp;
+            const double hn = sqrt(np > 0 ? np : 0.0);
+            if (j == 1) {
+                G.beta[rhs] = hn;
+            } else {  // h_{j-1,j-2}
+                double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 2) * (MG_IMAX + 1);
+                Hc[2 * (j - 1)] = hn;
+                Hc[2 * (j - 1) + 1] = 0.0;
+            }
+        }
+        if ((int)threadIdx.x < 2 * j) {  // h_{i,j-1} = s_i s_{j-1} t_i
+            const int i = threadIdx.x >> 1;
+            const double si = i == j - 1 ? sp : s_half;
             double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 1) * (MG_IMAX + 1);
-            Hc[2 * j] = h;
-            Hc[2 * j + 1] = 0.0;
+            Hc[threadIdx.x] = h[threadIdx.x] * si * sp;
         }
     }
-    coarse_row_total(ys, w.r, yr, yi);
-    yr *= sj;
-    yi *= sj;
+    // ---- v_j at the entry: s_{j-1} u_j - sum_i h_{i,j-1} s_i v_i (terms i >= j are zeros)
+    float2 x = ue;
+    if (j > 0) {
+        double yr = sp * ue.x, yi = sp * ue.y;
+#pragma unroll
+        for (int i = 0; i < JB; ++i) {
+            const double cr = i < j ? h[2 * i] * cf[i] : 0.0, ci = i < j ? h[2 * i + 1] * cf[i] : 0.0;
+            yr -= cr * ve[i].x - ci * ve[i].y;
+            yi -= cr * ve[i].y + ci * ve[i].x;
+        }
+        x = make_float2((float)yr, (float)yi);
+    }
+    if (e < NE) xs[e] = x;
+    __syncthreads();
+    // ---- own rows: store v_j (j > 0) and the partials of |v_j|^2 (group 0's 32 rows)
+    const int bl = w.r / K;
+    const float2 vj = w.act ? xs[bl * 9 * K + w.a] : make_float2(0.f, 0.f);
+    if (j > 0 && w.act && w.g == 0) vb[(int64_t)j * G.vstride + w.b * K + w.a] = vj;
+    if (w.g == 0) {
+        double n = (double)vj.x * vj.x + (double)vj.y * vj.y;
+#pragma unroll
+        for (int off = MG_ALANES / 2; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+        if (w.r == 0) pn_of(G, rhs, j)[blockIdx.x] = n;
+    }
+    if constexpr (TAIL) return;
+    // ---- u_{j+1} = D_c v_j from LDS: columns g, g + MG_AGRP of the nine blocks
+    double yr = 0, yi = 0;
     if (w.act) {
-        const float2 wf = make_float2((float)yr, (float)yi);
-        if (w.g == 0) wout[w.b * K + w.a] = wf;
-        yr = wf.x;  // the dot products see the stored vector
-        yi = wf.y;
+#pragma unroll
+        for (int d = 0; d < 9; ++d)
+#pragma unroll
+            for (int t = 0; t < MG_CPG; ++t) {
+                const int c = w.g + MG_AGRP * t;
+                const float f = c < K ? 1.f : 0.f;
+                const float2 xv = xs[(bl * 9 + d) * K + (c < K ? c : 0)];
+                const float mr = m[d][t].x * f, mi = m[d][t].y * f;
+                yr += (double)mr * xv.x - (double)mi * xv.y;
+                yi += (double)mr * xv.y + (double)mi * xv.x;
+            }
+    }
+    ys[0][w.g][w.r] = yr;
+    ys[1][w.g][w.r] = yi;
+    __syncthreads();
+    coarse_row_total(ys, w.r, yr, yi);
+    if (w.act) {
+        const float2 uf = make_float2((float)yr, (float)yi);
+        if (w.g == 0) un[w.b * K + w.a] = uf;
+        yr = uf.x;  // the dot products see the stored vector
+        yi = uf.y;
     } else {
         yr = yi = 0;
     }
+    // ---- partials of <v_i, u_{j+1}>, i <= j: two basis vectors per column group
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = w.g + MG_AGRP * u;
-        double pr = (double)v[u].x * yr + (double)v[u].y * yi;
-        double pi = (double)v[u].x * yi - (double)v[u].y * yr;
+        const float2 v = i == j ? vj : vo[u];
+        double pr = (double)v.x * yr + (double)v.y * yi;
+        double pi = (double)v.x * yi - (double)v.y * yr;
 #pragma unroll
         for (int off = MG_ALANES / 2; off > 0; off >>= 1) {  // the 32 rows of this group
             pr += __shfl_xor(pr, off, 64);
             pi += __shfl_xor(pi, off, 64);
         }
         if (w.r == 0 && i <= j) {
-            double *pd = pd_of(G, rhs, 0) + blockIdx.x;
+            double *pd = pd_of(G, rhs, j & 1) + blockIdx.x;
             pd[(int64_t)(2 * i) * G.pstride] = pr;
             pd[(int64_t)(2 * i + 1) * G.pstride] = pi;
         }
-    }
-}
-
-// Arnoldi step j, a correction pass: w -= sum_i h_i s_i v_i with h_i = s_i t_i and t the
-// totals of the partials of pass `src` (0: the operator kernel's <v_i, w>, 1: a second
-// pass's); then either the partials of <v_i, w> for a further pass (norm = 0) or of
-// |w|^2 (norm = 1). Workgroup 0 sets (src 0) or adds (src 1) h into column j of the
-// Hessenberg matrix.
-__global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int src, int norm) {
-    __shared__ double h[2 * MG_IMAX];
-    __shared__ double lds[(MG_GWG / 64) * 2 * MG_IMAX];
-    const int rhs = G.active[blockIdx.y];
-    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
-    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
-    const int64_t b = (int64_t)blockIdx.x * tc + bl;
-    const bool act = bl < tc && b < G.Nd;
-    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
-    float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
-    // this thread's rows of w and of the basis, loaded before the partial sums
-    // (unconditional loads with clamped indices: for i > j or a missing row they read a
-    // stored row that enters with a zero coefficient or is not kept)
-    const int64_t row = act ? b * K + a : 0;
-    const float2 w0 = w[row];
-    float2 vi[MG_IMAX];
-#pragma unroll
-    for (int i = 0; i < MG_IMAX; ++i) vi[i] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
-    // s_i in lane i of every wave (s_0 .. s_j are written; lanes past j read s_j)
-    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
-    const int lane = threadIdx.x & 63;
-    const double s_lane = sc[lane <= j ? lane : j];
-    load_totals(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
-    if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
-        double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
-        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x] * __shfl(s_lane, threadIdx.x >> 1, 64);
-    }
-    double yr = w0.x, yi = w0.y;
-#pragma unroll
-    for (int i = 0; i < MG_IMAX; ++i) {  // the terms i > j are zeros
-        const double si = __shfl(s_lane, i, 64);
-        const double cr = i <= j ? h[2 * i] * si * si : 0.0, ci = i <= j ? h[2 * i + 1] * si * si : 0.0;
-        yr -= cr * vi[i].x - ci * vi[i].y;
-        yi -= cr * vi[i].y + ci * vi[i].x;
-    }
-    if (act) w[b * K + a] = make_float2((float)yr, (float)yi);
-    yr = act ? (double)(float)yr : 0.0;
-    yi = act ? (double)(float)yi : 0.0;
-    if (!norm) {
-        double acc[2 * MG_IMAX];
-#pragma unroll
-        for (int i = 0; i < MG_IMAX; ++i) {
-            acc[2 * i] = acc[2 * i + 1] = 0.0;
-            if (i <= j && act) {
-                acc[2 * i] = (double)vi[i].x * yr + (double)vi[i].y * yi;
-                acc[2 * i + 1] = (double)vi[i].x * yi - (double)vi[i].y * yr;
-            }
-        }
-        wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd_of(G, rhs, 1) + blockIdx.x, G.pstride);
-    } else {
-        double n[1] = {yr * yr + yi * yi};
-        wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, j + 1) + blockIdx.x, 1);
     }
 }
 
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int sr
 __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
     const int rhs = G.active[blockIdx.x];
     const int lane = threadIdx.x;
-    const double nk = wave_sum_parts(pn_of(G, rhs, k), G.nwc);
+    const double nk = wave_sum_parts(pn_of(G, rhs, k), G.nwa);
     const double *Hm = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2;
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     double hr[MG_IMAX + 1], hi[MG_IMAX + 1];  // column `lane` of Hbar, rows 0..MG_IMAX
@@ -891,24 +893,30 @@ __global__ void mg_caccum_kernel(MgGmres G, int k, int first) {
     *xc = make_float2((float)vr, (float)vi);
 }
 
+// Step j of the Arnoldi kernel (the cycle's tail for j = k) with the smallest bound on
+// the basis vectors it loads.
+static void launch_arnoldi(bool tail, int j, dim3 ga, hipStream_t st, const MgGmres &G) {
+    static_assert(MG_IMAX == 24, "the bounds below cover MG_IMAX steps");
+    if (tail) {
+        if (j <= 8) hipLaunchKernelGGL((mg_carnoldi_kernel<true, 8>), ga, dim3(MG_AWG), 0, st, G, j);
+        else if (j <= 16) hipLaunchKernelGGL((mg_carnoldi_kernel<true, 16>), ga, dim3(MG_AWG), 0, st, G, j);
+        else hipLaunchKernelGGL((mg_carnoldi_kernel<true, 24>), ga, dim3(MG_AWG), 0, st, G, j);
+    } else {
+        if (j <= 8) hipLaunchKernelGGL((mg_carnoldi_kernel<false, 8>), ga, dim3(MG_AWG), 0, st, G, j);
+        else if (j <= 16) hipLaunchKernelGGL((mg_carnoldi_kernel<false, 16>), ga, dim3(MG_AWG), 0, st, G, j);
+        else hipLaunchKernelGGL((mg_carnoldi_kernel<false, 24>), ga, dim3(MG_AWG), 0, st, G, j);
+    }
+}
+
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st) {
     if (nact <= 0) return hipSuccess;
     if (k < 1 || k > MG_IMAX || cycles < 1 || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
-    const dim3 ga((unsigned)G.nwa, (unsigned)nact), gc((unsigned)G.nwc, (unsigned)nact);
+    const dim3 ga((unsigned)G.nwa, (unsigned)nact);
     const int64_t n = G.Nd * G.K;
     const dim3 ge((unsigned)((n + 255) / 256), (unsigned)nact);
     for (int cyc = 0; cyc < cycles; ++cyc) {
         hipLaunchKernelGGL(mg_cres_kernel, ga, dim3(MG_AWG), 0, st, G, (int)(cyc == 0));
-        hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
-        for (int j = 0; j < k; ++j) {
-            hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
-            if (G.reorth) {  // classical Gram-Schmidt twice
-                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 0, 0);
-                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 1, 1);
-            } else {  // once
-                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 0, 1);
-            }
-        }
+        for (int j = 0; j <= k; ++j) launch_arnoldi(j == k, j, ga, st, G);
         hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
         hipLaunchKernelGGL(mg_caccum_kernel, ge, dim3(256), 0, st, G, k, (int)(cyc == 0));
     }
