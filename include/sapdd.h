@@ -296,6 +296,11 @@ typedef struct {
     int setup_iters;  /* smoothing passes per test vector before P is built (>= 0)     */
     int coarse_iters; /* GMRES steps per coarse restart cycle (1..24)                  */
     int coarse_cycles;/* restart cycles of every coarse solve (0..64; 0 = 1)           */
+    int coarse_form;  /* 0: two kernel launches per coarse Arnoldi step (for batches of  */
+                      /* systems), 1: one launch per step, each workgroup correcting the  */
+                      /* rows it applies the stencil to (for a single system). Both run   */
+                      /* classical Gram-Schmidt; results agree to rounding. Fixed per     */
+                      /* object, so a system gets the same bits alone and in any batch.   */
 } sapdd_mg_params;
 /* Build P and D_c for (field, kappa). vecs: nvec canonical spinors (flags:
  * SAPDD_DEVICE_PTRS). smoother supplies nmr, ncy and sap_prec of the smoothing passes

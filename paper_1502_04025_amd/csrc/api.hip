@@ -1001,7 +1001,7 @@ namespace {
 
 // Workspace of one multigrid application for `cap` systems (indexed by rhs).
 struct MgWork {
-    int cap = 0, nwa = 0, pstride = 0;
+    int cap = 0, nwa = 0, nwc = 0, pstride = 0;
     double *t1 = nullptr, *t2 = nullptr;  // FP64 fields: interpolated coarse solution, residual
     float2 *cb = nullptr;                 // coarse Krylov bases
     float2 *rc = nullptr, *xc = nullptr;  // coarse right-hand sides and solutions
@@ -1013,8 +1013,8 @@ int mg_work_init(const sapdd_mg *mg, int cap, Alloc alloc, MgWork *w) {
     const Geom &g = mg->f->geo;
     const size_t nc = (size_t)g.Nd * mg->K;
     w->cap = cap;
-    w->nwa = mg_coarse_tiling(g, mg->K);
-    w->pstride = w->nwa;
+    mg_coarse_tiling(g, mg->K, &w->nwa, &w->nwc);
+    w->pstride = std::max(w->nwa, w->nwc);
     void *q;
     CHK(alloc("mg_t1", (size_t)cap * g.V * 24 * 8, &q));
     w->t1 = (double *)q;
@@ -1049,10 +1049,12 @@ MgGmres mg_gmres(const sapdd_mg *mg, const MgWork &w, const int *active) {
     for (int mu = 0; mu < 4; ++mu) G.grid[mu] = g.G[mu];
     G.Nd = g.Nd;
     G.nwa = w.nwa;
+    G.nwc = w.nwc;
     G.pstride = w.pstride;
     G.basis = w.cb;
     G.vstride = g.Nd * mg->K;
     G.bstride = MG_BASIS_SLOTS * G.vstride;
+    G.fused = mg->mp.coarse_form;
     G.rc = w.rc;
     G.xc = w.xc;
     G.pn = w.pn;
@@ -2470,6 +2472,7 @@ int sapdd_mg_setup(sapdd_ctx *c, sapdd_field *f, double kappa, const sapdd_param
         return fail(c, SAPDD_EINVAL, "coarse_iters must be in 1..%d", MG_IMAX);
     if (mgp->setup_iters < 0 || mgp->coarse_cycles < 0 || mgp->coarse_cycles > 64)
         return fail(c, SAPDD_EINVAL, "setup_iters must be >= 0 and coarse_cycles in 0..64");
+    if (mgp->coarse_form != 0 && mgp->coarse_form != 1) return fail(c, SAPDD_EINVAL, "coarse_form must be 0 or 1");
     const Geom &g = f->geo;
     if (g.Vb > 512) return fail(c, SAPDD_EINVAL, "multigrid aggregates (Schwarz blocks) must have <= 512 sites");
     if ((int64_t)mgp->coarse_iters > g.Nd * 2 * mgp->nvec)

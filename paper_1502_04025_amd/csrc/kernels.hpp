@@ -181,8 +181,8 @@ struct MgGmres {
     int K;             // 2 nvec
     int grid[4];       // block grid
     int64_t Nd;        // aggregates
-    int nwa;           // workgroups per system of the coarse kernels (and partials per value)
-    int pstride;       // partials stride per value (>= nwa)
+    int nwa, nwc;      // workgroups per system of the operator and Gram-Schmidt kernels
+    int pstride;       // partials stride per value (>= nwa, nwc)
     float2 *basis;     // basis(rhs)[i] at basis + rhs * bstride + i * vstride, i <= MG_IMAX, then
                        // the two slots of the unscaled operator products
 
@@ -195,9 +195,10 @@ struct MgGmres {
     double *sc;        // [rhs][MG_IMAX + 1] 1 / |v_i|
     double *beta;      // [rhs] |rhs|
     double *coef;      // [rhs][MG_IMAX] complex: a cycle's correction = sum_i coef[i] basis[i]
+    int fused;         // 1: one launch per Arnoldi step, 0: two
     const int *active;
 };
-int mg_coarse_tiling(const Geom &geo, int K);  // workgroups per system of the coarse kernels
+void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc);
 constexpr int MG_BASIS_SLOTS = MG_IMAX + 3;     // coarse vectors per system: basis and products
 // cycles cycles of restarted GMRES(k) from zero on D_c xc = rc for every listed system.
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st);

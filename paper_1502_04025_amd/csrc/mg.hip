@@ -17,10 +17,13 @@
 //
 // The coarse system is solved by a fixed number of restarted GMRES cycles of a fixed
 // number of steps, from zero, entirely on the device so the whole preconditioner is one
-// static launch sequence: every Arnoldi step is one kernel (classical Gram-Schmidt
-// correction of the previous step's product, its norm, the operator and the dot products
-// of the next), each reduction a fixed-order sum of per-workgroup partials that every
-// workgroup of the next kernel repeats for itself; one wave per system solves the small
+// static launch sequence. Classical Gram-Schmidt, in one of two forms chosen when the
+// multigrid is set up: every Arnoldi step two kernels (operator + the dot products, then
+// correction + norm), which suits batches of systems, or one kernel (correction of the
+// previous step's product at the rows it needs, its norm, the operator and the dot
+// products of the next), which suits a single system. Each reduction is a fixed-order
+// sum of per-workgroup partials that every workgroup of the next kernel repeats for
+// itself; one wave per system solves the small
 // least squares problem at the end of a cycle, and the cycle's correction is added to
 // the coarse solution, whose residual starts the next.
 #include "kernels.hpp"
@@ -65,6 +68,28 @@ __device__ __forceinline__ void wg_sum(double (&v)[N], double *lds) {
         v[k] = t;
     }
     __syncthreads();
+}
+
+// Sum of the first nval of N doubles over the workgroup, written by threads t < nval to
+// out[t * stride] (partials of one workgroup). lds holds (blockDim.x / 64) * N doubles.
+template <int N>
+__device__ __forceinline__ void wg_sum_store(double (&v)[N], double *lds, int nval, double *out, int64_t stride) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k < nval)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k < nval) lds[w * N + k] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < nval) {
+        double t = 0;
+        for (int q = 0; q < nw; ++q) t += lds[q * N + threadIdx.x];
+        out[(int64_t)threadIdx.x * stride] = t;
+    }
 }
 
 // FP64 site component c (complex) of a block-tiled spinor field.
@@ -415,14 +440,17 @@ hipError_t launch_mg_axpy(const Geom &geo, Fld y, int64_t ystride, const double 
 // rows sixteen threads each, one per column group: thread g of a row takes columns g,
 // g + 16 of each of the nine blocks (the aggregate and its eight neighbours), at most 18
 // terms, all of whose loads are in flight together. 512 threads cover 32 / K aggregates,
-// so the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. Every
-// workgroup of an Arnoldi step re-sums all partials of the step before.
-constexpr int MG_AWG = 512, MG_ALANES = 32, MG_AGRP = MG_AWG / MG_ALANES;
+// so the stencil (18 MB on a 16^3 x 32 lattice with K = 32) streams from many CUs. The
+// Gram-Schmidt kernels of the two-launch form take 256 / K aggregates per 256-thread
+// workgroup: every one of their workgroups re-sums all partials of the previous kernel,
+// so their count is kept small (their re-reads grow as the product of both counts).
+constexpr int MG_AWG = 512, MG_ALANES = 32, MG_AGRP = MG_AWG / MG_ALANES, MG_GWG = 256;
 constexpr int MG_CPG = (2 * MG_NVEC_MAX + MG_AGRP - 1) / MG_AGRP;  // columns per group and block
 static_assert(MG_IMAX <= 2 * MG_AGRP, "the operator kernel's column groups take two basis vectors each");
-int mg_coarse_tiling(const Geom &geo, int K) {
-    const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1;
-    return (int)((geo.Nd + ta - 1) / ta);
+void mg_coarse_tiling(const Geom &geo, int K, int *nwa, int *nwc) {
+    const int ta = MG_ALANES / K > 0 ? MG_ALANES / K : 1, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    *nwa = (int)((geo.Nd + ta - 1) / ta);
+    *nwc = (int)((geo.Nd + tc - 1) / tc);
 }
 
 namespace {
@@ -560,6 +588,159 @@ __device__ __forceinline__ void coarse_row_total(const double (&ys)[2][MG_AGRP][
 }
 
 }  // namespace
+
+// |v_0|^2 partials of every listed system (v_0 = the restricted right-hand side).
+__global__ __launch_bounds__(MG_GWG) void mg_cinit_kernel(MgGmres G) {
+    const int rhs = G.active[blockIdx.y];
+    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * tc + bl;
+    __shared__ double lds[MG_GWG / 64];
+    double n[1] = {0.0};
+    if (bl < tc && b < G.Nd) {
+        const float2 x = G.basis[(int64_t)rhs * G.bstride + b * K + a];
+        n[0] = (double)x.x * x.x + (double)x.y * x.y;
+    }
+    wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, 0) + blockIdx.x, 1);
+}
+
+// Arnoldi step j, pass 0: w = D_c (s_j v_j) into basis slot j + 1 and the partials of
+// <v_i, w>, i <= j (the Gram-Schmidt kernel applies s_i to their totals). s_j = 1 / |v_j|
+// from the norm partials of v_j. Every thread issues its stencil loads and the rows of
+// its two basis vectors (i = g and g + MG_AGRP) at once; after one barrier each thread
+// sums its row of w from the column groups' parts, and each group's two dot products
+// are summed over the 32 rows by a half-wave butterfly.
+__global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 4))) void mg_capply_kernel(MgGmres G,
+                                                                                                      int j) {
+    __shared__ double ys[2][MG_AGRP][MG_ALANES];
+    const int rhs = G.active[blockIdx.y];
+    const int K = G.K;
+    const CoarseRow w(G);
+    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
+    const float2 *vj = vb + (int64_t)j * G.vstride;
+    float2 *wout = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
+    // unconditional loads with clamped indices: for i > j or a missing row they read a
+    // stored row whose products are not kept
+    const int64_t row = w.act ? w.b * K + w.a : 0;
+    float2 v[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = w.g + MG_AGRP * u;
+        v[u] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
+    }
+    // |v_j|^2 by every wave (fixed order, as wave_sum_parts): partial `lane` loaded with
+    // the stencil (clamped, times zero past nwc), the rest and the butterfly after it
+    const double *pnj = pn_of(G, rhs, j);
+    const int lane = threadIdx.x & 63;
+    double nj = pnj[lane < G.nwc ? lane : 0] * (lane < G.nwc ? 1.0 : 0.0);
+    double yr = 0, yi = 0;  // this thread's part of (D_c v_j) row a of aggregate b
+    if (w.act) coarse_row_part(G, w, vj, yr, yi);
+    ys[0][w.g][w.r] = yr;
+    ys[1][w.g][w.r] = yi;
+    for (int q = lane + 64; q < G.nwc; q += 64) nj += pnj[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
+    __syncthreads();
+    const double sj = nj > 0 ? 1.0 / sqrt(nj) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        G.sc[(int64_t)rhs * (MG_IMAX + 1) + j] = sj;
+        const double h = sqrt(nj > 0 ? nj : 0.0);
+        if (j == 0) {
+            G.beta[rhs] = h;
+        } else {  // h_{j,j-1}
+            double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)(j - 1) * (MG_IMAX + 1);
+            Hc[2 * j] = h;
+            Hc[2 * j + 1] = 0.0;
+        }
+    }
+    coarse_row_total(ys, w.r, yr, yi);
+    yr *= sj;
+    yi *= sj;
+    if (w.act) {
+        const float2 wf = make_float2((float)yr, (float)yi);
+        if (w.g == 0) wout[w.b * K + w.a] = wf;
+        yr = wf.x;  // the dot products see the stored vector
+        yi = wf.y;
+    } else {
+        yr = yi = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = w.g + MG_AGRP * u;
+        double pr = (double)v[u].x * yr + (double)v[u].y * yi;
+        double pi = (double)v[u].x * yi - (double)v[u].y * yr;
+#pragma unroll
+        for (int off = MG_ALANES / 2; off > 0; off >>= 1) {  // the 32 rows of this group
+            pr += __shfl_xor(pr, off, 64);
+            pi += __shfl_xor(pi, off, 64);
+        }
+        if (w.r == 0 && i <= j) {
+            double *pd = pd_of(G, rhs, 0) + blockIdx.x;
+            pd[(int64_t)(2 * i) * G.pstride] = pr;
+            pd[(int64_t)(2 * i + 1) * G.pstride] = pi;
+        }
+    }
+}
+
+// Arnoldi step j, a correction pass: w -= sum_i h_i s_i v_i with h_i = s_i t_i and t the
+// totals of the partials of pass `src` (0: the operator kernel's <v_i, w>, 1: a second
+// pass's); then either the partials of <v_i, w> for a further pass (norm = 0) or of
+// |w|^2 (norm = 1). Workgroup 0 sets (src 0) or adds (src 1) h into column j of the
+// Hessenberg matrix.
+__global__ __launch_bounds__(MG_GWG) void mg_cgs_kernel(MgGmres G, int j, int src, int norm) {
+    __shared__ double h[2 * MG_IMAX];
+    __shared__ double lds[(MG_GWG / 64) * 2 * MG_IMAX];
+    const int rhs = G.active[blockIdx.y];
+    const int K = G.K, tc = MG_GWG / K > 0 ? MG_GWG / K : 1;
+    const int bl = threadIdx.x / K, a = threadIdx.x - bl * K;
+    const int64_t b = (int64_t)blockIdx.x * tc + bl;
+    const bool act = bl < tc && b < G.Nd;
+    const float2 *vb = G.basis + (int64_t)rhs * G.bstride;
+    float2 *w = const_cast<float2 *>(vb) + (int64_t)(j + 1) * G.vstride;
+    // this thread's rows of w and of the basis, loaded before the partial sums
+    // (unconditional loads with clamped indices: for i > j or a missing row they read a
+    // stored row that enters with a zero coefficient or is not kept)
+    const int64_t row = act ? b * K + a : 0;
+    const float2 w0 = w[row];
+    float2 vi[MG_IMAX];
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) vi[i] = vb[(int64_t)(i <= j ? i : j) * G.vstride + row];
+    // s_i in lane i of every wave (s_0 .. s_j are written; lanes past j read s_j)
+    const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
+    const int lane = threadIdx.x & 63;
+    const double s_lane = sc[lane <= j ? lane : j];
+    load_totals<MG_GWG / 64>(pd_of(G, rhs, src), G.pstride, src == 0 ? G.nwa : G.nwc, 2 * (j + 1), h);
+    if (blockIdx.x == 0 && (int)threadIdx.x < 2 * (j + 1)) {
+        double *Hc = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2 + 2 * (int64_t)j * (MG_IMAX + 1);
+        Hc[threadIdx.x] = (src == 0 ? 0.0 : Hc[threadIdx.x]) + h[threadIdx.x] * __shfl(s_lane, threadIdx.x >> 1, 64);
+    }
+    double yr = w0.x, yi = w0.y;
+#pragma unroll
+    for (int i = 0; i < MG_IMAX; ++i) {  // the terms i > j are zeros
+        const double si = __shfl(s_lane, i, 64);
+        const double cr = i <= j ? h[2 * i] * si * si : 0.0, ci = i <= j ? h[2 * i + 1] * si * si : 0.0;
+        yr -= cr * vi[i].x - ci * vi[i].y;
+        yi -= cr * vi[i].y + ci * vi[i].x;
+    }
+    if (act) w[b * K + a] = make_float2((float)yr, (float)yi);
+    yr = act ? (double)(float)yr : 0.0;
+    yi = act ? (double)(float)yi : 0.0;
+    if (!norm) {
+        double acc[2 * MG_IMAX];
+#pragma unroll
+        for (int i = 0; i < MG_IMAX; ++i) {
+            acc[2 * i] = acc[2 * i + 1] = 0.0;
+            if (i <= j && act) {
+                acc[2 * i] = (double)vi[i].x * yr + (double)vi[i].y * yi;
+                acc[2 * i + 1] = (double)vi[i].x * yi - (double)vi[i].y * yr;
+            }
+        }
+        wg_sum_store<2 * MG_IMAX>(acc, lds, 2 * (j + 1), pd_of(G, rhs, 1) + blockIdx.x, G.pstride);
+    } else {
+        double n[1] = {yr * yr + yi * yi};
+        wg_sum_store<1>(n, lds, 1, pn_of(G, rhs, j + 1) + blockIdx.x, 1);
+    }
+}
 
 // Arnoldi step j of a cycle in one launch (classical Gram-Schmidt, one pass). The basis
 // holds v_i (unnormalised, q_i = s_i v_i with s_i = 1 / |v_i|); u_j = D_c v_{j-1} is kept
@@ -759,7 +940,7 @@ __global__ __launch_bounds__(MG_AWG) __attribute__((amdgpu_waves_per_eu(1, 2))) 
 __global__ __launch_bounds__(64) void mg_cfinal_kernel(MgGmres G, int k) {
     const int rhs = G.active[blockIdx.x];
     const int lane = threadIdx.x;
-    const double nk = wave_sum_parts(pn_of(G, rhs, k), G.nwa);
+    const double nk = wave_sum_parts(pn_of(G, rhs, k), G.fused ? G.nwa : G.nwc);
     const double *Hm = G.H + (int64_t)rhs * (MG_IMAX + 1) * MG_IMAX * 2;
     const double *sc = G.sc + (int64_t)rhs * (MG_IMAX + 1);
     double hr[MG_IMAX + 1], hi[MG_IMAX + 1];  // column `lane` of Hbar, rows 0..MG_IMAX
@@ -911,12 +1092,20 @@ static void launch_arnoldi(bool tail, int j, dim3 ga, hipStream_t st, const MgGm
 hipError_t launch_mg_coarse_gmres(const MgGmres &G, int nact, int k, int cycles, hipStream_t st) {
     if (nact <= 0) return hipSuccess;
     if (k < 1 || k > MG_IMAX || cycles < 1 || G.K < 2 || G.K > 2 * MG_NVEC_MAX) return hipErrorInvalidValue;
-    const dim3 ga((unsigned)G.nwa, (unsigned)nact);
+    const dim3 ga((unsigned)G.nwa, (unsigned)nact), gc((unsigned)G.nwc, (unsigned)nact);
     const int64_t n = G.Nd * G.K;
     const dim3 ge((unsigned)((n + 255) / 256), (unsigned)nact);
     for (int cyc = 0; cyc < cycles; ++cyc) {
         hipLaunchKernelGGL(mg_cres_kernel, ga, dim3(MG_AWG), 0, st, G, (int)(cyc == 0));
-        for (int j = 0; j <= k; ++j) launch_arnoldi(j == k, j, ga, st, G);
+        if (G.fused) {  // one launch per step
+            for (int j = 0; j <= k; ++j) launch_arnoldi(j == k, j, ga, st, G);
+        } else {  // two launches per step
+            hipLaunchKernelGGL(mg_cinit_kernel, gc, dim3(MG_GWG), 0, st, G);
+            for (int j = 0; j < k; ++j) {
+                hipLaunchKernelGGL(mg_capply_kernel, ga, dim3(MG_AWG), 0, st, G, j);
+                hipLaunchKernelGGL(mg_cgs_kernel, gc, dim3(MG_GWG), 0, st, G, j, 0, 1);
+            }
+        }
         hipLaunchKernelGGL(mg_cfinal_kernel, dim3((unsigned)nact), dim3(64), 0, st, G, k);
         hipLaunchKernelGGL(mg_caccum_kernel, ge, dim3(256), 0, st, G, k, (int)(cyc == 0));
     }

@@ -55,7 +55,7 @@ class Params(C.Structure):
 
 class MgParams(C.Structure):
     _fields_ = [("nvec", C.c_int), ("setup_iters", C.c_int), ("coarse_iters", C.c_int),
-                ("coarse_cycles", C.c_int)]
+                ("coarse_cycles", C.c_int), ("coarse_form", C.c_int)]
 
 
 class KernelProfile(C.Structure):
@@ -433,16 +433,17 @@ class Batch:
 class Multigrid:
     """Two-level multigrid preconditioner with SAP as smoother (sapdd_mg_*), for one field
     and kappa. vecs: the nvec test vectors (canonical spinors [nvec,t,z,y,x,4,3]);
-    smoother keywords (nmr, ncy, prec) as Field.params."""
+    coarse_form: 0 = two launches per coarse Arnoldi step (batches), 1 = one (a single
+    system); smoother keywords (nmr, ncy, prec) as Field.params."""
 
     def __init__(self, field: "Field", kappa: float, vecs, setup_iters=0, coarse_iters=16, coarse_cycles=1,
-                 **smoother):
+                 coarse_form=0, **smoother):
         self.field, self.ctx, self.kappa = field, field.ctx, float(kappa)
         self.nvec = int(vecs.shape[0])
         self.K = 2 * self.nvec
         self.grid = tuple(field.dims[mu] // field.block[mu] for mu in range(4))  # x, y, z, t
         prm = field.params(**smoother)
-        mp = MgParams(self.nvec, int(setup_iters), int(coarse_iters), int(coarse_cycles))
+        mp = MgParams(self.nvec, int(setup_iters), int(coarse_iters), int(coarse_cycles), int(coarse_form))
         pv, dev = _ptr(vecs)
         h = C.c_void_p()
         self.ctx._check(self.ctx.lib.sapdd_mg_setup(self.ctx.h, field.h, self.kappa, C.byref(prm), C.byref(mp), pv,

@@ -95,7 +95,7 @@ def small(ctx):
     u, t, f, vecs = _setup(ctx, dims, block, kappa=kappa, seed=43)
     mg = Multigrid(f, kappa, vecs, setup_iters=2, coarse_iters=8, nmr=4, ncy=2, prec="f64")
     tl = omg.TwoLevel(u, t, kappa, block, list(vecs), ncy=2, nmr=4, setup_iters=2, coarse_iters=8)
-    yield dict(dims=dims, block=block, kappa=kappa, u=u, t=t, f=f, mg=mg, tl=tl)
+    yield dict(dims=dims, block=block, kappa=kappa, u=u, t=t, f=f, mg=mg, tl=tl, vecs=vecs)
     mg.close()
     f.free()
 
@@ -117,6 +117,29 @@ def test_coarse_gmres_matches_oracle(small):
     for i in range(2):
         ref = omg.gmres_fixed(tl.coarse_apply, rhs[i], 8)
         assert np.linalg.norm(got[i] - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_coarse_gmres_20_steps_matches_oracle(small, form):
+    """GMRES(20) on the coarse system in both forms of the Arnoldi step; in the one-launch
+    form the steps run with every bound on the basis vectors a step loads (8, 16, 24),
+    and the cycle's tail in the last."""
+    from paper_1502_04025_amd import Multigrid
+    print(f"mg coarse GMRES(20), form {form}", flush=True)
+    mg = Multigrid(small["f"], small["kappa"], small["vecs"], setup_iters=2, coarse_iters=20, nmr=4, ncy=2,
+                   prec="f64", coarse_form=form)
+    try:
+        rng = np.random.default_rng(5)
+        shape = (2, 2, 2, 2, 8)
+        rhs = np.stack([rng.standard_normal(shape) + 1j * rng.standard_normal(shape) for _ in range(2)])
+        got = mg.coarse_solve(rhs)
+        for i in range(2):
+            ref = omg.gmres_fixed(small["tl"].coarse_apply, rhs[i], 20)
+            err = np.linalg.norm(got[i] - ref) / np.linalg.norm(ref)
+            print(f"  rhs {i}: rel err {err:.2e}", flush=True)
+            assert err <= 1e-4
+    finally:
+        mg.close()
 
 
 def test_restarted_coarse_solve_and_application_match_oracle(small):
@@ -167,13 +190,16 @@ def test_solve_matches_oracle_iterations(small):
     assert info["converged"] and abs(info["iters"] - st["iters"]) <= 1
 
 
-def test_batch_results_do_not_depend_on_the_batch(small):
+@pytest.mark.parametrize("form", [0, 1])
+def test_batch_results_do_not_depend_on_the_batch(small, form):
     """Two right-hand sides solved together give the same bits as each alone, with the
-    FP32 smoother and graphs."""
-    print("mg batch independence", flush=True)
-    from paper_1502_04025_amd import Batch
+    FP32 smoother and graphs, in both forms of the coarse Arnoldi step."""
+    print(f"mg batch independence, form {form}", flush=True)
+    from paper_1502_04025_amd import Batch, Multigrid
     b = synthetic.gaussian_source(small["dims"], 2, 59)
-    f, mg = small["f"], small["mg"]
+    f = small["f"]
+    mg = small["mg"] if form == 0 else Multigrid(f, small["kappa"], small["vecs"], setup_iters=2, coarse_iters=8,
+                                                 nmr=4, ncy=2, prec="f64", coarse_form=1)
     alone = []
     for i in range(2):
         res = mg.solve(b[i:i + 1], nmr=4, ncy=2, restart=8, tol=1e-10, prec="f32")
@@ -189,6 +215,8 @@ def test_batch_results_do_not_depend_on_the_batch(small):
         assert st["converged"]
         np.testing.assert_array_equal(x, alone[i])
     batch.close()
+    if form == 1:
+        mg.close()
 
 
 def test_graph_replays_equal_direct_launches(small):
