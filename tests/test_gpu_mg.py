@@ -245,6 +245,9 @@ def test_errors_are_reported(small):
     assert e.value.code == EINVAL
     with pytest.raises(SapddError):
         Multigrid(f, 0.128, vecs[:2], coarse_iters=25)
+    with pytest.raises(SapddError) as e:
+        Multigrid(f, 0.128, vecs[:2], coarse_form=2)  # no such form
+    assert e.value.code == EINVAL
     batch = Batch(f, 1, nmr=2, ncy=1, restart=4)
     batch.set_mg(small["mg"])
     with pytest.raises(SapddError) as e:
